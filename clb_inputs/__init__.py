@@ -1,0 +1,59 @@
+"""Seeded synthetic inputs and workload shapes for the CLB tests and benchmark.
+
+Holds no arithmetic of the method itself: only array shapes, parameter sets
+(the paper's values and the benchmark workloads) and seeded random numbers.
+Both the HIP path and the CPU reference receive their inputs from here.
+"""
+import numpy as np
+
+# Parameter values fixed in Section 3 of the paper (Liu & He, arXiv:1603.01955).
+PAPER_A = 2.0
+PAPER_B2 = 0.55
+PAPER_S3 = 1.1
+PAPER_S8 = 1.2
+
+
+def uniform_populations(nx, ny, seed, lo=0.05, hi=0.15):
+    """Random positive populations, shape (9, ny, nx), uniform in [lo, hi).
+
+    Far from equilibrium on purpose: every moment of the collision is excited.
+    """
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(9, ny, nx))
+
+
+def sample_nodes(nx, ny, count, seed):
+    """Distinct node coordinates (ys, xs): all four corners, the wall rows,
+    the first and last columns, plus uniform random interior picks."""
+    rng = np.random.default_rng(seed)
+    fixed = [(0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1),
+             (0, nx // 2), (ny - 1, nx // 2), (ny // 2, 0), (ny // 2, nx - 1)]
+    ys = rng.integers(0, ny, size=count)
+    xs = rng.integers(0, nx, size=count)
+    pts = sorted(set(fixed) | set(zip(ys.tolist(), xs.tolist())))
+    return (np.array([p[0] for p in pts], dtype=np.int64),
+            np.array([p[1] for p in pts], dtype=np.int64))
+
+
+def kn_sweep_channels(count=64, seed=7, heights=(16, 24, 32, 48, 64, 96, 128),
+                      kn_lo=0.01, kn_hi=10.0):
+    """Batched Kn-sweep workload: ``count`` periodic channels with Kn
+    log-spaced over [kn_lo, kn_hi] and heights drawn from ``heights``."""
+    rng = np.random.default_rng(seed)
+    ny = rng.choice(np.array(heights), size=count)
+    kn = kn_lo * (kn_hi / kn_lo) ** (np.arange(count) / max(count - 1, 1))
+    return [int(v) for v in ny], [float(v) for v in kn]
+
+
+# Workloads (sizes follow the paper's two test problems, Section 3).
+WORKLOADS = {
+    # Force-driven periodic channel, small: steady state after 20,000 steps.
+    "channel_4x32": dict(nx=4, ny=32, xbc="periodic", kn=0.1, gx=1e-6, steps=20000),
+    # Long pressure-driven channel, L/H = 100.
+    "long_4000x40": dict(nx=4000, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0, steps=200000),
+    # Large periodic channel used for throughput.
+    "periodic_32768x2048": dict(nx=32768, ny=2048, xbc="periodic", kn=1.0, gx=1e-7,
+                                init="perturbed", init_amp=1e-4, seed=12345),
+    # Long channel for the adjoint calibration, L/H = 100.
+    "long_2000x20": dict(nx=2000, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, steps=2000),
+}

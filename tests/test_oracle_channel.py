@@ -1,0 +1,136 @@
+"""Pins of the CPU reference against closed-form steady channel flows and the
+numbers printed in Section 3.1 of Liu & He (arXiv:1603.01955)."""
+import os
+from math import pi, sqrt
+
+import numpy as np
+import pytest
+
+from oracle import analytic as A
+from oracle import clb_ref as C
+from oracle import rng
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _paper_values():
+    out = {}
+    with open(os.path.join(GOLDEN, "paper_values.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                k, v = line.split()
+                out[k] = float(v)
+    return out
+
+
+def _steady(prm, max_steps=60000, check=500, tol=1e-13):
+    P = C.init_uniform(prm)
+    prev = None
+    for n in range(0, max_steps, check):
+        P = C.run(P, prm, check)
+        su = C.column_sums(P, prm)[1].mean()
+        if prev is not None and abs(su - prev) <= tol * abs(su):
+            return P, n + check
+        prev = su
+    return P, max_steps
+
+
+def test_splitmix64_published_outputs():
+    """SplitMix64 seeded with 0: first three outputs of the public reference code."""
+    keys = np.array([0, int(rng.GAMMA), (2 * int(rng.GAMMA)) % 2 ** 64], dtype=np.uint64)
+    got = [int(v) for v in rng.splitmix64_first(keys)]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_section3_parameters():
+    pv = _paper_values()
+    # sigma = 1: B1 = 1 - 0.1817 = 0.8183, sigma_v = 1.
+    assert abs(C.slip_A1(1.0) - (1 - pv["slip_B1_coeff"])) < 1e-15
+    # Fig. 1 Knudsen numbers Kn = 2k/sqrt(pi) quoted in the text.
+    assert round(2 * pv["fig1_k_min"] / sqrt(pi), 4) == pv["fig1_kn_first"]
+    assert round(2 * pv["fig1_k_max"] / sqrt(pi), 4) == pv["fig1_kn_last"]
+
+
+@pytest.fixture(scope="module")
+def channel_4x32():
+    """Force-driven periodic channel 4 x 32, Kn = 0.1, g = 1e-6, 20,000 steps."""
+    prm = C.Params(nx=4, ny=32, kn=0.1, gx=1e-6)
+    return prm, C.run(C.init_uniform(prm), prm, 20000)
+
+
+def test_discrete_closed_form_channel(channel_4x32):
+    """P11: the steady x-uniform solution of the scheme is the discrete
+    slip-parabola u = U_s + G y (H - y); nonlinear terms are O(u^2) ~ 1e-8."""
+    prm, P = channel_4x32
+    _, r = C.resolved(prm)
+    _, ux, uy = C.moments(P, prm)
+    Us, G, rows, su = A.discrete_channel(32, 0.1, 2.0, 0.55, r, 1e-6)
+    for x in range(4):
+        assert np.max(np.abs(ux[:, x] - rows) / np.array(rows)) <= 1e-6
+    assert abs(ux[:, 0].sum() / su - 1) <= 1e-6
+    assert np.max(np.abs(uy)) <= 1e-14
+    # flow rate of Section 3.1
+    assert abs(C.flow_rate_Q(P, prm) / A.discrete_Q(32, 0.1, 2.0, 0.55, r) - 1) <= 1e-6
+
+
+def test_excess_over_continuum_second_order_slip(channel_4x32):
+    """P12: with the printed Eq. (21) the scheme's flow exceeds the continuum
+    second-order slip profile (Eq. 19) by 3g/(16 tt) + (pi/4) B2 tt g per row."""
+    prm, P = channel_4x32
+    A1, _ = C.resolved(prm)
+    _, ux, _ = C.moments(P, prm)
+    cont = A.continuum_sum_u(32, 0.1, 2.0, A1, 0.55, 1e-6)
+    tt = C.tau_tilde(0.1, 32, 2.0)
+    excess = 32 * (3e-6 / (16 * tt) + pi / 4 * 0.55 * tt * 1e-6)
+    assert abs(ux[:, 0].sum() - cont - excess) <= 1e-6 * cont
+    assert 0.0160 < ux[:, 0].sum() / cont - 1 < 0.0165
+
+
+def test_denominator_24_matches_continuum_slip():
+    """P12: with 24 in place of 16 in Eq. (21) the scheme reproduces the
+    continuum second-order slip profile of Eq. (19)."""
+    prm = C.Params(nx=1, ny=16, kn=0.1, gx=1e-6, tq_den=24.0)
+    P, _ = _steady(prm)
+    A1, _ = C.resolved(prm)
+    _, ux, _ = C.moments(P, prm)
+    cont = A.continuum_sum_u(16, 0.1, 2.0, A1, 0.55, 1e-6)
+    assert abs(ux[:, 0].sum() / cont - 1) <= 1e-6
+
+
+def test_no_slip_magic_combination():
+    """P13: r = 1 with (tau_s - 1/2)(tau_q - 1/2) = 1/8 (B2 = 0, denominator
+    24) gives the exact no-slip Poiseuille parabola."""
+    prm = C.Params(nx=1, ny=16, kn=0.1, gx=1e-6, r=1.0, A2=0.0, tq_den=24.0)
+    P, _ = _steady(prm)
+    _, ux, _ = C.moments(P, prm)
+    tt = C.tau_tilde(0.1, 16, 2.0)
+    y = np.arange(16) + 0.5
+    ref = 1.5e-6 / tt * y * (16 - y)
+    assert np.max(np.abs(ux[:, 0] - ref)) <= 1e-6 * ref.max()
+
+
+@pytest.mark.parametrize("kn", [0.3, 0.87, 3.0])
+def test_flow_rate_matches_discrete_closed_form(kn):
+    """P14: converged Q of the reference equals the discrete closed form."""
+    prm = C.Params(nx=1, ny=16, kn=kn, gx=1e-6)
+    P, _ = _steady(prm)
+    _, r = C.resolved(prm)
+    assert abs(C.flow_rate_Q(P, prm) / A.discrete_Q(16, kn, 2.0, 0.55, r) - 1) <= 1e-6
+
+
+def test_knudsen_minimum_location():
+    """P14: the scheme's flow rate has its minimum at Kn* = 1/(sqrt(18 B2) - a)
+    = 0.872, which is the paper's 'Kn ~ 0.9' (Abstract, Section 3.1); the
+    continuum law (2 B2) would put it at 1.76."""
+    pv = _paper_values()
+    kstar = A.knudsen_minimum(pv["rarefaction_factor_a"], pv["slip_B2"])
+    assert abs(kstar - 0.8723) < 1e-3
+    assert round(kstar, 1) == pv["knudsen_minimum_clb"]
+    r = C.bounce_fraction(C.slip_A1(1.0))
+    grid = np.exp(np.linspace(np.log(0.1), np.log(10.0), 2001))
+    for N in (16, 32, 64, 128):
+        q = [A.discrete_Q(N, k, 2.0, 0.55, r) for k in grid]
+        assert 0.85 < grid[int(np.argmin(q))] < 0.90
+    big = [A.large_N_Q(k, 2.0, C.slip_A1(1.0), 0.55) for k in grid]
+    assert abs(grid[int(np.argmin(big))] - kstar) < 5e-3

@@ -1,0 +1,134 @@
+"""Pins of the CPU reference's streaming and boundaries (Eqs. 5 and 20,
+Sections 3.1-3.2 of Liu & He, arXiv:1603.01955)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from clb_inputs import uniform_populations
+from oracle import clb_ref as C
+from oracle import exact as X
+from oracle import lattice as L
+
+
+def _jx(f):
+    return np.tensordot(L.EX.astype(float), f, (0, 0))
+
+
+@pytest.mark.parametrize("shift", [1, 0])
+@pytest.mark.parametrize("shape", [(7, 5), (1, 3), (4, 1), (1, 1)])
+def test_stream_conserves_mass(shift, shape):
+    """P8: streaming with CBBSR walls (weights r, 1-r sum to one) and
+    periodic x moves mass without creating or losing any."""
+    nx, ny = shape
+    P = uniform_populations(nx, ny, 21)
+    prm = C.Params(nx=nx, ny=ny, cbbsr_shift=shift, r=0.37)
+    pre = C.stream_bc(P, prm)
+    assert abs(pre.sum() - P.sum()) <= 1e-14 * P.sum()
+
+
+@pytest.mark.parametrize("shift", [1, 0])
+def test_gather_nodes_matches_stream(shift):
+    P = uniform_populations(6, 5, 22)
+    prm = C.Params(nx=6, ny=5, cbbsr_shift=shift, r=0.41)
+    pre = C.stream_bc(P, prm)
+    ys, xs = np.meshgrid(np.arange(5), np.arange(6), indexing="ij")
+    got = C.gather_nodes(P, prm, ys.ravel(), xs.ravel())
+    assert np.array_equal(got, pre.reshape(9, -1))
+
+
+def test_specular_walls_conserve_x_momentum():
+    """P9: with r = 0 the walls reflect specularly, so they exert no shear:
+    the total x-momentum grows by exactly g * total mass per step."""
+    prm = C.Params(nx=5, ny=6, r=0.0, gx=1e-3, kn=0.3)
+    P = uniform_populations(5, 6, 23)
+    for _ in range(4):
+        pre = C.stream_bc(P, prm)
+        assert abs(_jx(pre).sum() - _jx(P).sum()) <= 1e-14
+        Pn = C.step(P, prm)
+        assert abs(_jx(Pn).sum() - _jx(P).sum() - prm.gx * P.sum()) <= 1e-14
+        P = Pn
+
+
+def test_bounce_back_reverses_wall_momentum():
+    """P9: with r = 1 the wall returns every outgoing particle reversed, so the
+    wall rows gain no net tangential momentum from streaming across the wall."""
+    prm = C.Params(nx=4, ny=3, r=1.0)
+    P = uniform_populations(4, 3, 24)
+    pre = C.stream_bc(P, prm)
+    # bottom row: what arrives in 2, 5, 6 is what left in 4, 7, 8 at the same node
+    np.testing.assert_array_equal(pre[[2, 5, 6], 0], P[[4, 7, 8], 0])
+    np.testing.assert_array_equal(pre[[4, 7, 8], 2], P[[2, 5, 6], 2])
+
+
+def test_x_translation_invariance():
+    prm = C.Params(nx=7, ny=4, gx=1e-3, kn=0.5)
+    P = uniform_populations(7, 4, 25)
+    a = np.roll(C.run(P, prm, 3), 2, axis=2)
+    b = C.run(np.roll(P, 2, axis=2), prm, 3)
+    assert np.max(np.abs(a - b)) <= 1e-15
+
+
+def test_mirror_symmetry():
+    """P10: for a y-mirror-symmetric start (2<->4, 5<->8, 6<->7, y -> ny-1-y)
+    and a force along x, the state stays mirror-symmetric."""
+    prm = C.Params(nx=3, ny=6, gx=1e-4, kn=0.2)
+    P = uniform_populations(3, 6, 26)
+    mirror = [0, 1, 4, 3, 2, 8, 7, 6, 5]
+    P = 0.5 * (P + P[mirror][:, ::-1, :])
+    for _ in range(5):
+        P = C.step(P, prm)
+        assert np.max(np.abs(P - P[mirror][:, ::-1, :])) <= 1e-15
+    rho, ux, uy = C.moments(P, prm)
+    assert np.max(np.abs(ux - ux[::-1])) <= 1e-15
+    assert np.max(np.abs(uy + uy[::-1])) <= 1e-15
+
+
+@pytest.mark.parametrize("shift", [True, False])
+def test_brute_force_exact_tiny_grid(shift):
+    """P17: two steps on a 4x3 channel: FP64 reference vs node-by-node exact
+    rational evaluation of Eqs. (5), (6)-(9) and (20)."""
+    nx, ny = 4, 3
+    P0 = uniform_populations(nx, ny, 27)
+    r = Fraction(5, 8)
+    Fx, Fy = Fraction(1, 1000), Fraction(-1, 4000)
+    s3, snu, sq, s8 = Fraction(11, 10), Fraction(2, 5), Fraction(3, 4), Fraction(6, 5)
+    # The FP64 reference with the same (rational, exactly representable) rates.
+    prm = C.Params(nx=nx, ny=ny, r=float(r), gx=float(Fx), gy=float(Fy), cbbsr_shift=int(shift))
+    P = P0.copy()
+    Pe = [[[Fraction(v) for v in row] for row in plane] for plane in P0]
+    for _ in range(2):
+        pre = C.stream_bc(P, prm)
+        P = C.collide(pre, prm.gx, prm.gy, float(s3), float(snu), float(sq), float(s8))
+        Pe = X.step_grid(Pe, nx, ny, r, Fx, Fy, s3, snu, sq, s8, shift)
+    ref = np.array([[[float(v) for v in row] for row in plane] for plane in Pe])
+    assert np.max(np.abs(P - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_pressure_rest_state_is_steady():
+    """Equal inlet and outlet pressure: the uniform rest state is a fixed
+    point of the whole step including the ghost columns."""
+    prm = C.Params(nx=6, ny=4, xbc="pressure", kn=0.2, p_ratio=1.0, rho_out=1.0)
+    P = C.init_linear_rho(prm)
+    Pn = C.run(P, prm, 3)
+    assert np.max(np.abs(Pn - P)) <= 1e-15
+
+
+def test_pressure_ghost_density_is_linear():
+    """Ghost columns place the prescribed density on the inlet/outlet planes:
+    (rho_ghost + rho_adjacent)/2 = rho_boundary."""
+    prm = C.Params(nx=5, ny=3, xbc="pressure", kn=0.2, p_ratio=1.7, rho_out=1.0)
+    P = uniform_populations(5, 3, 28)
+    g_in, g_out = C.ghost_columns(P, prm)
+    assert np.allclose(0.5 * (g_in.sum(0) + P[:, :, 0].sum(0)), 1.7, rtol=0, atol=1e-15)
+    assert np.allclose(0.5 * (g_out.sum(0) + P[:, :, -1].sum(0)), 1.0, rtol=0, atol=1e-15)
+
+
+def test_perturbed_start_counter_layout():
+    """The seeded start depends only on (seed, node, direction)."""
+    prm = C.Params(nx=5, ny=3)
+    a = C.init_perturbed(prm, 99, 1e-4)
+    big = C.init_perturbed(C.Params(nx=5, ny=6), 99, 1e-4)
+    assert np.array_equal(a, big[:, :3, :])
+    w = C.init_uniform(prm)
+    assert np.max(np.abs(a - w)) <= 1e-4 and np.max(np.abs(a - w)) > 5e-5
