@@ -1,0 +1,156 @@
+"""Benchmark of the fused D2Q9 cascaded LB step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: periodic force-driven channel, 32768 x 2048 nodes (H = 2048),
+Kn = 1, body acceleration 1e-7, seeded perturbed equilibrium start, FP64.
+A step is one full pass of the hot path over the grid: pull streaming with
+periodic x and CBBSR slip walls, cascaded collision with forcing.  Prints
+one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "D2Q9 CLB MLUPS & HBM GB/s; batched Kn-sweep vs loop; adjoint/forward time"
+WORKLOAD = dict(nx=32768, ny=2048, kn=1.0, gx=1e-7, init="perturbed", init_amp=1e-4, seed=12345)
+BYTES_PER_NODE = 144          # 9 FP64 loads + 9 FP64 stores per node update
+HBM_PEAK_GBS = 8000.0         # MI355X HBM3E, published
+CPU_SAMPLE_ROWS = 128
+CPU_SAMPLE_STEPS = 3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block-x", type=int, default=256)
+    ap.add_argument("--xcd-remap", type=int, default=1)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="instead of the benchmark, run a plain device copy of this many GB "
+                         "(reference kernel for scaling hardware byte counters)")
+    return ap.parse_args()
+
+
+def copy_calibration(gb):
+    """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+    calibrate the counters read on the step kernel."""
+    import torch
+    n = int(gb * 1e9) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
+
+
+def traffic_from_profile():
+    """HBM bytes per step-kernel launch (FETCH_SIZE + WRITE_SIZE, each scaled by
+    the same counter on a plain copy of known size) from the committed counter
+    summary; None unless it was taken on the current kernel sources."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "step_periodic_32768x2048_traffic.txt")
+    rec = {}
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    rec[k.strip()] = v.strip()
+    except OSError:
+        return None
+    from paper_1603_01955_amd.build import source_hash
+    if rec.get("source_hash") != source_hash() or "bytes_per_launch" not in rec:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def cpu_baseline():
+    """The CPU reference, as it stands, on a bounded sample of the workload:
+    CPU_SAMPLE_STEPS steps of a 32768 x CPU_SAMPLE_ROWS slab of the same
+    channel (same Kn, force and seeded start), BLAS limited to one thread."""
+    import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_limits
+    from oracle import clb_ref as C
+    prm = C.Params(nx=WORKLOAD["nx"], ny=CPU_SAMPLE_ROWS, kn=WORKLOAD["kn"], gx=WORKLOAD["gx"])
+    with threadpool_limits(limits=1):
+        P = C.init_perturbed(prm, WORKLOAD["seed"], WORKLOAD["init_amp"])
+        P = C.step(P, prm)                      # warm-up
+        t0 = time.perf_counter()
+        P = C.run(P, prm, CPU_SAMPLE_STEPS)
+        dt = time.perf_counter() - t0
+    nodes = prm.nx * prm.ny
+    return {"value": nodes * CPU_SAMPLE_STEPS / dt / 1e6, "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d steps of a %dx%d slab of the same channel (Kn=1, g=1e-7, seeded start), "
+                      "NumPy FP64, one thread, %.1f s" % (CPU_SAMPLE_STEPS, prm.nx, prm.ny, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
+    import torch
+    from paper_1603_01955_amd import Solver
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = Solver(device=dev, **WORKLOAD)
+    s.set_launch(args.block_x, args.xcd_remap)
+    nodes = s.nx * s.ny
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = s.stream
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    s.step(args.steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    ok = s.check_finite()
+    mlups = nodes / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_NODE * nodes / (ms * 1e-3) / 1e9
+    traffic = traffic_from_profile()
+    rec = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "periodic_32768x2048", "nx": s.nx, "ny": s.ny, "kn": WORKLOAD["kn"],
+                   "g": WORKLOAD["gx"], "start": "seeded perturbed equilibrium, amp 1e-4, seed 12345",
+                   "buffers": "A-B", "block_x": args.block_x, "xcd_remap": args.xcd_remap},
+        "hbm_gbs": round(achieved, 1),
+        "finite": ok,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+    }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * clb.h -- C ABI of the MI355X (gfx950) cascaded lattice Boltzmann library.
+ *
+ * Method: Liu & He, "Numerical modelling of microchannel gas flows in the
+ * transition flow regime using the cascaded lattice Boltzmann method",
+ * arXiv:1603.01955.  D2Q9 cascaded collision with semi-implicit forcing
+ * (Section 2.1, Eqs. 1-14), Bosanquet-type effective viscosity setting the
+ * shear rate from Kn (Section 2.2, Eqs. 15-18), combined bounce-back /
+ * specular-reflection walls matched to a modified second-order slip law
+ * (Section 2.3, Eqs. 19-21), periodic or pressure inlet/outlet (Section 3).
+ *
+ * Conventions shared by every entry point
+ *  - Lattice units: dx = dt = c = 1, c_s^2 = 1/3, p = rho/3.
+ *  - Grid: nx x ny fluid nodes; row y sits at height y + 1/2 between walls
+ *    placed half a spacing below row 0 and above row ny-1, so the channel
+ *    height is H = ny (the N of Eq. 18).  Column x sits at x + 1/2; in
+ *    pressure mode the inlet plane is x = 0 and the outlet plane x = nx.
+ *  - Populations: FP64, structure of arrays, P[i][y][x] with x fastest,
+ *    direction i ordered as in Eq. (1): (0,0) (1,0) (0,1) (-1,0) (0,-1)
+ *    (1,1) (-1,1) (-1,-1) (1,-1).  The stored state is the post-collision
+ *    transformed population of Eq. (4); one step is streaming (Eq. 5) with
+ *    the boundaries, then the collision.
+ *  - Memory: the caller owns all device memory and the stream.  The library
+ *    allocates only a small host-side context and never calls hipMalloc.
+ *    "d_" pointers are device pointers, "h_" pointers host pointers.
+ *  - Asynchrony: every call enqueues work on the context's stream and
+ *    returns; only calls that write a host pointer synchronise that stream.
+ *  - Errors: every call returns a clb_status; CLB_OK is 0.  The message of
+ *    the last failure on the calling thread is returned by clb_last_error().
+ *    Invalid arguments are rejected before any device work is enqueued.
+ */
+#ifndef CLB_H
+#define CLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum clb_status {
+  CLB_OK = 0,
+  CLB_EINVAL = -1,     /* invalid argument; the message names the field      */
+  CLB_ENOMEM = -2,     /* caller's workspace smaller than required            */
+  CLB_EHIP = -3,       /* a HIP runtime call failed; message has its text     */
+  CLB_ESTATE = -4,     /* call not valid for this context (e.g. wrong mode)   */
+  CLB_EUNSTABLE = -5   /* non-finite populations detected                     */
+} clb_status;
+
+typedef enum clb_xbc {
+  CLB_X_PERIODIC = 0,  /* periodic inlet/outlet, body-force driven (Section 3.1) */
+  CLB_X_PRESSURE = 1   /* pressure inlet/outlet, local Kn(x) (Section 3.2)       */
+} clb_xbc;
+
+typedef enum clb_init_kind {
+  CLB_INIT_UNIFORM = 0,    /* f = f^eq(rho0, (ux0, uy0)) everywhere (Eq. 11)        */
+  CLB_INIT_LINEAR_RHO = 1, /* f = f^eq(rho(x), 0), rho linear from p_ratio*rho_out
+                              at x = 0 to rho_out at x = nx                        */
+  CLB_INIT_PERTURBED = 2   /* f_i = f_i^eq(rho0, u0) + init_amp * (2U - 1) with U the
+                              top 53 bits of SplitMix64 (Steele, Lea & Flood 2014)
+                              of key = seed XOR (9 * (y*nx + x) + i), times 2^-53   */
+} clb_init_kind;
+
+/* Problem statement.  clb_params_default() fills the values of Section 3:
+ * a = 2, sigma = 1, B2 = 0.55, s3 = 1.1, s8 = 1.2. */
+typedef struct clb_params {
+  int32_t nx, ny;        /* fluid nodes along / across the channel (>= 1; pressure: nx >= 2) */
+  int32_t xbc;           /* clb_xbc                                                        */
+  int32_t init;          /* clb_init_kind                                                  */
+  double kn;             /* Kn (periodic) or outlet Kn_out (pressure), > 0    Eqs. 18, Sec. 3.2 */
+  double a;              /* Bosanquet rarefaction factor, >= 0                Eq. 16          */
+  double sigma;          /* TMAC in (0, 2]; A1 = (1 - 0.1817 sigma)(2 - sigma)/sigma  Eq. 19, Sec. 3 */
+  double A1;             /* first-order slip coefficient B1*sigma_v; NaN -> from sigma         */
+  double A2;             /* second-order slip coefficient B2, >= 0            Eq. 19, 21      */
+  double r;              /* bounce-back fraction in [0, 1]; NaN -> Eq. 21 from A1              */
+  double s3, s8;         /* bulk and fourth-order relaxation rates in (0, 2)  Eq. 14, Sec. 3  */
+  double gx, gy;         /* body acceleration F (periodic mode only; 0 in pressure mode) Eq. 9 */
+  double p_ratio;        /* p_in / p_out (pressure mode), > 0                 Sec. 3.2        */
+  double rho_out;        /* outlet density (pressure mode), > 0                               */
+  double rho0, ux0, uy0; /* uniform start (CLB_INIT_UNIFORM / PERTURBED)                       */
+  double init_amp;       /* perturbation amplitude (CLB_INIT_PERTURBED), >= 0                  */
+  uint64_t seed;         /* perturbation seed                                                  */
+  double tq_den;         /* denominator of Eq. 21 (16 as printed; 24 = exact-slip variant)     */
+  int32_t cbbsr_shift;   /* Eq. 20 specular source: 1 = neighbour x-1 / x+1 (default),
+                            0 = the same node                                                   */
+  int32_t reserved;      /* must be 0                                                          */
+} clb_params;
+
+/* Derived constants (host-only).  In pressure mode s_nu, s_q and tau_tilde
+ * are the outlet values; inside the step they are evaluated per column. */
+typedef struct clb_derived {
+  double A1;             /* B1 * sigma_v actually used                       */
+  double r;              /* bounce-back fraction, Eq. 21                     */
+  double tau_tilde;      /* s_nu^-1 - 1/2 = sqrt(6/pi) N Kn / (1 + a Kn), Eq. 18 */
+  double s_nu;           /* shear rate s4 = s5, Eq. 18                       */
+  double s_q;            /* third-order rate s6 = s7, Eq. 21                 */
+} clb_derived;
+
+typedef struct clb_ctx clb_ctx;
+
+/* Fill *p with the Section 3 defaults and a 1 x 1 periodic grid. */
+void clb_params_default(clb_params* p);
+
+/* Validate *p and compute the derived constants (Eqs. 18, 21).  Host only,
+ * no device needed.  CLB_EINVAL if *p is out of range. */
+clb_status clb_derive(const clb_params* p, clb_derived* out);
+
+/* Device workspace in bytes needed by clb_init for *p: two population buffers
+ * of 72 * nx * ny bytes each plus a small diagnostics area. */
+clb_status clb_workspace_size(const clb_params* p, size_t* bytes);
+
+/* Create a context over the caller's workspace (device memory of at least
+ * clb_workspace_size bytes, 8-byte aligned, owned by the caller and kept alive
+ * until clb_destroy) and enqueue the initial state (init kind of *p) on
+ * hip_stream (a hipStream_t; NULL means the null stream).  The context keeps
+ * its own copy of *p. */
+clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes,
+                    void* hip_stream, clb_ctx** out);
+
+/* Advance nsteps >= 0 time steps (stream + boundaries + collision, Eqs. 4-5,
+ * 20).  Asynchronous. */
+clb_status clb_step(clb_ctx* c, int64_t nsteps);
+
+/* Number of steps taken since clb_init / the last clb_set_populations. */
+clb_status clb_steps_done(const clb_ctx* c, int64_t* h_steps);
+
+/* Macroscopic fields of the current pre-collision state (the populations
+ * after streaming and boundaries at the current time level), Eqs. 12-13:
+ * rho = sum f, rho u = sum e f + rho F/2.  Each output is a device array of
+ * ny * nx doubles, [y][x]; any of them may be NULL. */
+clb_status clb_moments(clb_ctx* c, double* d_rho, double* d_ux, double* d_uy);
+
+/* Per-column sums of the pre-collision state: d_m[x] = sum_y rho u_x (the
+ * mass flow m of Section 3.2), d_su[x] = sum_y u_x, d_rhoc[x] = centre-line
+ * density (middle row, or mean of the two middle rows for even ny).  Device
+ * arrays of nx doubles; any may be NULL.  Fixed summation order. */
+clb_status clb_column_sums(clb_ctx* c, double* d_m, double* d_su, double* d_rhoc);
+
+/* Mass flow (Section 3.2): optional per-column d_m_col[nx] (device) and the
+ * column mean written to *h_m_mean (host; synchronises the stream; may be NULL,
+ * then nothing is synchronised). */
+clb_status clb_massflow(clb_ctx* c, double* d_m_col, double* h_m_mean);
+
+/* Dimensionless flow rate of Section 3.1, Q = (int u_x dy)/(F_x H^2 sqrt(RT/2)/p)
+ * with F_x = rho0 gx, RT = 1/3, p = rho0/3, the integral a midpoint sum over
+ * rows, averaged over columns.  Periodic mode with gx != 0 only.  Synchronises. */
+clb_status clb_flow_rate(clb_ctx* c, double* h_Q);
+
+/* Pressure deviation along the centre line (Section 3.2):
+ * d_dp[x] = (p_c(x) - p_l(x)) / p_out with p_l falling linearly from p_in at
+ * x = 0 to p_out at x = nx; optional d_rho_c[x].  Pressure mode only. */
+clb_status clb_pressure_deviation(clb_ctx* c, double* d_dp, double* d_rho_c);
+
+/* Copy the current post-collision populations out / in, [9][ny][nx] doubles
+ * in device memory.  clb_set_populations resets the step counter. */
+clb_status clb_get_populations(clb_ctx* c, double* d_out);
+clb_status clb_set_populations(clb_ctx* c, const double* d_in);
+
+/* Failure detection: *h_ok = 1 if every population is finite, else 0 and the
+ * call returns CLB_EUNSTABLE.  Synchronises. */
+clb_status clb_check_finite(clb_ctx* c, int32_t* h_ok);
+
+/* Step-kernel launch shape (tuning; defaults are chosen by measurement):
+ * block_x threads per row segment (64, 128, 256, 512 or 1024) and
+ * xcd_remap = 1 to map consecutive row segments onto the same XCD. */
+clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap);
+
+/* Release the host context (not the caller's workspace or stream). */
+clb_status clb_destroy(clb_ctx* c);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* clb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLB_H */

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of ``libclb.so`` (the C ABI declared in include/clb.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch provides device memory (the workspace and output
+arrays) and the stream.  There is no CPU fallback: if the library is not
+built, loading it raises.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclb.so")
+
+CLB_OK, CLB_EINVAL, CLB_ENOMEM, CLB_EHIP, CLB_ESTATE, CLB_EUNSTABLE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "CLB_OK", -1: "CLB_EINVAL", -2: "CLB_ENOMEM", -3: "CLB_EHIP",
+                -4: "CLB_ESTATE", -5: "CLB_EUNSTABLE"}
+X_PERIODIC, X_PRESSURE = 0, 1
+INIT_UNIFORM, INIT_LINEAR_RHO, INIT_PERTURBED = 0, 1, 2
+
+
+class ClbError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class clb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("xbc", ctypes.c_int32), ("init", ctypes.c_int32),
+        ("kn", ctypes.c_double), ("a", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("A1", ctypes.c_double), ("A2", ctypes.c_double), ("r", ctypes.c_double),
+        ("s3", ctypes.c_double), ("s8", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("p_ratio", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("ux0", ctypes.c_double), ("uy0", ctypes.c_double),
+        ("init_amp", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("tq_den", ctypes.c_double),
+        ("cbbsr_shift", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class clb_derived(ctypes.Structure):
+    _fields_ = [("A1", ctypes.c_double), ("r", ctypes.c_double), ("tau_tilde", ctypes.c_double),
+                ("s_nu", ctypes.c_double), ("s_q", ctypes.c_double)]
+
+
+_lib = None
+
+_SIGNATURES = {
+    "clb_params_default": (None, [ctypes.POINTER(clb_params)]),
+    "clb_derive": (ctypes.c_int, [ctypes.POINTER(clb_params), ctypes.POINTER(clb_derived)]),
+    "clb_workspace_size": (ctypes.c_int, [ctypes.POINTER(clb_params), ctypes.POINTER(ctypes.c_size_t)]),
+    "clb_init": (ctypes.c_int, [ctypes.POINTER(clb_params), ctypes.c_void_p, ctypes.c_size_t,
+                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "clb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "clb_steps_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "clb_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_column_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_massflow": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "clb_flow_rate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "clb_pressure_deviation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "clb_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "clb_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "clb_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libclb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libclb.so not built: run `python -m paper_1603_01955_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(status):
+    if status != CLB_OK:
+        raise ClbError(status, lib().clb_last_error().decode())
+
+
+def make_params(nx, ny, xbc="periodic", kn=0.1, a=2.0, sigma=1.0, A1=None, A2=0.55, r=None,
+                s3=1.1, s8=1.2, gx=0.0, gy=0.0, p_ratio=2.0, rho_out=1.0, rho0=1.0, ux0=0.0,
+                uy0=0.0, init=None, init_amp=0.0, seed=0, tq_den=16.0, cbbsr_shift=1):
+    p = clb_params()
+    lib().clb_params_default(ctypes.byref(p))
+    p.nx, p.ny = int(nx), int(ny)
+    p.xbc = {"periodic": X_PERIODIC, "pressure": X_PRESSURE}[xbc] if isinstance(xbc, str) else int(xbc)
+    if init is None:
+        init = INIT_LINEAR_RHO if p.xbc == X_PRESSURE else INIT_UNIFORM
+    elif isinstance(init, str):
+        init = {"uniform": INIT_UNIFORM, "linear_rho": INIT_LINEAR_RHO, "perturbed": INIT_PERTURBED}[init]
+    p.init = int(init)
+    p.kn, p.a, p.sigma = float(kn), float(a), float(sigma)
+    p.A1 = math.nan if A1 is None else float(A1)
+    p.A2 = float(A2)
+    p.r = math.nan if r is None else float(r)
+    p.s3, p.s8 = float(s3), float(s8)
+    p.gx, p.gy = float(gx), float(gy)
+    p.p_ratio, p.rho_out = float(p_ratio), float(rho_out)
+    p.rho0, p.ux0, p.uy0 = float(rho0), float(ux0), float(uy0)
+    p.init_amp, p.seed = float(init_amp), int(seed)
+    p.tq_den = float(tq_den)
+    p.cbbsr_shift = int(cbbsr_shift)
+    return p
+
+
+def derive(params):
+    d = clb_derived()
+    check(lib().clb_derive(ctypes.byref(params), ctypes.byref(d)))
+    return {"A1": d.A1, "r": d.r, "tau_tilde": d.tau_tilde, "s_nu": d.s_nu, "s_q": d.s_q}
+
+
+def workspace_size(params):
+    n = ctypes.c_size_t()
+    check(lib().clb_workspace_size(ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One channel: populations live in a torch-allocated device workspace;
+    every call enqueues on the current torch stream of ``device``."""
+
+    def __init__(self, params=None, device="cuda", stream=None, **kw):
+        self.params = params if params is not None else make_params(**kw)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        self.device = torch.device(device)
+        self.derived = derive(self.params)
+        nbytes = workspace_size(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        check(lib().clb_init(ctypes.byref(self.params), _ptr(self.workspace), nbytes,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    # -- stepping ---------------------------------------------------------
+    def step(self, n=1):
+        check(lib().clb_step(self._ctx, int(n)))
+        return self
+
+    @property
+    def steps_done(self):
+        v = ctypes.c_int64()
+        check(lib().clb_steps_done(self._ctx, ctypes.byref(v)))
+        return v.value
+
+    def set_launch(self, block_x=256, xcd_remap=1):
+        check(lib().clb_set_launch(self._ctx, int(block_x), int(xcd_remap)))
+
+    # -- state ------------------------------------------------------------
+    def _empty(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def populations(self):
+        out = self._empty(9, self.ny, self.nx)
+        check(lib().clb_get_populations(self._ctx, _ptr(out)))
+        return out
+
+    def set_populations(self, P):
+        P = P.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(P.shape) != (9, self.ny, self.nx):
+            raise ValueError("populations must have shape (9, ny, nx)")
+        check(lib().clb_set_populations(self._ctx, _ptr(P)))
+        self._keep = P   # keep alive until the copy on the stream has run
+
+    # -- diagnostics ------------------------------------------------------
+    def moments(self):
+        rho, ux, uy = (self._empty(self.ny, self.nx) for _ in range(3))
+        check(lib().clb_moments(self._ctx, _ptr(rho), _ptr(ux), _ptr(uy)))
+        return rho, ux, uy
+
+    def column_sums(self):
+        m, su, rc = (self._empty(self.nx) for _ in range(3))
+        check(lib().clb_column_sums(self._ctx, _ptr(m), _ptr(su), _ptr(rc)))
+        return m, su, rc
+
+    def massflow(self):
+        m = self._empty(self.nx)
+        mean = ctypes.c_double()
+        check(lib().clb_massflow(self._ctx, _ptr(m), ctypes.byref(mean)))
+        return m, mean.value
+
+    def flow_rate(self):
+        q = ctypes.c_double()
+        check(lib().clb_flow_rate(self._ctx, ctypes.byref(q)))
+        return q.value
+
+    def pressure_deviation(self):
+        dp, rc = self._empty(self.nx), self._empty(self.nx)
+        check(lib().clb_pressure_deviation(self._ctx, _ptr(dp), _ptr(rc)))
+        return dp, rc
+
+    def check_finite(self):
+        ok = ctypes.c_int32()
+        st = lib().clb_check_finite(self._ctx, ctypes.byref(ok))
+        if st not in (CLB_OK, CLB_EUNSTABLE):
+            check(st)
+        return bool(ok.value)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            check(lib().clb_destroy(self._ctx))
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

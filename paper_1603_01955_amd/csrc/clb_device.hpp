@@ -1,0 +1,151 @@
+// Device-side building blocks of the D2Q9 cascaded LB step for gfx950.
+//
+// Method: Liu & He, arXiv:1603.01955, Section 2.  All arithmetic is FP64.
+// Populations are stored structure-of-arrays, P[i][y][x] with x fastest;
+// direction order as in Eq. (1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clb {
+
+// Relaxation rates used by one node (Eq. 14, Section 3): s3 (bulk),
+// s4 = s5 = s_nu (shear, Eq. 18), s6 = s7 = s_q (Eq. 21), s8.
+struct Rates {
+  double s3, snu, sq, s8;
+};
+
+// ---------------------------------------------------------------------------
+// Cascaded collision with semi-implicit forcing, in place on f[9]:
+//   raw moments of the pre-collision f-bar (Eq. 8), velocity from Eq. (13)
+//   (rho u = sum e f + rho F / 2, F = (gx, gy) the body acceleration),
+//   collision kernels g3..g8 in ascending order (Eq. 7, g0 = g1 = g2 = 0),
+//   forcing S = T^-1 S_hat (Eqs. 9, 10) with T^-1 in closed form, and the
+//   update f + K g + S written out per direction (Eqs. 4, 6).
+// ---------------------------------------------------------------------------
+template <bool FORCE>
+__device__ __forceinline__ void collide(double f[9], double gx, double gy, const Rates& s) {
+  const double f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4];
+  const double f5 = f[5], f6 = f[6], f7 = f[7], f8 = f[8];
+
+  // Eq. (8)
+  const double d57 = f5 + f7, d68 = f6 + f8;
+  const double diag = d57 + d68;                      // k'_xxyy
+  const double k_xx = f1 + f3 + diag;
+  const double k_yy = f2 + f4 + diag;
+  const double k_xy = d57 - d68;
+  const double k_xxy = (f5 + f6) - (f7 + f8);
+  const double k_xyy = (f5 + f8) - (f6 + f7);
+  const double rho = f0 + (f1 + f3) + (f2 + f4) + diag;
+  const double jx = (f1 - f3) + (f5 - f7) + (f8 - f6);
+  const double jy = (f2 - f4) + (f5 - f7) + (f6 - f8);
+
+  // Eq. (13)
+  const double inv_rho = 1.0 / rho;
+  double ux = jx * inv_rho, uy = jy * inv_rho;
+  if (FORCE) {
+    ux += 0.5 * gx;
+    uy += 0.5 * gy;
+  }
+  const double ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+
+  // Eq. (7): the force corrections are the "-1/2 rho (...)" terms.
+  double c3 = (2.0 / 3.0) * rho + rho * (ux2 + uy2) - (k_xx + k_yy);
+  double c4 = rho * (ux2 - uy2) - (k_xx - k_yy);
+  double c5 = rho * uxy - k_xy;
+  double c6 = 2.0 * rho * ux2 * uy + k_xxy - 2.0 * ux * k_xy - uy * k_xx;
+  double c7 = 2.0 * rho * ux * uy2 + k_xyy - 2.0 * uy * k_xy - ux * k_yy;
+  double c8 = rho * (1.0 / 9.0) + 3.0 * rho * ux2 * uy2 -
+              (diag - 2.0 * ux * k_xyy - 2.0 * uy * k_xxy + ux2 * k_yy + uy2 * k_xx + 4.0 * uxy * k_xy);
+  if (FORCE) {
+    c3 -= rho * (gx * ux + gy * uy);
+    c4 -= rho * (gx * ux - gy * uy);
+    c5 -= 0.5 * rho * (gx * uy + gy * ux);
+    c6 -= 0.5 * rho * (gy * ux2 + 2.0 * gx * uxy);
+    c7 -= 0.5 * rho * (gx * uy2 + 2.0 * gy * uxy);
+    c8 -= rho * (gx * ux * uy2 + gy * uy * ux2);
+  }
+  const double g3 = s.s3 * (1.0 / 12.0) * c3;
+  const double g4 = 0.25 * s.snu * c4;
+  const double g5 = 0.25 * s.snu * c5;
+  const double a34 = 3.0 * g3 + g4;   // appears in g6 and g8
+  const double b34 = 3.0 * g3 - g4;   // appears in g7 and g8
+  const double g6 = 0.25 * s.sq * c6 - 0.5 * uy * a34 - 2.0 * ux * g5;
+  const double g7 = 0.25 * s.sq * c7 - 0.5 * ux * b34 - 2.0 * uy * g5;
+  const double g8 = 0.25 * s.s8 * c8 - 2.0 * g3 - 0.5 * uy2 * a34 - 0.5 * ux2 * b34 -
+                    4.0 * uxy * g5 - 2.0 * uy * g6 - 2.0 * ux * g7;
+
+  // Eq. (6): f + K g (columns of K from Eq. 3).
+  double o0 = f0 - 4.0 * (g3 - g8);
+  double o1 = f1 - g3 + g4 + 2.0 * (g7 - g8);
+  double o2 = f2 - g3 - g4 + 2.0 * (g6 - g8);
+  double o3 = f3 - g3 + g4 - 2.0 * (g7 + g8);
+  double o4 = f4 - g3 - g4 - 2.0 * (g6 + g8);
+  const double t = 2.0 * g3 + g8;
+  double o5 = f5 + t + g5 - g6 - g7;
+  double o6 = f6 + t - g5 - g6 + g7;
+  double o7 = f7 + t + g5 + g6 + g7;
+  double o8 = f8 + t - g5 + g6 - g7;
+
+  if (FORCE) {
+    // Eq. (9) source moments in the basis of Eq. (10) ...
+    const double Sx = rho * gx, Sy = rho * gy;
+    const double Sxy = rho * (ux * gy + uy * gx);
+    const double Sxxy = rho * gy * ux2 + 2.0 * rho * gx * uxy;
+    const double Sxyy = rho * gx * uy2 + 2.0 * rho * gy * uxy;
+    const double Sxxyy = 2.0 * rho * gx * ux * uy2 + 2.0 * rho * gy * uy * ux2;
+    const double Sxx = 2.0 * rho * ux * gx;   // (S3 + S4)/2
+    const double Syy = 2.0 * rho * uy * gy;   // (S3 - S4)/2
+    // ... mapped back to populations by the inverse of T (closed form).
+    o0 += Sxxyy - Sxx - Syy;
+    o1 += 0.5 * (Sxx - Sxxyy + Sx - Sxyy);
+    o3 += 0.5 * (Sxx - Sxxyy - Sx + Sxyy);
+    o2 += 0.5 * (Syy - Sxxyy + Sy - Sxxy);
+    o4 += 0.5 * (Syy - Sxxyy - Sy + Sxxy);
+    o5 += 0.25 * (Sxxyy + Sxy + Sxxy + Sxyy);
+    o6 += 0.25 * (Sxxyy - Sxy + Sxxy - Sxyy);
+    o7 += 0.25 * (Sxxyy + Sxy - Sxxy - Sxyy);
+    o8 += 0.25 * (Sxxyy - Sxy - Sxxy + Sxyy);
+  }
+  f[0] = o0; f[1] = o1; f[2] = o2; f[3] = o3; f[4] = o4;
+  f[5] = o5; f[6] = o6; f[7] = o7; f[8] = o8;
+}
+
+// Equilibrium of Eq. (11).  Its T-moments factor per axis into the D1Q3
+// moments (1, u, 1/3 + u^2), so f_i^eq = rho * w(e_ix, ux) * w(e_iy, uy) with
+// w(0, u) = 2/3 - u^2 and w(+-1, u) = (1/3 + u^2 +- u) / 2.
+__device__ __forceinline__ void equilibrium(double rho, double ux, double uy, double e[9]) {
+  const double ax0 = 2.0 / 3.0 - ux * ux, axp = 0.5 * (1.0 / 3.0 + ux * ux + ux),
+               axm = 0.5 * (1.0 / 3.0 + ux * ux - ux);
+  const double ay0 = 2.0 / 3.0 - uy * uy, ayp = 0.5 * (1.0 / 3.0 + uy * uy + uy),
+               aym = 0.5 * (1.0 / 3.0 + uy * uy - uy);
+  e[0] = rho * ax0 * ay0;
+  e[1] = rho * axp * ay0;
+  e[2] = rho * ax0 * ayp;
+  e[3] = rho * axm * ay0;
+  e[4] = rho * ax0 * aym;
+  e[5] = rho * axp * ayp;
+  e[6] = rho * axm * ayp;
+  e[7] = rho * axm * aym;
+  e[8] = rho * axp * aym;
+}
+
+// Density and velocity of a population vector without force (Eqs. 12-13).
+__device__ __forceinline__ void rho_u(const double f[9], double& rho, double& ux, double& uy) {
+  rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const double inv = 1.0 / rho;
+  ux = ((f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6])) * inv;
+  uy = ((f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8])) * inv;
+}
+
+// SplitMix64 finaliser (Steele, Lea & Flood 2014): first output of a stream
+// whose state is `key`.
+__device__ __forceinline__ uint64_t splitmix64_first(uint64_t key) {
+  uint64_t z = key + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace clb

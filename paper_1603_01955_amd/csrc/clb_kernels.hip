@@ -1,0 +1,382 @@
+// HIP kernels of the D2Q9 cascaded LB step for gfx950 (MI355X).
+//
+// Method: Liu & He, arXiv:1603.01955.  Streaming (Eq. 5) is done as a pull:
+// node (x, y) reads P_i from (x - e_ix, y - e_iy), except where that source
+// lies behind a wall (Eq. 20, half-way walls below row 0 and above row
+// ny - 1) or outside the inlet/outlet (periodic wrap, Section 3.1, or
+// pressure ghost columns, Section 3.2).  The step is one fused kernel:
+// gather -> cascaded collision (Eqs. 4, 6-9, 13) -> store to the other
+// buffer, so each node update moves 72 B in and 72 B out of HBM.
+#include "clb_device.hpp"
+#include "clb_internal.hpp"
+
+namespace clb {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Gather of the pre-collision populations of node (x, y).
+// MODE 0: periodic x.  MODE 1: pressure ghost columns at x = -1 and x = nx.
+// ---------------------------------------------------------------------------
+struct View {
+  const double* __restrict__ P;
+  size_t plane;
+  int nx, ny;
+  __device__ __forceinline__ double at(int i, int x, int y) const {
+    return P[(size_t)i * plane + (size_t)y * (size_t)nx + (size_t)x];
+  }
+};
+
+// Population i of a pressure ghost column at row y.  Reading adopted for the
+// extrapolation scheme the paper cites (Section 3.2): density extrapolated
+// so that the boundary plane carries rho_b, velocity extrapolated linearly
+// from the two adjacent columns, non-equilibrium part copied from the
+// adjacent column: f_g = f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1).
+__device__ __noinline__ double ghost_pop(View v, bool inlet, int y, double rho_b, int i) {
+  const int c1 = inlet ? 0 : v.nx - 1;
+  const int c2 = inlet ? 1 : v.nx - 2;
+  double f1[9], f2[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    f1[k] = v.at(k, c1, y);
+    f2[k] = v.at(k, c2, y);
+  }
+  double rho1, ux1, uy1, rho2, ux2, uy2;
+  rho_u(f1, rho1, ux1, uy1);
+  rho_u(f2, rho2, ux2, uy2);
+  double eg[9], e1[9];
+  equilibrium(2.0 * rho_b - rho1, 2.0 * ux1 - ux2, 2.0 * uy1 - uy2, eg);
+  equilibrium(rho1, ux1, uy1, e1);
+  double out = eg[0] + (f1[0] - e1[0]);
+#pragma unroll
+  for (int k = 1; k < 9; ++k)
+    if (k == i) out = eg[k] + (f1[k] - e1[k]);
+  return out;
+}
+
+template <int MODE>
+struct Gather {
+  View v;
+  double r, omr;        // bounce-back fraction r and 1 - r (Eq. 20)
+  int shift;            // specular source from x -/+ 1 (1) or the same node (0)
+  double rho_in, rho_out;
+
+  // P_i at column xs (possibly -1 or nx) and row ys (always inside).
+  __device__ __forceinline__ double pop(int i, int xs, int ys) const {
+    if (MODE == 0) {
+      if (xs < 0) xs += v.nx;
+      else if (xs >= v.nx) xs -= v.nx;
+      return v.at(i, xs, ys);
+    } else {
+      if (xs < 0 || xs >= v.nx) return ghost_pop(v, xs < 0, ys, xs < 0 ? rho_in : rho_out, i);
+      return v.at(i, xs, ys);
+    }
+  }
+
+  __device__ __forceinline__ void operator()(int x, int y, double f[9]) const {
+    f[0] = pop(0, x, y);
+    f[1] = pop(1, x - 1, y);
+    f[3] = pop(3, x + 1, y);
+    const int xsm = shift ? x - 1 : x;
+    const int xsp = shift ? x + 1 : x;
+    if (y > 0) {
+      f[2] = pop(2, x, y - 1);
+      f[5] = pop(5, x - 1, y - 1);
+      f[6] = pop(6, x + 1, y - 1);
+    } else {  // bottom wall, Eq. (20)
+      f[2] = pop(4, x, 0);
+      f[5] = r * pop(7, x, 0) + omr * pop(8, xsm, 0);
+      f[6] = r * pop(8, x, 0) + omr * pop(7, xsp, 0);
+    }
+    const int t = v.ny - 1;
+    if (y < t) {
+      f[4] = pop(4, x, y + 1);
+      f[7] = pop(7, x + 1, y + 1);
+      f[8] = pop(8, x - 1, y + 1);
+    } else {  // top wall: mirror image of Eq. (20)
+      f[4] = pop(2, x, t);
+      f[7] = r * pop(5, x, t) + omr * pop(6, xsp, t);
+      f[8] = r * pop(6, x, t) + omr * pop(5, xsm, t);
+    }
+  }
+};
+
+__device__ __forceinline__ void store9(double* __restrict__ Q, size_t plane, size_t idx, const double f[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], Q + (size_t)i * plane + idx);
+}
+
+// Row-segment tile index with optional XCD-aware remap: blocks are dealt to
+// the 8 XCDs round-robin, so logical tile (xcd * per + k) makes each XCD walk
+// a contiguous run of row segments (shared edge cache lines stay in one L2).
+__device__ __forceinline__ int logical_block(int remap) {
+  int b = blockIdx.x;
+  if (remap) {
+    const int nb = gridDim.x;
+    const int per = nb >> 3;
+    if (b < (per << 3)) b = (b & 7) * per + (b >> 3);
+  }
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// K1: fused periodic step.  One thread per node, one block per row segment.
+// ---------------------------------------------------------------------------
+template <bool FORCE>
+__global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
+  const int b = logical_block(a.xcd_remap);
+  const int seg = b % a.nseg;
+  const int y = b / a.nseg;
+  const int x = seg * (int)blockDim.x + (int)threadIdx.x;
+  if (x >= a.nx) return;
+  Gather<0> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+  double f[9];
+  g(x, y, f);
+  const Rates s{a.s3, a.snu, a.sq, a.s8};
+  collide<FORCE>(f, a.gx, a.gy, s);
+  store9(a.dst, a.plane, (size_t)y * (size_t)a.nx + (size_t)x, f);
+}
+
+// ---------------------------------------------------------------------------
+// K2: fused pressure-driven step.  Block = PX columns x PY row lanes.  The
+// centre-line density of each column (same step, pre-collision) sets the
+// local Knudsen number Kn(x) = Kn_out rho_out / rho_c(x) (Section 3.2) and
+// through Eqs. (18), (21) the column's s_nu and s_q, shared through LDS.
+// ---------------------------------------------------------------------------
+constexpr int PX = 64;
+constexpr int PY = 4;
+
+__global__ __launch_bounds__(PX * PY) void k_step_pressure(StepArgs a) {
+  __shared__ double s_nu[PX], s_q[PX];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int x = blockIdx.x * PX + tx;
+  Gather<1> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  if (ty == 0 && x < a.nx) {
+    double f[9];
+    const int yc = a.ny / 2;
+    g(x, yc, f);
+    double rc = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    if ((a.ny & 1) == 0) {
+      g(x, yc - 1, f);
+      const double r2 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+      rc = 0.5 * (r2 + rc);
+    }
+    const double kn = a.kn * a.rho_out / rc;
+    const double tt = a.c_tau * kn / (1.0 + a.a * kn);   // Eq. (18): c_tau = sqrt(6/pi) N
+    s_nu[tx] = 1.0 / (0.5 + tt);
+    s_q[tx] = 1.0 / (0.5 + (3.0 + 4.0 * M_PI * tt * tt * a.A2) / (a.tq_den * tt));  // Eq. (21)
+  }
+  __syncthreads();
+  if (x >= a.nx) return;
+  const Rates s{a.s3, s_nu[tx], s_q[tx], a.s8};
+  for (int y = ty; y < a.ny; y += PY) {
+    double f[9];
+    g(x, y, f);
+    collide<false>(f, 0.0, 0.0, s);
+    store9(a.dst, a.plane, (size_t)y * (size_t)a.nx + (size_t)x, f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3: initial state.
+// ---------------------------------------------------------------------------
+__global__ void k_init(InitArgs a) {
+  const size_t n = (size_t)a.nx * (size_t)a.ny;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(idx % (size_t)a.nx);
+    double rho = a.rho0, ux = a.ux0, uy = a.uy0;
+    if (a.kind == 1) {
+      const double xc = (double)x + 0.5;
+      rho = a.rho_in - (a.rho_in - a.rho_out) * xc / (double)a.nx;
+      ux = 0.0;
+      uy = 0.0;
+    }
+    double e[9];
+    equilibrium(rho, ux, uy, e);
+    if (a.kind == 2) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const uint64_t key = a.seed ^ (9ull * (uint64_t)idx + (uint64_t)i);
+        const double U = (double)(splitmix64_first(key) >> 11) * (1.0 / 9007199254740992.0);
+        e[i] += a.amp * (2.0 * U - 1.0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a.dst[(size_t)i * n + idx] = e[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: diagnostics of the pre-collision state.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void k_moments(DiagArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= a.nx) return;
+  Gather<MODE> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  double f[9];
+  g(x, y, f);
+  double rho, ux, uy;
+  rho_u(f, rho, ux, uy);
+  ux += 0.5 * a.gx;
+  uy += 0.5 * a.gy;
+  const size_t idx = (size_t)y * a.nx + x;
+  if (a.rho) a.rho[idx] = rho;
+  if (a.ux) a.ux[idx] = ux;
+  if (a.uy) a.uy[idx] = uy;
+}
+
+// Per-column sums, block = PX columns x PY row lanes, fixed summation order.
+template <int MODE>
+__global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
+  __shared__ double sm[PY][PX], su[PY][PX];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int x = blockIdx.x * PX + tx;
+  Gather<MODE> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  double accm = 0.0, accu = 0.0;
+  if (x < a.nx) {
+    for (int y = ty; y < a.ny; y += PY) {
+      double f[9];
+      g(x, y, f);
+      double rho, ux, uy;
+      rho_u(f, rho, ux, uy);
+      ux += 0.5 * a.gx;
+      accm += rho * ux;
+      accu += ux;
+    }
+  }
+  sm[ty][tx] = accm;
+  su[ty][tx] = accu;
+  __syncthreads();
+  if (ty == 0 && x < a.nx) {
+    double m = sm[0][tx], u = su[0][tx];
+#pragma unroll
+    for (int k = 1; k < PY; ++k) {
+      m += sm[k][tx];
+      u += su[k][tx];
+    }
+    double f[9];
+    const int yc = a.ny / 2;
+    g(x, yc, f);
+    double rc = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    if ((a.ny & 1) == 0) {
+      g(x, yc - 1, f);
+      rc = 0.5 * ((f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]) + rc);
+    }
+    if (a.m) a.m[x] = m;
+    if (a.su) a.su[x] = u;
+    if (a.rhoc) a.rhoc[x] = rc;
+  }
+}
+
+// Sum of n values in a fixed order (one block of 256 threads), divided by
+// `divisor` (n for a mean, 1 for a plain sum).
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ v, int n, double divisor,
+                                             double* __restrict__ out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0] / divisor;
+}
+
+// delta p(x) = (rho_c/3 - p_l(x)) / p_out, p_l linear from p_in to p_out.
+__global__ void k_pressure_dev(const double* __restrict__ rhoc, int nx, double rho_in, double rho_out,
+                               double* __restrict__ dp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  const double p_out = rho_out / 3.0, p_in = rho_in / 3.0;
+  const double pl = p_in - (p_in - p_out) * ((double)x + 0.5) / (double)nx;
+  dp[x] = (rhoc[x] / 3.0 - pl) / p_out;
+}
+
+// Non-finite count: per-block partials, then one block sums them in order.
+__global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restrict__ p, size_t n,
+                                                           double* __restrict__ partial) {
+  __shared__ double s[256];
+  double cnt = 0.0;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double v = p[i];
+    cnt += (v - v == 0.0) ? 0.0 : 1.0;   // inf - inf and NaN - NaN are NaN
+  }
+  s[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st) {
+  if (a.mode == 0) {
+    const int nseg = a.nseg;
+    const dim3 grid((unsigned)((size_t)nseg * (size_t)a.ny));
+    if (a.gx != 0.0 || a.gy != 0.0)
+      k_step_periodic<true><<<grid, block_x, 0, st>>>(a);
+    else
+      k_step_periodic<false><<<grid, block_x, 0, st>>>(a);
+  } else {
+    const dim3 grid((unsigned)((a.nx + PX - 1) / PX));
+    k_step_pressure<<<grid, dim3(PX, PY), 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const InitArgs& a, hipStream_t st) {
+  const size_t n = (size_t)a.nx * a.ny;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_init<<<(unsigned)blocks, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const DiagArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.ny);
+  if (a.mode == 0)
+    k_moments<0><<<grid, 256, 0, st>>>(a);
+  else
+    k_moments<1><<<grid, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)((a.nx + PX - 1) / PX));
+  if (a.mode == 0)
+    k_column_sums<0><<<grid, dim3(PX, PY), 0, st>>>(a);
+  else
+    k_column_sums<1><<<grid, dim3(PX, PY), 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean(const double* v, int n, double* out, hipStream_t st) {
+  k_sum<<<1, 256, 0, st>>>(v, n, (double)n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pressure_dev(const double* rhoc, int nx, double rho_in, double rho_out, double* dp,
+                               hipStream_t st) {
+  k_pressure_dev<<<(nx + 255) / 256, 256, 0, st>>>(rhoc, nx, rho_in, rho_out, dp);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const double* p, size_t n, double* partial, int nblocks, double* out,
+                            hipStream_t st) {
+  k_nonfinite_partial<<<nblocks, 256, 0, st>>>(p, n, partial);
+  k_sum<<<1, 256, 0, st>>>(partial, nblocks, 1.0, out);
+  return hipGetLastError();
+}
+
+}  // namespace clb

@@ -1,0 +1,111 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/clb.h, validates parameters with the documented
+status codes, and derives the Eq. (18) / Eq. (21) constants like the CPU
+reference."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+clb = pytest.importorskip("paper_1603_01955_amd.clb")
+
+from oracle import clb_ref as C  # noqa: E402
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(HEADER_DIR):
+        if fn.endswith(".h"):
+            with open(os.path.join(HEADER_DIR, fn)) as fh:
+                text = fh.read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(clb_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(clb.LIB_PATH):
+        pytest.fail("libclb.so is not built (python -m paper_1603_01955_amd.build)")
+    return clb.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_symbols()
+    assert "clb_init" in names and "clb_step" in names and "clb_moments" in names
+    assert "clb_massflow" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_defaults_are_section3_values(lib):
+    p = clb.clb_params()
+    lib.clb_params_default(ctypes.byref(p))
+    assert (p.a, p.A2, p.s3, p.s8, p.sigma, p.tq_den) == (2.0, 0.55, 1.1, 1.2, 1.0, 16.0)
+    assert math.isnan(p.A1) and math.isnan(p.r)
+
+
+@pytest.mark.parametrize("nx,ny,kn,sigma,xbc", [
+    (4, 32, 0.1, 1.0, "periodic"), (4000, 40, 0.1, 1.0, "pressure"),
+    (32768, 2048, 1.0, 1.0, "periodic"), (2000, 20, 0.1, 0.93, "pressure"),
+    (50, 50, 2 * 10 / math.sqrt(math.pi), 1.0, "periodic")])
+def test_derived_constants_match_reference(lib, nx, ny, kn, sigma, xbc):
+    p = clb.make_params(nx, ny, xbc=xbc, kn=kn, sigma=sigma)
+    d = clb.derive(p)
+    prm = C.Params(nx=nx, ny=ny, kn=kn, sigma=sigma, xbc=xbc)
+    A1, r = C.resolved(prm)
+    assert d["A1"] == pytest.approx(A1, rel=1e-15)
+    assert d["r"] == pytest.approx(r, rel=1e-15)
+    assert d["s_nu"] == pytest.approx(C.rate_nu(kn, ny, 2.0), rel=1e-14)
+    assert d["s_q"] == pytest.approx(C.rate_q(kn, ny, 2.0, 0.55), rel=1e-14)
+    assert d["tau_tilde"] == pytest.approx(C.tau_tilde(kn, ny, 2.0), rel=1e-14)
+
+
+def test_workspace_size_arithmetic(lib):
+    p = clb.make_params(1000, 30)
+    n = clb.workspace_size(p)
+    assert n >= 2 * 72 * 1000 * 30 + 4 * 8 * 1000
+    assert n < 2 * 72 * 1000 * 30 + 4 * 8 * 1000 + 64 * 1024
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("ny", -1), ("xbc", 7), ("init", 9), ("kn", 0.0), ("kn", -1.0), ("kn", math.inf),
+    ("a", -0.1), ("sigma", 0.0), ("sigma", 2.5), ("A2", -1.0), ("r", 1.5), ("s3", 2.0),
+    ("s8", 0.0), ("gx", math.nan), ("p_ratio", 0.0), ("rho_out", -1.0), ("rho0", 0.0),
+    ("init_amp", -1e-3), ("tq_den", 0.0), ("cbbsr_shift", 2), ("reserved", 1)])
+def test_invalid_parameters_rejected(lib, field, value):
+    p = clb.make_params(8, 8)
+    setattr(p, field, value)
+    d = clb.clb_derived()
+    st = lib.clb_derive(ctypes.byref(p), ctypes.byref(d))
+    assert st == clb.CLB_EINVAL
+    msg = lib.clb_last_error().decode()
+    assert field.split("_")[0] in msg or field in msg
+    n = ctypes.c_size_t()
+    assert lib.clb_workspace_size(ctypes.byref(p), ctypes.byref(n)) == clb.CLB_EINVAL
+
+
+def test_pressure_mode_rules(lib):
+    p = clb.make_params(1, 8, xbc="pressure")
+    assert lib.clb_derive(ctypes.byref(p), ctypes.byref(clb.clb_derived())) == clb.CLB_EINVAL
+    p = clb.make_params(10, 8, xbc="pressure")
+    p.gx = 1e-6
+    assert lib.clb_derive(ctypes.byref(p), ctypes.byref(clb.clb_derived())) == clb.CLB_EINVAL
+    assert "pressure" in lib.clb_last_error().decode()
+
+
+def test_null_arguments(lib):
+    p = clb.make_params(8, 8)
+    assert lib.clb_derive(ctypes.byref(p), None) == clb.CLB_EINVAL
+    assert lib.clb_workspace_size(ctypes.byref(p), None) == clb.CLB_EINVAL
+    assert lib.clb_step(None, 1) == clb.CLB_EINVAL
+    assert lib.clb_destroy(None) == clb.CLB_EINVAL
+    out = ctypes.c_void_p()
+    assert lib.clb_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == clb.CLB_EINVAL
+    assert lib.clb_init(ctypes.byref(p), ctypes.c_void_p(4096), 16, None, ctypes.byref(out)) == clb.CLB_ENOMEM
+    assert out.value is None
