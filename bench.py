@@ -28,7 +28,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--block-x", type=int, default=256)
+    ap.add_argument("--block-x", type=int, default=1024)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="instead of the benchmark, run a plain device copy of this many GB "

@@ -107,7 +107,10 @@ void clb_params_default(clb_params* p);
 clb_status clb_derive(const clb_params* p, clb_derived* out);
 
 /* Device workspace in bytes needed by clb_init for *p: two population buffers
- * of 72 * nx * ny bytes each plus a small diagnostics area. */
+ * (72 bytes per node; rows are padded to whole segments of L lanes,
+ * L = min(1024, next power of two >= nx)) plus a small diagnostics area.
+ * The device-side layout of a buffer is internal; populations cross the ABI
+ * only in the [9][ny][nx] layout (clb_get_populations / clb_set_populations). */
 clb_status clb_workspace_size(const clb_params* p, size_t* bytes);
 
 /* Create a context over the caller's workspace (device memory of at least

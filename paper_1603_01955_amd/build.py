@@ -35,10 +35,15 @@ def hipcc():
     return "hipcc"
 
 
-def source_hash():
-    """Hash of the kernel and ABI sources (ties profile data to a kernel version)."""
+# Sources that define the single-channel step kernels (ties recorded
+# profile data to the kernel version it was measured on).
+STEP_SOURCES = ["clb_device.hpp", "clb_internal.hpp", "clb_kernels.hip"]
+
+
+def source_hash(names=STEP_SOURCES):
+    """Hash of the given csrc/ files."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
+    for name in sorted(names):
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]

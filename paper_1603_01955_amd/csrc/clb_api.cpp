@@ -51,8 +51,8 @@ struct Layout {
 
 Layout layout_of(const clb_params* p) {
   Layout L;
-  const size_t n = (size_t)p->nx * (size_t)p->ny;
-  L.buf = align256(9 * n * sizeof(double));
+  const clb::Geo g = clb::make_geo(p->nx, p->ny);
+  L.buf = align256(g.size() * sizeof(double));
   L.col = align256((size_t)p->nx * sizeof(double));
   L.total = 2 * L.buf + 4 * L.col + align256(kPartials * sizeof(double)) + align256(32 * sizeof(double));
   return L;
@@ -92,9 +92,8 @@ clb_status validate(const clb_params* p, clb_derived* d) {
   if (!(finite(p->tq_den) && p->tq_den > 0)) return fail(CLB_EINVAL, "tq_den: must be finite and > 0");
   if (p->cbbsr_shift != 0 && p->cbbsr_shift != 1) return fail(CLB_EINVAL, "cbbsr_shift: must be 0 or 1");
   if (p->reserved != 0) return fail(CLB_EINVAL, "reserved: must be 0");
-  // Launch-shape limit of the periodic kernel (one block per 64-node row segment at worst).
-  const size_t nseg64 = ((size_t)p->nx + 63) / 64;
-  if (nseg64 * (size_t)p->ny >= ((size_t)1 << 31))
+  // Launch-shape limit of the periodic kernel (64-thread blocks at worst).
+  if (clb::make_geo(p->nx, p->ny).padded_nodes() / 64 >= ((size_t)1 << 31))
     return fail(CLB_EINVAL, "nx*ny: grid too large for one launch");
 
   clb_derived dd;
@@ -141,6 +140,7 @@ clb_status check_device_range(const void* ptr, size_t bytes, const char* name) {
 struct clb_ctx {
   clb_params p;
   clb_derived d;
+  clb::Geo g;           // device layout of the population buffers
   double* buf[2];
   int cur;              // buf[cur] holds the current post-collision state
   double* col_m;
@@ -161,10 +161,7 @@ clb::StepArgs step_args(const clb_ctx* c) {
   clb::StepArgs a{};
   a.src = c->buf[c->cur];
   a.dst = c->buf[c->cur ^ 1];
-  a.nx = c->p.nx;
-  a.ny = c->p.ny;
-  a.plane = (size_t)c->p.nx * (size_t)c->p.ny;
-  a.nseg = (c->p.nx + c->block_x - 1) / c->block_x;
+  a.g = c->g;
   a.mode = c->p.xbc;
   a.shift = c->p.cbbsr_shift;
   a.xcd_remap = c->xcd_remap;
@@ -188,9 +185,7 @@ clb::StepArgs step_args(const clb_ctx* c) {
 clb::DiagArgs diag_args(const clb_ctx* c) {
   clb::DiagArgs a{};
   a.src = c->buf[c->cur];
-  a.plane = (size_t)c->p.nx * (size_t)c->p.ny;
-  a.nx = c->p.nx;
-  a.ny = c->p.ny;
+  a.g = c->g;
   a.mode = c->p.xbc;
   a.shift = c->p.cbbsr_shift;
   a.r = c->d.r;
@@ -275,6 +270,7 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   if (!c) return fail(CLB_ENOMEM, "host context allocation failed");
   c->p = *p;
   c->d = d;
+  c->g = clb::make_geo(p->nx, p->ny);
   char* base = static_cast<char*>(d_workspace);
   c->buf[0] = reinterpret_cast<double*>(base);
   c->buf[1] = reinterpret_cast<double*>(base + L.buf);
@@ -288,13 +284,12 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->cur = 0;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
-  c->block_x = 256;
+  c->block_x = 1024;
   c->xcd_remap = 1;
 
   clb::InitArgs ia{};
   ia.dst = c->buf[0];
-  ia.nx = p->nx;
-  ia.ny = p->ny;
+  ia.g = c->g;
   ia.kind = p->init;
   ia.rho0 = p->rho0;
   ia.ux0 = p->ux0;
@@ -404,7 +399,7 @@ clb_status clb_get_populations(clb_ctx* c, double* d_out) {
   if (st != CLB_OK) return st;
   const size_t bytes = 9 * (size_t)c->p.nx * c->p.ny * sizeof(double);
   if ((st = check_device_range(d_out, bytes, "d_out")) != CLB_OK) return st;
-  CLB_HIP(hipMemcpyAsync(d_out, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+  CLB_HIP(clb::launch_export(c->buf[c->cur], c->g, d_out, c->stream));
   return CLB_OK;
 }
 
@@ -413,7 +408,7 @@ clb_status clb_set_populations(clb_ctx* c, const double* d_in) {
   if (st != CLB_OK) return st;
   const size_t bytes = 9 * (size_t)c->p.nx * c->p.ny * sizeof(double);
   if ((st = check_device_range(d_in, bytes, "d_in")) != CLB_OK) return st;
-  CLB_HIP(hipMemcpyAsync(c->buf[c->cur], d_in, bytes, hipMemcpyDeviceToDevice, c->stream));
+  CLB_HIP(clb::launch_import(d_in, c->g, c->buf[c->cur], c->stream));
   c->steps = 0;
   return CLB_OK;
 }
@@ -422,10 +417,10 @@ clb_status clb_check_finite(clb_ctx* c, int32_t* h_ok) {
   clb_status st = check_ctx(c);
   if (st != CLB_OK) return st;
   if (!h_ok) return fail(CLB_EINVAL, "h_ok: NULL");
-  const size_t n = 9 * (size_t)c->p.nx * c->p.ny;
+  const size_t n = (size_t)c->p.nx * c->p.ny;
   size_t nb = (n + 255) / 256;
   if (nb > (size_t)kPartials) nb = kPartials;
-  CLB_HIP(clb::launch_nonfinite(c->buf[c->cur], n, c->partial, (int)nb, c->result, c->stream));
+  CLB_HIP(clb::launch_nonfinite(c->buf[c->cur], c->g, c->partial, (int)nb, c->result, c->stream));
   double bad = 0;
   if ((st = read_result(c, &bad)) != CLB_OK) return st;
   *h_ok = bad == 0.0 ? 1 : 0;
@@ -439,8 +434,7 @@ clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap) {
   if (block_x != 64 && block_x != 128 && block_x != 256 && block_x != 512 && block_x != 1024)
     return fail(CLB_EINVAL, "block_x: must be 64, 128, 256, 512 or 1024");
   if (xcd_remap != 0 && xcd_remap != 1) return fail(CLB_EINVAL, "xcd_remap: must be 0 or 1");
-  const size_t nseg = ((size_t)c->p.nx + block_x - 1) / block_x;
-  if (nseg * (size_t)c->p.ny >= ((size_t)1 << 31)) return fail(CLB_EINVAL, "block_x: grid too large");
+  if (c->g.padded_nodes() / block_x >= ((size_t)1 << 31)) return fail(CLB_EINVAL, "block_x: grid too large");
   c->block_x = block_x;
   c->xcd_remap = xcd_remap;
   return CLB_OK;

@@ -7,13 +7,36 @@
 
 namespace clb {
 
+// Device layout of one population buffer: array of structures of arrays,
+// [y][segment][i][lane] with L = 2^lshift lanes per row segment.  Each row
+// segment keeps its nine directions in one contiguous 72*L-byte block, so a
+// block of threads streams through few DRAM pages; x = segment * L + lane,
+// lanes >= nx in the last segment are padding and never read.
+struct Geo {
+  int nx, ny;
+  int lshift;   // log2 L
+  int nseg;     // segments per row, ceil(nx / L)
+  __host__ __device__ __forceinline__ size_t index(int i, int x, int y) const {
+    return ((((size_t)y * (size_t)nseg + (size_t)(x >> lshift)) * 9 + (size_t)i) << lshift) +
+           (size_t)(x & ((1 << lshift) - 1));
+  }
+  // doubles in one buffer (including padding lanes)
+  __host__ __device__ __forceinline__ size_t size() const {
+    return ((size_t)ny * (size_t)nseg * 9) << lshift;
+  }
+  // padded nodes (threads of a one-node-per-thread launch)
+  __host__ __device__ __forceinline__ size_t padded_nodes() const {
+    return ((size_t)ny * (size_t)nseg) << lshift;
+  }
+};
+
+Geo make_geo(int nx, int ny);
+
 // Arguments of one fused step launch.
 struct StepArgs {
-  const double* src;    // post-collision populations at t - 1, [9][ny][nx]
+  const double* src;    // post-collision populations at t - 1 (device layout)
   double* dst;          // post-collision populations at t
-  size_t plane;         // nx * ny
-  int nx, ny;
-  int nseg;             // row segments per row (periodic kernel)
+  Geo g;
   int mode;             // 0 periodic, 1 pressure
   int shift;            // Eq. (20) specular source from x -/+ 1
   int xcd_remap;
@@ -31,7 +54,7 @@ struct StepArgs {
 
 struct InitArgs {
   double* dst;
-  int nx, ny;
+  Geo g;
   int kind;             // clb_init_kind
   double rho0, ux0, uy0;
   double rho_in, rho_out;
@@ -41,8 +64,7 @@ struct InitArgs {
 
 struct DiagArgs {
   const double* src;
-  size_t plane;
-  int nx, ny;
+  Geo g;
   int mode;
   int shift;
   double r;
@@ -63,7 +85,10 @@ hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);
 hipError_t launch_mean(const double* v, int n, double* out, hipStream_t st);
 hipError_t launch_pressure_dev(const double* rhoc, int nx, double rho_in, double rho_out, double* dp,
                                hipStream_t st);
-hipError_t launch_nonfinite(const double* p, size_t n, double* partial, int nblocks, double* out,
+hipError_t launch_nonfinite(const double* p, const Geo& g, double* partial, int nblocks, double* out,
                             hipStream_t st);
+// Copy between the ABI layout [9][ny][nx] and the device layout.
+hipError_t launch_export(const double* src, const Geo& g, double* out, hipStream_t st);
+hipError_t launch_import(const double* in, const Geo& g, double* dst, hipStream_t st);
 
 }  // namespace clb

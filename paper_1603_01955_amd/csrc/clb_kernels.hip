@@ -12,6 +12,17 @@
 
 namespace clb {
 
+Geo make_geo(int nx, int ny) {
+  Geo g;
+  g.nx = nx;
+  g.ny = ny;
+  int ls = 0;
+  while ((1 << ls) < nx && ls < 10) ++ls;   // L = min(1024, next power of two >= nx)
+  g.lshift = ls;
+  g.nseg = (nx + (1 << ls) - 1) >> ls;
+  return g;
+}
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -20,11 +31,8 @@ namespace {
 // ---------------------------------------------------------------------------
 struct View {
   const double* __restrict__ P;
-  size_t plane;
-  int nx, ny;
-  __device__ __forceinline__ double at(int i, int x, int y) const {
-    return P[(size_t)i * plane + (size_t)y * (size_t)nx + (size_t)x];
-  }
+  Geo g;
+  __device__ __forceinline__ double at(int i, int x, int y) const { return P[g.index(i, x, y)]; }
 };
 
 // Population i of a pressure ghost column at row y.  Reading adopted for the
@@ -33,8 +41,8 @@ struct View {
 // from the two adjacent columns, non-equilibrium part copied from the
 // adjacent column: f_g = f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1).
 __device__ __noinline__ double ghost_pop(View v, bool inlet, int y, double rho_b, int i) {
-  const int c1 = inlet ? 0 : v.nx - 1;
-  const int c2 = inlet ? 1 : v.nx - 2;
+  const int c1 = inlet ? 0 : v.g.nx - 1;
+  const int c2 = inlet ? 1 : v.g.nx - 2;
   double f1[9], f2[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
@@ -64,11 +72,11 @@ struct Gather {
   // P_i at column xs (possibly -1 or nx) and row ys (always inside).
   __device__ __forceinline__ double pop(int i, int xs, int ys) const {
     if (MODE == 0) {
-      if (xs < 0) xs += v.nx;
-      else if (xs >= v.nx) xs -= v.nx;
+      if (xs < 0) xs += v.g.nx;
+      else if (xs >= v.g.nx) xs -= v.g.nx;
       return v.at(i, xs, ys);
     } else {
-      if (xs < 0 || xs >= v.nx) return ghost_pop(v, xs < 0, ys, xs < 0 ? rho_in : rho_out, i);
+      if (xs < 0 || xs >= v.g.nx) return ghost_pop(v, xs < 0, ys, xs < 0 ? rho_in : rho_out, i);
       return v.at(i, xs, ys);
     }
   }
@@ -88,7 +96,7 @@ struct Gather {
       f[5] = r * pop(7, x, 0) + omr * pop(8, xsm, 0);
       f[6] = r * pop(8, x, 0) + omr * pop(7, xsp, 0);
     }
-    const int t = v.ny - 1;
+    const int t = v.g.ny - 1;
     if (y < t) {
       f[4] = pop(4, x, y + 1);
       f[7] = pop(7, x + 1, y + 1);
@@ -101,14 +109,16 @@ struct Gather {
   }
 };
 
-__device__ __forceinline__ void store9(double* __restrict__ Q, size_t plane, size_t idx, const double f[9]) {
+__device__ __forceinline__ void store9(double* __restrict__ Q, const Geo& g, int x, int y, const double f[9]) {
+  const size_t base = g.index(0, x, y);
+  const size_t stride = (size_t)1 << g.lshift;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], Q + (size_t)i * plane + idx);
+  for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], Q + base + (size_t)i * stride);
 }
 
-// Row-segment tile index with optional XCD-aware remap: blocks are dealt to
-// the 8 XCDs round-robin, so logical tile (xcd * per + k) makes each XCD walk
-// a contiguous run of row segments (shared edge cache lines stay in one L2).
+// Block index with optional XCD-aware remap: blocks are dealt to the 8 XCDs
+// round-robin, so logical block (xcd * per + k) makes each XCD walk a
+// contiguous run of row segments (shared edge cache lines stay in one L2).
 __device__ __forceinline__ int logical_block(int remap) {
   int b = blockIdx.x;
   if (remap) {
@@ -120,21 +130,23 @@ __device__ __forceinline__ int logical_block(int remap) {
 }
 
 // ---------------------------------------------------------------------------
-// K1: fused periodic step.  One thread per node, one block per row segment.
+// K1: fused periodic step.  One thread per node; threads enumerate the
+// padded nodes in device-layout order (y, segment, lane).
 // ---------------------------------------------------------------------------
 template <bool FORCE>
 __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
-  const int b = logical_block(a.xcd_remap);
-  const int seg = b % a.nseg;
-  const int y = b / a.nseg;
-  const int x = seg * (int)blockDim.x + (int)threadIdx.x;
-  if (x >= a.nx) return;
-  Gather<0> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+  const size_t t = (size_t)logical_block(a.xcd_remap) * blockDim.x + threadIdx.x;
+  const int lane = (int)(t & (((size_t)1 << a.g.lshift) - 1));
+  const size_t rest = t >> a.g.lshift;
+  const int y = (int)(rest / (size_t)a.g.nseg);
+  const int x = (int)(rest - (size_t)y * a.g.nseg) * (1 << a.g.lshift) + lane;
+  if (y >= a.g.ny || x >= a.g.nx) return;
+  Gather<0> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
   double f[9];
-  g(x, y, f);
+  gat(x, y, f);
   const Rates s{a.s3, a.snu, a.sq, a.s8};
   collide<FORCE>(f, a.gx, a.gy, s);
-  store9(a.dst, a.plane, (size_t)y * (size_t)a.nx + (size_t)x, f);
+  store9(a.dst, a.g, x, y, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -150,14 +162,14 @@ __global__ __launch_bounds__(PX * PY) void k_step_pressure(StepArgs a) {
   __shared__ double s_nu[PX], s_q[PX];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x = blockIdx.x * PX + tx;
-  Gather<1> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
-  if (ty == 0 && x < a.nx) {
+  Gather<1> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  if (ty == 0 && x < a.g.nx) {
     double f[9];
-    const int yc = a.ny / 2;
-    g(x, yc, f);
+    const int yc = a.g.ny / 2;
+    gat(x, yc, f);
     double rc = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    if ((a.ny & 1) == 0) {
-      g(x, yc - 1, f);
+    if ((a.g.ny & 1) == 0) {
+      gat(x, yc - 1, f);
       const double r2 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
       rc = 0.5 * (r2 + rc);
     }
@@ -167,28 +179,29 @@ __global__ __launch_bounds__(PX * PY) void k_step_pressure(StepArgs a) {
     s_q[tx] = 1.0 / (0.5 + (3.0 + 4.0 * M_PI * tt * tt * a.A2) / (a.tq_den * tt));  // Eq. (21)
   }
   __syncthreads();
-  if (x >= a.nx) return;
+  if (x >= a.g.nx) return;
   const Rates s{a.s3, s_nu[tx], s_q[tx], a.s8};
-  for (int y = ty; y < a.ny; y += PY) {
+  for (int y = ty; y < a.g.ny; y += PY) {
     double f[9];
-    g(x, y, f);
+    gat(x, y, f);
     collide<false>(f, 0.0, 0.0, s);
-    store9(a.dst, a.plane, (size_t)y * (size_t)a.nx + (size_t)x, f);
+    store9(a.dst, a.g, x, y, f);
   }
 }
 
 // ---------------------------------------------------------------------------
-// K3: initial state.
+// K3: initial state (logical node order; node = y * nx + x).
 // ---------------------------------------------------------------------------
 __global__ void k_init(InitArgs a) {
-  const size_t n = (size_t)a.nx * (size_t)a.ny;
+  const size_t n = (size_t)a.g.nx * (size_t)a.g.ny;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
        idx += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(idx % (size_t)a.nx);
+    const int y = (int)(idx / (size_t)a.g.nx);
+    const int x = (int)(idx - (size_t)y * a.g.nx);
     double rho = a.rho0, ux = a.ux0, uy = a.uy0;
     if (a.kind == 1) {
       const double xc = (double)x + 0.5;
-      rho = a.rho_in - (a.rho_in - a.rho_out) * xc / (double)a.nx;
+      rho = a.rho_in - (a.rho_in - a.rho_out) * xc / (double)a.g.nx;
       ux = 0.0;
       uy = 0.0;
     }
@@ -203,7 +216,24 @@ __global__ void k_init(InitArgs a) {
       }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a.dst[(size_t)i * n + idx] = e[i];
+    for (int i = 0; i < 9; ++i) a.dst[a.g.index(i, x, y)] = e[i];
+  }
+}
+
+// ABI layout [9][ny][nx] <-> device layout.
+template <bool EXPORT>
+__global__ void k_convert(const double* __restrict__ src, Geo g, double* __restrict__ dst) {
+  const size_t plane = (size_t)g.nx * (size_t)g.ny;
+  const size_t n = 9 * plane;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(k / plane);
+    const size_t node = k - (size_t)i * plane;
+    const int y = (int)(node / (size_t)g.nx);
+    const int x = (int)(node - (size_t)y * g.nx);
+    if (EXPORT)
+      dst[k] = src[g.index(i, x, y)];
+    else
+      dst[g.index(i, x, y)] = src[k];
   }
 }
 
@@ -214,15 +244,15 @@ template <int MODE>
 __global__ void k_moments(DiagArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= a.nx) return;
-  Gather<MODE> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  if (x >= a.g.nx) return;
+  Gather<MODE> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
   double f[9];
-  g(x, y, f);
+  gat(x, y, f);
   double rho, ux, uy;
   rho_u(f, rho, ux, uy);
   ux += 0.5 * a.gx;
   uy += 0.5 * a.gy;
-  const size_t idx = (size_t)y * a.nx + x;
+  const size_t idx = (size_t)y * a.g.nx + x;
   if (a.rho) a.rho[idx] = rho;
   if (a.ux) a.ux[idx] = ux;
   if (a.uy) a.uy[idx] = uy;
@@ -234,12 +264,12 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
   __shared__ double sm[PY][PX], su[PY][PX];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x = blockIdx.x * PX + tx;
-  Gather<MODE> g{{a.src, a.plane, a.nx, a.ny}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  Gather<MODE> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
   double accm = 0.0, accu = 0.0;
-  if (x < a.nx) {
-    for (int y = ty; y < a.ny; y += PY) {
+  if (x < a.g.nx) {
+    for (int y = ty; y < a.g.ny; y += PY) {
       double f[9];
-      g(x, y, f);
+      gat(x, y, f);
       double rho, ux, uy;
       rho_u(f, rho, ux, uy);
       ux += 0.5 * a.gx;
@@ -250,7 +280,7 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
   sm[ty][tx] = accm;
   su[ty][tx] = accu;
   __syncthreads();
-  if (ty == 0 && x < a.nx) {
+  if (ty == 0 && x < a.g.nx) {
     double m = sm[0][tx], u = su[0][tx];
 #pragma unroll
     for (int k = 1; k < PY; ++k) {
@@ -258,11 +288,11 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
       u += su[k][tx];
     }
     double f[9];
-    const int yc = a.ny / 2;
-    g(x, yc, f);
+    const int yc = a.g.ny / 2;
+    gat(x, yc, f);
     double rc = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    if ((a.ny & 1) == 0) {
-      g(x, yc - 1, f);
+    if ((a.g.ny & 1) == 0) {
+      gat(x, yc - 1, f);
       rc = 0.5 * ((f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]) + rc);
     }
     if (a.m) a.m[x] = m;
@@ -297,14 +327,21 @@ __global__ void k_pressure_dev(const double* __restrict__ rhoc, int nx, double r
   dp[x] = (rhoc[x] / 3.0 - pl) / p_out;
 }
 
-// Non-finite count: per-block partials, then one block sums them in order.
-__global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restrict__ p, size_t n,
+// Non-finite count over the logical nodes: per-block partials, then one
+// block sums them in order.
+__global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restrict__ p, Geo g,
                                                            double* __restrict__ partial) {
   __shared__ double s[256];
+  const size_t n = (size_t)g.nx * (size_t)g.ny;
   double cnt = 0.0;
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const double v = p[i];
-    cnt += (v - v == 0.0) ? 0.0 : 1.0;   // inf - inf and NaN - NaN are NaN
+  for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+    const int y = (int)(k / (size_t)g.nx);
+    const int x = (int)(k - (size_t)y * g.nx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const double v = p[g.index(i, x, y)];
+      cnt += (v - v == 0.0) ? 0.0 : 1.0;   // inf - inf and NaN - NaN are NaN
+    }
   }
   s[threadIdx.x] = cnt;
   __syncthreads();
@@ -315,6 +352,13 @@ __global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restr
   if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
 }
 
+unsigned grid_for(size_t n, unsigned cap = 65536) {
+  size_t b = (n + 255) / 256;
+  if (b > cap) b = cap;
+  if (b == 0) b = 1;
+  return (unsigned)b;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -322,29 +366,36 @@ __global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restr
 // ---------------------------------------------------------------------------
 hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st) {
   if (a.mode == 0) {
-    const int nseg = a.nseg;
-    const dim3 grid((unsigned)((size_t)nseg * (size_t)a.ny));
+    const size_t threads = a.g.padded_nodes();
+    const dim3 grid((unsigned)((threads + block_x - 1) / block_x));
     if (a.gx != 0.0 || a.gy != 0.0)
       k_step_periodic<true><<<grid, block_x, 0, st>>>(a);
     else
       k_step_periodic<false><<<grid, block_x, 0, st>>>(a);
   } else {
-    const dim3 grid((unsigned)((a.nx + PX - 1) / PX));
+    const dim3 grid((unsigned)((a.g.nx + PX - 1) / PX));
     k_step_pressure<<<grid, dim3(PX, PY), 0, st>>>(a);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_init(const InitArgs& a, hipStream_t st) {
-  const size_t n = (size_t)a.nx * a.ny;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  k_init<<<(unsigned)blocks, 256, 0, st>>>(a);
+  k_init<<<grid_for((size_t)a.g.nx * a.g.ny), 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const double* src, const Geo& g, double* out, hipStream_t st) {
+  k_convert<true><<<grid_for(9 * (size_t)g.nx * g.ny), 256, 0, st>>>(src, g, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_import(const double* in, const Geo& g, double* dst, hipStream_t st) {
+  k_convert<false><<<grid_for(9 * (size_t)g.nx * g.ny), 256, 0, st>>>(in, g, dst);
   return hipGetLastError();
 }
 
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st) {
-  const dim3 grid((unsigned)((a.nx + 255) / 256), (unsigned)a.ny);
+  const dim3 grid((unsigned)((a.g.nx + 255) / 256), (unsigned)a.g.ny);
   if (a.mode == 0)
     k_moments<0><<<grid, 256, 0, st>>>(a);
   else
@@ -353,7 +404,7 @@ hipError_t launch_moments(const DiagArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st) {
-  const dim3 grid((unsigned)((a.nx + PX - 1) / PX));
+  const dim3 grid((unsigned)((a.g.nx + PX - 1) / PX));
   if (a.mode == 0)
     k_column_sums<0><<<grid, dim3(PX, PY), 0, st>>>(a);
   else
@@ -372,9 +423,9 @@ hipError_t launch_pressure_dev(const double* rhoc, int nx, double rho_in, double
   return hipGetLastError();
 }
 
-hipError_t launch_nonfinite(const double* p, size_t n, double* partial, int nblocks, double* out,
+hipError_t launch_nonfinite(const double* p, const Geo& g, double* partial, int nblocks, double* out,
                             hipStream_t st) {
-  k_nonfinite_partial<<<nblocks, 256, 0, st>>>(p, n, partial);
+  k_nonfinite_partial<<<nblocks, 256, 0, st>>>(p, g, partial);
   k_sum<<<1, 256, 0, st>>>(partial, nblocks, 1.0, out);
   return hipGetLastError();
 }
