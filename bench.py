@@ -28,6 +28,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batched Kn-sweep comparison")
     ap.add_argument("--block-x", type=int, default=1024)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -68,6 +69,67 @@ def traffic_from_profile():
     if rec.get("source_hash") != source_hash() or "bytes_per_launch" not in rec:
         return None
     return float(rec["bytes_per_launch"])
+
+
+def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12):
+    """Batched Kn sweep (64 periodic channels, heights from {16..128}, Kn
+    log-spaced 0.01-10, g = 1e-6, each to steady state) in one persistent
+    launch, against a loop of single-channel solvers with the same check
+    cadence, eager and hipGraph'd.  Returns a dict for the JSON line."""
+    import numpy as np
+    import torch
+    from clb_inputs import kn_sweep_channels
+    from paper_1603_01955_amd import Batch, Solver, clb
+
+    heights, kns = kn_sweep_channels(64, seed=7)
+    params = [clb.make_params(4, ny, kn=kn, gx=1e-6) for ny, kn in zip(heights, kns)]
+    b = Batch(params)
+    t0 = time.perf_counter()
+    threads, longest = b.tune(probe_steps=200)
+    t_tune = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_b, conv = b.run(max_steps, check_every, tol)        # synchronises
+    t_batch = time.perf_counter() - t0
+    q = b.flow_rate()
+    b.close()
+
+    def loop(graph):
+        solvers = [Solver(params=p) for p in params]
+        for s in solvers:
+            if graph:
+                s.set_graph_steps(check_every)
+        torch.cuda.synchronize()
+        steps = []
+        t0 = time.perf_counter()
+        for s in solvers:
+            prev, n = float("nan"), 0
+            while n < max_steps:
+                s.step(check_every)
+                n += check_every
+                cur = s.flow_rate()                            # synchronises
+                if abs(cur - prev) <= tol * abs(cur):
+                    break
+                prev = cur
+            steps.append(n)
+        dt = time.perf_counter() - t0
+        for s in solvers:
+            s.close()
+        return dt, steps
+
+    t_loop, steps_l = loop(graph=False)
+    t_graph, _ = loop(graph=True)
+    kmin = float(np.array(kns)[int(np.argmin(q))])
+    return {
+        "channels": len(params), "check_every": check_every, "tol": tol,
+        "all_converged": bool(conv.all()),
+        "steps_total": int(steps_b.sum()), "steps_max": int(steps_b.max()),
+        "loop_steps_match": bool((np.array(steps_l) == steps_b).all()),
+        "batched_s": round(t_batch, 4), "loop_s": round(t_loop, 4), "graph_loop_s": round(t_graph, 4),
+        "speedup_vs_loop": round(t_loop / t_batch, 2), "speedup_vs_graph_loop": round(t_graph / t_batch, 2),
+        "tuned": {"threads": threads, "longest_first": longest, "tune_s": round(t_tune, 3)},
+        "kn_at_min_Q": kmin,
+    }
 
 
 def cpu_baseline():
@@ -147,6 +209,8 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if not args.no_sweep:
+        rec["kn_sweep"] = kn_sweep()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec), flush=True)

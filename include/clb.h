@@ -169,8 +169,67 @@ clb_status clb_check_finite(clb_ctx* c, int32_t* h_ok);
  * xcd_remap = 1 to map consecutive row segments onto the same XCD. */
 clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap);
 
+/* Launch-overhead control for small grids: with steps_per_graph > 0,
+ * clb_step replays a hipGraph of steps_per_graph recorded step launches
+ * (recorded on first use, on a private stream, and replayed on the context's
+ * stream) and launches any remainder one by one.  0 (default) disables it.
+ * Results are identical either way. */
+clb_status clb_set_graph_steps(clb_ctx* c, int32_t steps_per_graph);
+
 /* Release the host context (not the caller's workspace or stream). */
 clb_status clb_destroy(clb_ctx* c);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent small periodic channels advanced by one
+ * persistent launch (the Kn sweep of Section 3.1 that traces the flow rate
+ * Q(Kn) and its Knudsen minimum).  Channel c is described by params[c]
+ * (periodic, uniform or perturbed start); its two population buffers must fit
+ * in one workgroup's LDS (144 * nx * ny bytes plus a reduction area, e.g.
+ * nx * ny <= 1024 on MI355X).  Each channel advances exactly as a
+ * single-channel context with the same parameters would.
+ * ------------------------------------------------------------------------- */
+typedef struct clb_batch clb_batch;
+
+/* Device workspace in bytes for a batch of nch channels. */
+clb_status clb_batch_workspace_size(int32_t nch, const clb_params* params, size_t* bytes);
+
+/* Create a batch over the caller's workspace and enqueue every channel's
+ * start; params is copied.  Synchronises hip_stream once (table uploads). */
+clb_status clb_batch_init(int32_t nch, const clb_params* params, void* d_workspace, size_t bytes,
+                          void* hip_stream, clb_batch** out);
+
+/* Advance every channel that has not converged by up to max_steps steps in
+ * one persistent launch (recorded once as a hipGraph and replayed while the
+ * arguments stay the same).  With check_every > 0, every check_every steps
+ * (counted from the channel's start) the channel computes S = sum over its
+ * nodes of u_x of the pre-collision state and stops once
+ * |S - S_previous| <= tol * |S|.  h_steps[nch] (total steps per channel) and
+ * h_converged[nch] are written if non-NULL, which synchronises the stream. */
+clb_status clb_batch_run(clb_batch* b, int64_t max_steps, int32_t check_every, double tol,
+                         int64_t* h_steps, int32_t* h_converged);
+
+/* Dimensionless flow rate Q of every channel (Section 3.1, as clb_flow_rate),
+ * h_Q[nch] on the host; every channel needs gx != 0.  Synchronises. */
+clb_status clb_batch_flow_rate(clb_batch* b, double* h_Q);
+
+/* Launch shape: threads per workgroup (64, 128, 256, 512 or 1024) and the
+ * channel-to-workgroup order (1: estimated longest run first, 0: as given). */
+clb_status clb_batch_set_launch(clb_batch* b, int32_t threads, int32_t longest_first);
+
+/* Autotuner: time every admissible launch shape for probe_steps steps on a
+ * scratch copy of the state (the batch does not advance), keep the fastest
+ * and report it.  Synchronises. */
+clb_status clb_batch_tune(clb_batch* b, int32_t probe_steps, int32_t* h_threads, int32_t* h_longest_first);
+
+/* Copy channel ch's post-collision populations out / in ([9][ny][nx], device). */
+clb_status clb_batch_get_populations(clb_batch* b, int32_t ch, double* d_out);
+clb_status clb_batch_set_populations(clb_batch* b, int32_t ch, const double* d_in);
+
+/* Forget step counts and convergence history (the populations are kept). */
+clb_status clb_batch_reset(clb_batch* b);
+
+/* Release the host context (synchronises the stream first). */
+clb_status clb_batch_destroy(clb_batch* b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* clb_last_error(void);

@@ -67,6 +67,7 @@ _SIGNATURES = {
     "clb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "clb_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "clb_set_graph_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "clb_last_error": (ctypes.c_char_p, []),
 }
@@ -162,8 +163,11 @@ class Solver:
         check(lib().clb_steps_done(self._ctx, ctypes.byref(v)))
         return v.value
 
-    def set_launch(self, block_x=256, xcd_remap=1):
+    def set_launch(self, block_x=1024, xcd_remap=1):
         check(lib().clb_set_launch(self._ctx, int(block_x), int(xcd_remap)))
+
+    def set_graph_steps(self, steps_per_graph):
+        check(lib().clb_set_graph_steps(self._ctx, int(steps_per_graph)))
 
     # -- state ------------------------------------------------------------
     def _empty(self, *shape):
@@ -219,6 +223,102 @@ class Solver:
         if getattr(self, "_ctx", None):
             check(lib().clb_destroy(self._ctx))
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_BATCH_SIGNATURES = {
+    "clb_batch_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "clb_batch_init": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "clb_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_batch_flow_rate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "clb_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "clb_batch_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "clb_batch_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "clb_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "clb_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+}
+_SIGNATURES.update(_BATCH_SIGNATURES)
+
+
+def batch_workspace_size(params_list):
+    arr = (clb_params * len(params_list))(*params_list)
+    n = ctypes.c_size_t()
+    check(lib().clb_batch_workspace_size(len(params_list), arr, ctypes.byref(n)))
+    return n.value
+
+
+class Batch:
+    """Many independent periodic channels advanced by one persistent launch
+    (the Kn sweep of Section 3.1).  ``params_list`` holds one clb_params per
+    channel (see make_params)."""
+
+    def __init__(self, params_list, device="cuda", stream=None):
+        import numpy as np
+        self.params = list(params_list)
+        self.nch = len(self.params)
+        self.device = torch.device(device)
+        self._arr = (clb_params * self.nch)(*self.params)
+        nbytes = batch_workspace_size(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib().clb_batch_init(self.nch, self._arr, _ptr(self.workspace), nbytes,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._steps = np.zeros(self.nch, dtype=np.int64)
+        self._conv = np.zeros(self.nch, dtype=np.int32)
+
+    def run(self, max_steps, check_every=0, tol=0.0):
+        """Returns (steps per channel, converged flags) as numpy arrays."""
+        check(lib().clb_batch_run(self._h, int(max_steps), int(check_every), float(tol),
+                                  self._steps.ctypes.data_as(ctypes.c_void_p),
+                                  self._conv.ctypes.data_as(ctypes.c_void_p)))
+        return self._steps.copy(), self._conv.astype(bool)
+
+    def flow_rate(self):
+        import numpy as np
+        q = np.zeros(self.nch, dtype=np.float64)
+        check(lib().clb_batch_flow_rate(self._h, q.ctypes.data_as(ctypes.c_void_p)))
+        return q
+
+    def set_launch(self, threads, longest_first=1):
+        check(lib().clb_batch_set_launch(self._h, int(threads), int(longest_first)))
+
+    def tune(self, probe_steps=500):
+        t, o = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().clb_batch_tune(self._h, int(probe_steps), ctypes.byref(t), ctypes.byref(o)))
+        return t.value, o.value
+
+    def populations(self, ch):
+        p = self.params[ch]
+        out = torch.empty(9, p.ny, p.nx, dtype=torch.float64, device=self.device)
+        check(lib().clb_batch_get_populations(self._h, int(ch), _ptr(out)))
+        return out
+
+    def set_populations(self, ch, P):
+        p = self.params[ch]
+        P = P.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(P.shape) != (9, p.ny, p.nx):
+            raise ValueError("populations must have shape (9, ny, nx)")
+        check(lib().clb_batch_set_populations(self._h, int(ch), _ptr(P)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def reset(self):
+        check(lib().clb_batch_reset(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().clb_batch_destroy(self._h))
+            self._h = None
 
     def __del__(self):
         try:

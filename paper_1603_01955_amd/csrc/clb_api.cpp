@@ -153,6 +153,11 @@ struct clb_ctx {
   int64_t steps;
   int block_x;
   int xcd_remap;
+  // optional hipGraph of graph_steps step launches, one per starting buffer
+  int graph_steps;
+  hipStream_t capture;  // private stream used only to record the graphs
+  hipGraph_t graph[2];
+  hipGraphExec_t gexec[2];
 };
 
 namespace {
@@ -266,7 +271,7 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   if (bytes < L.total) return fail(CLB_ENOMEM, "workspace: %zu bytes given, %zu needed", bytes, L.total);
   st = check_device_range(d_workspace, L.total, "d_workspace");
   if (st != CLB_OK) return st;
-  clb_ctx* c = new (std::nothrow) clb_ctx;
+  clb_ctx* c = new (std::nothrow) clb_ctx();   // value-initialised: no graphs yet
   if (!c) return fail(CLB_ENOMEM, "host context allocation failed");
   c->p = *p;
   c->d = d;
@@ -307,10 +312,57 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   return CLB_OK;
 }
 
+namespace {
+
+void drop_graphs(clb_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+}
+
+// Record graph_steps step launches starting from buffer parity c->cur on the
+// private capture stream (recording only: nothing runs there).
+clb_status record_graph(clb_ctx* c) {
+  const int p = c->cur;
+  if (!c->capture) CLB_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+  CLB_HIP(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  int cur = p;
+  for (int k = 0; k < c->graph_steps && e == hipSuccess; ++k) {
+    clb::StepArgs a = step_args(c);
+    a.src = c->buf[cur];
+    a.dst = c->buf[cur ^ 1];
+    e = clb::launch_step(a, c->block_x, c->capture);
+    cur ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->capture, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(e, "step launch during graph capture");
+  }
+  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+  c->graph[p] = g;
+  CLB_HIP(hipGraphInstantiate(&c->gexec[p], g, nullptr, nullptr, 0));
+  return CLB_OK;
+}
+
+}  // namespace
+
 clb_status clb_step(clb_ctx* c, int64_t nsteps) {
   clb_status st = check_ctx(c);
   if (st != CLB_OK) return st;
   if (nsteps < 0) return fail(CLB_EINVAL, "nsteps: must be >= 0");
+  while (c->graph_steps > 0 && nsteps >= c->graph_steps) {
+    if (!c->gexec[c->cur] && (st = record_graph(c)) != CLB_OK) return st;
+    CLB_HIP(hipGraphLaunch(c->gexec[c->cur], c->stream));
+    c->cur ^= (c->graph_steps & 1);
+    c->steps += c->graph_steps;
+    nsteps -= c->graph_steps;
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
     clb::StepArgs a = step_args(c);
     CLB_HIP(clb::launch_step(a, c->block_x, c->stream));
@@ -435,13 +487,33 @@ clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap) {
     return fail(CLB_EINVAL, "block_x: must be 64, 128, 256, 512 or 1024");
   if (xcd_remap != 0 && xcd_remap != 1) return fail(CLB_EINVAL, "xcd_remap: must be 0 or 1");
   if (c->g.padded_nodes() / block_x >= ((size_t)1 << 31)) return fail(CLB_EINVAL, "block_x: grid too large");
+  if (block_x != c->block_x || xcd_remap != c->xcd_remap) {
+    CLB_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+  }
   c->block_x = block_x;
   c->xcd_remap = xcd_remap;
   return CLB_OK;
 }
 
+clb_status clb_set_graph_steps(clb_ctx* c, int32_t steps_per_graph) {
+  clb_status st = check_ctx(c);
+  if (st != CLB_OK) return st;
+  if (steps_per_graph < 0 || steps_per_graph > 100000)
+    return fail(CLB_EINVAL, "steps_per_graph: must lie in [0, 100000]");
+  if (steps_per_graph != c->graph_steps) {
+    CLB_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->graph_steps = steps_per_graph;
+  }
+  return CLB_OK;
+}
+
 clb_status clb_destroy(clb_ctx* c) {
   if (!c) return fail(CLB_EINVAL, "ctx: NULL");
+  if (c->gexec[0] || c->gexec[1]) (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
   delete c;
   return CLB_OK;
 }
@@ -449,3 +521,16 @@ clb_status clb_destroy(clb_ctx* c) {
 const char* clb_last_error(void) { return g_err; }
 
 }  // extern "C"
+
+// Helpers shared with the other translation units of the library.
+namespace clb {
+
+clb_status set_error(clb_status st, const char* message) { return fail(st, "%s", message); }
+
+clb_status validate_params(const clb_params* p, clb_derived* d) { return validate(p, d); }
+
+clb_status check_device_ptr(const void* ptr, size_t bytes, const char* name) {
+  return check_device_range(ptr, bytes, name);
+}
+
+}  // namespace clb

@@ -26,6 +26,9 @@ struct Rates {
 // ---------------------------------------------------------------------------
 template <bool FORCE>
 __device__ __forceinline__ void collide(double f[9], double gx, double gy, const Rates& s) {
+  // Every product and sum rounded on its own: the same FP64 result in every
+  // kernel that inlines this, whatever the compiler fuses around it.
+#pragma clang fp contract(off)
   const double f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4];
   const double f5 = f[5], f6 = f[6], f7 = f[7], f8 = f[8];
 
@@ -116,6 +119,7 @@ __device__ __forceinline__ void collide(double f[9], double gx, double gy, const
 // moments (1, u, 1/3 + u^2), so f_i^eq = rho * w(e_ix, ux) * w(e_iy, uy) with
 // w(0, u) = 2/3 - u^2 and w(+-1, u) = (1/3 + u^2 +- u) / 2.
 __device__ __forceinline__ void equilibrium(double rho, double ux, double uy, double e[9]) {
+#pragma clang fp contract(off)
   const double ax0 = 2.0 / 3.0 - ux * ux, axp = 0.5 * (1.0 / 3.0 + ux * ux + ux),
                axm = 0.5 * (1.0 / 3.0 + ux * ux - ux);
   const double ay0 = 2.0 / 3.0 - uy * uy, ayp = 0.5 * (1.0 / 3.0 + uy * uy + uy),
@@ -133,6 +137,7 @@ __device__ __forceinline__ void equilibrium(double rho, double ux, double uy, do
 
 // Density and velocity of a population vector without force (Eqs. 12-13).
 __device__ __forceinline__ void rho_u(const double f[9], double& rho, double& ux, double& uy) {
+#pragma clang fp contract(off)
   rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   const double inv = 1.0 / rho;
   ux = ((f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6])) * inv;

@@ -92,3 +92,12 @@ hipError_t launch_export(const double* src, const Geo& g, double* out, hipStream
 hipError_t launch_import(const double* in, const Geo& g, double* dst, hipStream_t st);
 
 }  // namespace clb
+
+// Host helpers defined in clb_api.cpp and used by every ABI translation unit.
+#include "clb.h"
+
+namespace clb {
+clb_status set_error(clb_status st, const char* message);
+clb_status validate_params(const clb_params* p, clb_derived* d);
+clb_status check_device_ptr(const void* ptr, size_t bytes, const char* name);
+}  // namespace clb

@@ -8,6 +8,7 @@
 // gather -> cascaded collision (Eqs. 4, 6-9, 13) -> store to the other
 // buffer, so each node update moves 72 B in and 72 B out of HBM.
 #include "clb_device.hpp"
+#include "clb_gather.hpp"
 #include "clb_internal.hpp"
 
 namespace clb {
@@ -24,90 +25,6 @@ Geo make_geo(int nx, int ny) {
 }
 
 namespace {
-
-// ---------------------------------------------------------------------------
-// Gather of the pre-collision populations of node (x, y).
-// MODE 0: periodic x.  MODE 1: pressure ghost columns at x = -1 and x = nx.
-// ---------------------------------------------------------------------------
-struct View {
-  const double* __restrict__ P;
-  Geo g;
-  __device__ __forceinline__ double at(int i, int x, int y) const { return P[g.index(i, x, y)]; }
-};
-
-// Population i of a pressure ghost column at row y.  Reading adopted for the
-// extrapolation scheme the paper cites (Section 3.2): density extrapolated
-// so that the boundary plane carries rho_b, velocity extrapolated linearly
-// from the two adjacent columns, non-equilibrium part copied from the
-// adjacent column: f_g = f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1).
-__device__ __noinline__ double ghost_pop(View v, bool inlet, int y, double rho_b, int i) {
-  const int c1 = inlet ? 0 : v.g.nx - 1;
-  const int c2 = inlet ? 1 : v.g.nx - 2;
-  double f1[9], f2[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    f1[k] = v.at(k, c1, y);
-    f2[k] = v.at(k, c2, y);
-  }
-  double rho1, ux1, uy1, rho2, ux2, uy2;
-  rho_u(f1, rho1, ux1, uy1);
-  rho_u(f2, rho2, ux2, uy2);
-  double eg[9], e1[9];
-  equilibrium(2.0 * rho_b - rho1, 2.0 * ux1 - ux2, 2.0 * uy1 - uy2, eg);
-  equilibrium(rho1, ux1, uy1, e1);
-  double out = eg[0] + (f1[0] - e1[0]);
-#pragma unroll
-  for (int k = 1; k < 9; ++k)
-    if (k == i) out = eg[k] + (f1[k] - e1[k]);
-  return out;
-}
-
-template <int MODE>
-struct Gather {
-  View v;
-  double r, omr;        // bounce-back fraction r and 1 - r (Eq. 20)
-  int shift;            // specular source from x -/+ 1 (1) or the same node (0)
-  double rho_in, rho_out;
-
-  // P_i at column xs (possibly -1 or nx) and row ys (always inside).
-  __device__ __forceinline__ double pop(int i, int xs, int ys) const {
-    if (MODE == 0) {
-      if (xs < 0) xs += v.g.nx;
-      else if (xs >= v.g.nx) xs -= v.g.nx;
-      return v.at(i, xs, ys);
-    } else {
-      if (xs < 0 || xs >= v.g.nx) return ghost_pop(v, xs < 0, ys, xs < 0 ? rho_in : rho_out, i);
-      return v.at(i, xs, ys);
-    }
-  }
-
-  __device__ __forceinline__ void operator()(int x, int y, double f[9]) const {
-    f[0] = pop(0, x, y);
-    f[1] = pop(1, x - 1, y);
-    f[3] = pop(3, x + 1, y);
-    const int xsm = shift ? x - 1 : x;
-    const int xsp = shift ? x + 1 : x;
-    if (y > 0) {
-      f[2] = pop(2, x, y - 1);
-      f[5] = pop(5, x - 1, y - 1);
-      f[6] = pop(6, x + 1, y - 1);
-    } else {  // bottom wall, Eq. (20)
-      f[2] = pop(4, x, 0);
-      f[5] = r * pop(7, x, 0) + omr * pop(8, xsm, 0);
-      f[6] = r * pop(8, x, 0) + omr * pop(7, xsp, 0);
-    }
-    const int t = v.g.ny - 1;
-    if (y < t) {
-      f[4] = pop(4, x, y + 1);
-      f[7] = pop(7, x + 1, y + 1);
-      f[8] = pop(8, x - 1, y + 1);
-    } else {  // top wall: mirror image of Eq. (20)
-      f[4] = pop(2, x, t);
-      f[7] = r * pop(5, x, t) + omr * pop(6, xsp, t);
-      f[8] = r * pop(6, x, t) + omr * pop(5, xsm, t);
-    }
-  }
-};
 
 __device__ __forceinline__ void store9(double* __restrict__ Q, const Geo& g, int x, int y, const double f[9]) {
   const size_t base = g.index(0, x, y);
@@ -141,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
   const int y = (int)(rest / (size_t)a.g.nseg);
   const int x = (int)(rest - (size_t)y * a.g.nseg) * (1 << a.g.lshift) + lane;
   if (y >= a.g.ny || x >= a.g.nx) return;
-  Gather<0> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+  Gather<0, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
   double f[9];
   gat(x, y, f);
   const Rates s{a.s3, a.snu, a.sq, a.s8};
@@ -162,7 +79,7 @@ __global__ __launch_bounds__(PX * PY) void k_step_pressure(StepArgs a) {
   __shared__ double s_nu[PX], s_q[PX];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x = blockIdx.x * PX + tx;
-  Gather<1> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  Gather<1, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
   if (ty == 0 && x < a.g.nx) {
     double f[9];
     const int yc = a.g.ny / 2;
@@ -245,7 +162,7 @@ __global__ void k_moments(DiagArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= a.g.nx) return;
-  Gather<MODE> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  Gather<MODE, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
   double f[9];
   gat(x, y, f);
   double rho, ux, uy;
@@ -264,7 +181,7 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
   __shared__ double sm[PY][PX], su[PY][PX];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x = blockIdx.x * PX + tx;
-  Gather<MODE> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+  Gather<MODE, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
   double accm = 0.0, accu = 0.0;
   if (x < a.g.nx) {
     for (int y = ty; y < a.g.ny; y += PY) {

@@ -1,0 +1,122 @@
+"""GPU tests of the batched Kn-sweep form, through the C ABI.
+
+Each channel of a batch must advance bitwise identically to a single-channel
+context with the same parameters (same gather and collision code), match the
+CPU reference, and the converged sweep must reproduce the closed-form
+steady flow rate of the scheme and its Knudsen minimum (Section 3.1).
+"""
+import numpy as np
+import pytest
+import torch
+
+from clb_inputs import kn_sweep_channels, uniform_populations
+from oracle import analytic as A
+from oracle import clb_ref as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+
+
+def _mods():
+    from paper_1603_01955_amd import Batch, Solver, clb
+    return Batch, Solver, clb
+
+
+CHANNELS = [
+    dict(nx=4, ny=16, kn=0.3, gx=1e-6),
+    dict(nx=4, ny=128, kn=0.01, gx=1e-6),
+    dict(nx=7, ny=9, kn=2.0, gx=1e-4, gy=3e-5, cbbsr_shift=0),
+    dict(nx=1, ny=1, kn=0.5, gx=1e-5),
+    dict(nx=32, ny=32, kn=10.0, gx=1e-6, sigma=0.8, tq_den=24.0),
+    dict(nx=3, ny=5, kn=0.1, init="perturbed", init_amp=1e-3, seed=9),
+]
+
+
+def test_batch_bitwise_equals_single_channel():
+    Batch, Solver, clb = _mods()
+    params = [clb.make_params(**kw) for kw in CHANNELS]
+    b = Batch(params)
+    starts = {}
+    for c, kw in enumerate(CHANNELS):
+        if c % 2 == 0:   # random far-from-equilibrium start on half the channels
+            starts[c] = uniform_populations(kw["nx"], kw["ny"], seed=200 + c)
+            b.set_populations(c, torch.from_numpy(starts[c]))
+    steps, conv = b.run(137)
+    assert (steps == 137).all() and not conv.any()
+    for c, kw in enumerate(CHANNELS):
+        s = Solver(params=clb.make_params(**kw))
+        if c in starts:
+            s.set_populations(torch.from_numpy(starts[c]))
+        s.step(137)
+        assert torch.equal(b.populations(c), s.populations()), c
+
+
+def test_batch_matches_reference():
+    Batch, _, clb = _mods()
+    b = Batch([clb.make_params(**kw) for kw in CHANNELS])
+    b.run(60)
+    for c, kw in enumerate(CHANNELS):
+        keys = {k: v for k, v in kw.items() if k not in ("init", "init_amp", "seed")}
+        prm = C.Params(**keys)
+        P0 = C.init_perturbed(prm, 9, 1e-3) if kw.get("init") == "perturbed" else C.init_uniform(prm)
+        ref = C.run(P0, prm, 60)
+        got = b.populations(c).cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref)), c
+
+
+def test_graph_replay_continues_and_tuner_leaves_state():
+    Batch, _, clb = _mods()
+    params = [clb.make_params(**kw) for kw in CHANNELS[:4]]
+    one = Batch(params)
+    one.run(200)
+    two = Batch(params)
+    t, o = two.tune(probe_steps=50)
+    assert t in (64, 128, 256, 512, 1024) and o in (0, 1)
+    steps, _ = two.run(100)
+    assert (steps == 100).all()
+    steps, _ = two.run(100)          # replay of the recorded graph
+    assert (steps == 200).all()
+    for c in range(len(params)):
+        assert torch.equal(one.populations(c), two.populations(c))
+    for threads in (64, 1024):
+        for longest in (0, 1):
+            three = Batch(params)
+            three.set_launch(threads, longest)
+            three.run(200)
+            for c in range(len(params)):
+                assert torch.equal(one.populations(c), three.populations(c)), (threads, longest)
+
+
+def test_kn_sweep_matches_closed_form_and_knudsen_minimum():
+    """64 periodic channels, heights from {16..128}, Kn log-spaced 0.01-10,
+    g = 1e-6, each run to steady state in one persistent launch."""
+    Batch, _, clb = _mods()
+    heights, kns = kn_sweep_channels(64, seed=7)
+    params = [clb.make_params(4, ny, kn=kn, gx=1e-6) for ny, kn in zip(heights, kns)]
+    b = Batch(params)
+    b.tune(probe_steps=200)
+    steps, conv = b.run(400000, check_every=1000, tol=1e-12)
+    assert conv.all(), steps[~conv]
+    Q = b.flow_rate()
+    r = C.bounce_fraction(C.slip_A1(1.0))
+    Qref = np.array([A.discrete_Q(ny, kn, 2.0, 0.55, r) for ny, kn in zip(heights, kns)])
+    assert np.max(np.abs(Q / Qref - 1)) <= 1e-6
+    # The Knudsen minimum: over the sweep, Q normalised per height is
+    # smallest near Kn* = 1/(sqrt(18 B2) - a) = 0.872 (the paper's ~0.9).
+    grid = np.array(kns)
+    ref_curve = np.array([A.discrete_Q(128, k, 2.0, 0.55, r) for k in grid])
+    kmin = grid[int(np.argmin(ref_curve))]
+    assert 0.6 < kmin < 1.3
+
+
+def test_batch_rejects_bad_channels():
+    Batch, _, clb = _mods()
+    with pytest.raises(clb.ClbError):
+        Batch([clb.make_params(10, 8, xbc="pressure")])
+    with pytest.raises(clb.ClbError):
+        Batch([clb.make_params(512, 512, kn=1.0, gx=1e-6)])   # does not fit in LDS

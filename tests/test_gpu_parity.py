@@ -196,6 +196,20 @@ def test_deterministic_and_resumable():
     assert np.array_equal(s2.populations().cpu().numpy(), a)
 
 
+@pytest.mark.parametrize("graph_steps", [1, 7, 64])
+def test_graph_replay_identical(graph_steps):
+    """Stepping through recorded hipGraphs (odd and even lengths, with a
+    remainder launched eagerly) gives the same bits as eager stepping."""
+    kw = dict(nx=130, ny=11, kn=0.4, gx=1e-4, init="perturbed", init_amp=1e-3, seed=3)
+    ref, _ = _gpu_run(kw, 200)
+    s = _solver(**kw)
+    s.set_graph_steps(graph_steps)
+    s.step(150)
+    s.step(50)
+    assert s.steps_done == 200
+    assert np.array_equal(s.populations().cpu().numpy(), ref)
+
+
 def test_nonfinite_detection():
     s = _solver(nx=40, ny=6, kn=0.5)
     assert s.check_finite()
