@@ -29,6 +29,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched Kn-sweep comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--block-x", type=int, default=1024)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -132,6 +133,51 @@ def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12):
     }
 
 
+def adjoint_calibration(T=2000, K=45, repeats=3):
+    """Adjoint of the long pressure-driven channel (L/H = 100, 2000 x 20,
+    p_in/p_out = 2, Kn_out = 0.1) over T steps with K-step checkpoints: the
+    target (dp*, m*) comes from the same run with theta* = theta0 (1 + 0.05 xi),
+    xi ~ N(0, 1) seeded 2024, over theta = (a, A1, A2, r).  Times the forward
+    run (with checkpoints and loss) and the backward sweep (recompute + reverse)."""
+    import numpy as np
+    import torch
+    from paper_1603_01955_amd import Adjoint, clb
+
+    A1 = 1.0 - 0.1817          # sigma = 1 (Section 3)
+    r0 = 1.0 / (1.0 + A1 * np.sqrt(np.pi / 6.0))
+    theta0 = np.array([2.0, A1, 0.55, r0])
+    xi = np.random.default_rng(2024).standard_normal(4)
+    star = theta0 * (1.0 + 0.05 * xi)
+
+    def params(th):
+        return clb.make_params(2000, 20, xbc="pressure", kn=0.1, p_ratio=2.0,
+                               a=th[0], A1=th[1], A2=th[2], r=th[3])
+
+    tgt = Adjoint(params(star), T, K)
+    tgt.forward(torch.zeros(2000, dtype=torch.float64), 1.0)
+    dps, ms = tgt.observables()
+    tgt.close()
+    adj = Adjoint(params(theta0), T, K)
+    adj.forward(dps, ms)          # warm-up (first launches, graph-free)
+    adj.backward()
+    tf, tb = [], []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = adj.forward(dps, ms)             # synchronises
+        t1 = time.perf_counter()
+        g = adj.backward()                      # synchronises
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t2 - t1)
+    adj.close()
+    f, b = min(tf), min(tb)
+    return {"workload": "long_2000x20", "T": T, "K": K, "loss": loss,
+            "grad": {"a": g[0], "A1": g[1], "A2": g[2], "r": g[3]},
+            "forward_s": round(f, 4), "backward_s": round(b, 4),
+            "backward_over_forward": round(b / f, 3)}
+
+
 def cpu_baseline():
     """The CPU reference, as it stands, on a bounded sample of the workload:
     CPU_SAMPLE_STEPS steps of a 32768 x CPU_SAMPLE_ROWS slab of the same
@@ -211,6 +257,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_sweep:
         rec["kn_sweep"] = kn_sweep()
+    if not args.no_adjoint:
+        rec["adjoint"] = adjoint_calibration()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec), flush=True)

@@ -231,6 +231,58 @@ clb_status clb_batch_reset(clb_batch* b);
 /* Release the host context (synchronises the stream first). */
 clb_status clb_batch_destroy(clb_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Differentiation: hand-written adjoint of the pressure-driven run (Section
+ * 3.2).  A run is T steps from the start of *p (normally the linear-density
+ * start, CLB_INIT_LINEAR_RHO); its loss is
+ *   L = (1/nx) sum_x (dp(x) - dp*(x))^2 + ((m - m*) / m*)^2
+ * with dp the centre-line pressure deviation (as clb_pressure_deviation) and
+ * m = sum_y rho u_x at the outlet column x = nx - 1, both of the state after T
+ * steps.  Gradients are taken with respect to the Bosanquet factor a
+ * (Eq. 16, through Eq. 18 and the local Kn), the second-order slip
+ * coefficient A2 = B2 (Eq. 21), the bounce-back fraction r (Eq. 20), and A1
+ * (Eq. 21, which enters only through r).  The forward run keeps ceil(T/K)
+ * checkpoints; the backward sweep recomputes each K-step segment from its
+ * checkpoint (K ~ sqrt(T) balances memory and recompute).
+ * ------------------------------------------------------------------------- */
+typedef struct clb_adjoint clb_adjoint;
+
+/* Device workspace for T steps with checkpoints every K steps (pressure mode
+ * only; ceil(T/K) + max(K, 2) + 4 population buffers plus small arrays). */
+clb_status clb_adjoint_workspace_size(const clb_params* p, int32_t T, int32_t K, size_t* bytes);
+
+clb_status clb_adjoint_init(const clb_params* p, int32_t T, int32_t K, void* d_workspace, size_t bytes,
+                            void* hip_stream, clb_adjoint** out);
+
+/* Run the T forward steps from the start of *p, keep the checkpoints, and
+ * evaluate the loss against d_dp_target[nx] (device) and m_target (!= 0).
+ * *h_loss (host, may be NULL; synchronises). */
+clb_status clb_adjoint_forward(clb_adjoint* a, const double* d_dp_target, double m_target, double* h_loss);
+
+/* Backward sweep after clb_adjoint_forward.  h_grad[4] (host):
+ *   [0] dL/da, [1] dL/dA1, [2] dL/dA2, [3] dL/dr,
+ * where [3] treats r as an independent parameter and [1] is dL/dr * dr/dA1
+ * (dr/dA1 = -sqrt(pi/6) r^2) when r is derived from A1 (p->r NaN), else 0.
+ * Synchronises. */
+clb_status clb_adjoint_backward(clb_adjoint* a, double* h_grad);
+
+/* Observables of the final state: d_dp[nx] (device, may be NULL) and the
+ * outlet mass flow *h_m (host, may be NULL; synchronises). */
+clb_status clb_adjoint_observables(clb_adjoint* a, double* d_dp, double* h_m);
+
+/* Post-collision populations after the T forward steps, [9][ny][nx] (device). */
+clb_status clb_adjoint_final_state(clb_adjoint* a, double* d_out);
+
+/* One reverse step for an arbitrary state: given P_n and lambda_{n+1} (both
+ * [9][ny][nx], device), write lambda_n = (dP_{n+1}/dP_n)^T lambda_{n+1} and
+ * h_grad3 = lambda_{n+1} . dP_{n+1}/d(a, A2, r) (host, may be NULL).
+ * Does not disturb a completed forward run. */
+clb_status clb_adjoint_vjp_step(clb_adjoint* a, const double* d_P, const double* d_lam_next, double* d_lam_prev,
+                                double* h_grad3);
+
+/* Release the host context (synchronises the stream first). */
+clb_status clb_adjoint_destroy(clb_adjoint* a);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* clb_last_error(void);
 
