@@ -37,7 +37,7 @@ def hipcc():
 
 # Sources that define the single-channel step kernels (ties recorded
 # profile data to the kernel version it was measured on).
-STEP_SOURCES = ["clb_device.hpp", "clb_internal.hpp", "clb_kernels.hip"]
+STEP_SOURCES = ["clb_device.hpp", "clb_gather.hpp", "clb_internal.hpp", "clb_kernels.hip"]
 
 
 def source_hash(names=STEP_SOURCES):

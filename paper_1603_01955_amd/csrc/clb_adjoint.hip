@@ -12,13 +12,14 @@
 // One step is P' = C(G(P; r); s(x)) with G the gather (streaming, walls,
 // ghost columns) and s(x) = (s_nu, s_q) from rho_c(x) of the same gathered
 // state.  The reverse step for lambda' = dL/dP':
-//   k_adj_collide: recompute pre = G(P); lpre = (dC/dpre)^T lambda' per
-//     node; per column, the rate sensitivities flow through
-//     s(tau(Kn(rho_c))) back into lpre at the centre rows and into dL/da,
-//     dL/dA2; wall rows add lpre . dpre/dr to dL/dr.
-//   k_adj_gather: lambda = G^T lpre as a pull over the uses of each P_i(x, y)
-//     (regular streaming, the CBBSR mixes, the reverse of the ghost
-//     extrapolation at the first two and last two columns).
+//   lambda' = G^T lpre' as a pull over the uses of each P'_i(x, y) (regular
+//     streaming, the CBBSR mixes, the reverse of the ghost extrapolation at
+//     the first two and last two columns), evaluated on the fly;
+//   lpre = (dC/dpre)^T lambda' at pre = G(P) per node; per column the rate
+//     sensitivities flow through s(tau(Kn(rho_c))) back into lpre at the
+//     centre rows and into dL/da, dL/dA2; wall rows add lpre . dpre/dr to
+//     dL/dr.
+// Both halves run in one kernel per reverse step (k_adj_step).
 // The forward run keeps ceil(T/K) checkpoints; the backward sweep recomputes
 // each segment of K steps from its checkpoint and then reverses it.
 #include <hip/hip_runtime.h>
@@ -36,14 +37,21 @@
 namespace clb {
 namespace {
 
-constexpr int AX = 64;   // columns per block
-constexpr int AY = 4;    // row lanes per block
+// Column blocks of 256 threads: (256 / RY) columns x RY row lanes, RY the
+// smallest of 16, 32, 64 covering ny (one node per thread up to ny = 64).
+inline int adj_rows(int ny) { return ny <= 16 ? 16 : (ny <= 32 ? 32 : 64); }
+
+// Largest ny whose ghost columns and their reverse ([6][9][ny] doubles) are
+// staged in LDS by the edge workgroups of the reverse step.
+constexpr int kAdjGhostLdsMaxNy = 256;
 
 struct AdjArgs {
   const double* P;       // state P_n (device layout)
-  const double* lam;     // lambda_{n+1} (device layout)
-  double* lpre;          // lpre (device layout)
-  double* out;           // lambda_n (device layout)
+  const double* Pn1;     // state P_{n+1} (ghost reverse of the pulled adjoint)
+  const double* lam;     // lambda_{n+1} (device layout), when not pulled
+  const double* lin;     // lpre_{n+1}, pulled through the transposed gather
+  double* lpre;          // lpre_n out (device layout); k_adj_gather reads it
+  double* out;           // lambda_n (device layout), k_adj_gather
   double* gpart;         // [blocks][3] accumulated (da, dA2, dr)
   Geo g;
   int shift;
@@ -51,11 +59,8 @@ struct AdjArgs {
   double s3, s8;
   double kn, a, A2, tq_den, c_tau;
   double rho_in, rho_out;
+  int ghost_lds;         // ghost columns staged in LDS by the edge workgroups
 };
-
-__device__ __forceinline__ double sum9(const double f[9]) {
-  return f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-}
 
 // lpre . d pre / d r for the wall-replaced entries of node (x, y) (Eq. 20).
 __device__ double wall_dr(const Gather<1, View>& gat, int x, int y, const double lp[9]) {
@@ -75,121 +80,74 @@ __device__ double wall_dr(const Gather<1, View>& gat, int x, int y, const double
   return dr;
 }
 
-// Reverse of the collision and of the local-Kn rates for one step.
-__global__ __launch_bounds__(AX * AY) void k_adj_collide(AdjArgs a) {
+// lambda(x, y) = (G^T lp)(x, y): the adjoint of P_i(x, y) gathered over its
+// uses in the gather G(P) (regular streaming, the CBBSR mixes of Eq. 20, and
+// the reverse of the ghost extrapolation at the first two / last two
+// columns, which needs P itself there).
+// Reverse of ghost row y (inlet or outlet): the adjoint reaching the ghost
+// populations from their uses in G(P), pushed back onto the two adjacent
+// columns (l1: the column next to the boundary, l2: the one after).
+__device__ __forceinline__ void ghost_row_vjp(const AdjArgs& a, const double* __restrict__ lp,
+                                              const double* __restrict__ P, bool inlet, int y, double l1[9],
+                                              double l2[9]) {
 #pragma clang fp contract(off)
-  __shared__ double s_nu[AX], s_q[AX], s_kn[AX], s_tt[AX], s_rc[AX];
-  __shared__ double r_nu[AY][AX], r_q[AY][AX], r_r[AY][AX];
-  __shared__ double c_a[AX], c_A2[AX], c_r[AX];
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * AX + tx;
+  const int nx = a.g.nx, t = a.g.ny - 1;
+  const double omr = 1.0 - a.r;
+  auto L = [&](int i, int xx, int yy) { return lp[a.g.index(i, xx, yy)]; };
+  const int c1 = inlet ? 0 : nx - 1, c2 = inlet ? 1 : nx - 2;
+  // ghost directions entering the channel: 1, 5, 8 at the inlet; 3, 6, 7 at the outlet
+  const int d0 = inlet ? 1 : 3, dup = inlet ? 5 : 6, ddn = inlet ? 8 : 7;
+  double lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  lg[d0] = L(d0, c1, y);
+  if (y + 1 <= t) lg[dup] += L(dup, c1, y + 1);
+  if (y == t && a.shift) lg[dup] += omr * L(inlet ? 8 : 7, c1, t);
+  if (y - 1 >= 0) lg[ddn] += L(ddn, c1, y - 1);
+  if (y == 0 && a.shift) lg[ddn] += omr * L(inlet ? 5 : 6, c1, 0);
+  double f1[9], f2[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    f1[i] = P[a.g.index(i, c1, y)];
+    f2[i] = P[a.g.index(i, c2, y)];
+    l1[i] = 0.0;
+    l2[i] = 0.0;
+  }
+  ghost_vjp(f1, f2, inlet ? a.rho_in : a.rho_out, lg, l1, l2);
+}
+
+// Edge workgroups: the reverse of every ghost row, one row per thread, into
+// gv[4][9][ny] (inlet l1, inlet l2, outlet l1, outlet l2).
+__device__ __forceinline__ void fill_ghost_vjp(const AdjArgs& a, const double* __restrict__ lp,
+                                               const double* __restrict__ P, bool need_in, bool need_out,
+                                               double* gv, int tid, int nthreads) {
   const int ny = a.g.ny;
-  const Gather<1, View> gat{{a.P, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
-  const int yc = ny / 2;
-  const bool even = (ny & 1) == 0;
-  if (ty == 0 && x < a.g.nx) {
-    double f[9];
-    gat(x, yc, f);
-    double rc = sum9(f);
-    if (even) {
-      gat(x, yc - 1, f);
-      rc = 0.5 * (sum9(f) + rc);
-    }
-    const double kn = a.kn * a.rho_out / rc;
-    const double tt = a.c_tau * kn / (1.0 + a.a * kn);
-    s_rc[tx] = rc;
-    s_kn[tx] = kn;
-    s_tt[tx] = tt;
-    s_nu[tx] = 1.0 / (0.5 + tt);
-    s_q[tx] = 1.0 / (0.5 + (3.0 + 4.0 * M_PI * tt * tt * a.A2) / (a.tq_den * tt));
-  }
-  __syncthreads();
-  double acc_nu = 0.0, acc_q = 0.0, acc_r = 0.0;
-  if (x < a.g.nx) {
-    const Rates s{a.s3, s_nu[tx], s_q[tx], a.s8};
-    for (int y = ty; y < ny; y += AY) {
-      double f[9], lo[9], lf[9];
-      gat(x, y, f);
-      const size_t base = a.g.index(0, x, y);
-      const size_t stride = (size_t)1 << a.g.lshift;
+  for (int y = tid; y < ny; y += nthreads) {
+    double l1[9], l2[9];
+    if (need_in) {
+      ghost_row_vjp(a, lp, P, true, y, l1, l2);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) lo[i] = a.lam[base + i * stride];
-      double lsnu, lsq;
-      collide_vjp(f, lo, s, lf, lsnu, lsq);
-      acc_nu += lsnu;
-      acc_q += lsq;
-      if (y == 0 || y == ny - 1) acc_r += wall_dr(gat, x, y, lf);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] = lf[i];
-    }
-  }
-  r_nu[ty][tx] = acc_nu;
-  r_q[ty][tx] = acc_q;
-  r_r[ty][tx] = acc_r;
-  __syncthreads();
-  if (ty == 0) {
-    double da = 0.0, dA2 = 0.0, dr = 0.0;
-    if (x < a.g.nx) {
-      double lnu = r_nu[0][tx], lq = r_q[0][tx];
-      for (int k = 1; k < AY; ++k) {
-        lnu += r_nu[k][tx];
-        lq += r_q[k][tx];
-      }
-      // s_nu = 1/(1/2 + tt);  s_q = 1/(1/2 + 3/(D tt) + 4 pi A2 tt / D)   (Eqs. 18, 21)
-      const double snu = s_nu[tx], sq = s_q[tx], tt = s_tt[tx], kn = s_kn[tx], rc = s_rc[tx];
-      const double D = a.tq_den;
-      const double l_tt = -snu * snu * lnu + (-sq * sq) * (4.0 * M_PI * a.A2 / D - 3.0 / (D * tt * tt)) * lq;
-      const double den = 1.0 + a.a * kn;
-      // tt = c_tau Kn / (1 + a Kn),  Kn = Kn_out rho_out / rho_c
-      const double dtt_dkn = a.c_tau / (den * den);
-      const double l_rc = l_tt * dtt_dkn * (-kn / rc);
-      da = l_tt * (-a.c_tau * kn * kn / (den * den));
-      dA2 = (-sq * sq) * (4.0 * M_PI * tt / D) * lq;
-      // rho_c = mean of the (one or two) centre rows of pre: spread l_rc back.
-      const double w = even ? 0.5 : 1.0;
-      double lp[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) lp[i] = w * l_rc;
-      const size_t stride = (size_t)1 << a.g.lshift;
-      for (int k = 0; k < (even ? 2 : 1); ++k) {
-        const int yy = yc - k;
-        const size_t base = a.g.index(0, x, yy);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] += lp[i];
-        if (yy == 0 || yy == ny - 1) dr += wall_dr(gat, x, yy, lp);
+      for (int i = 0; i < 9; ++i) {
+        gv[(0 * 9 + i) * ny + y] = l1[i];
+        gv[(1 * 9 + i) * ny + y] = l2[i];
       }
     }
-    c_a[tx] = da;
-    c_A2[tx] = dA2;
-    c_r[tx] = dr;
-  }
-  __syncthreads();
-  if (tx == 0 && ty == 0) {
-    double sa = 0.0, sA2 = 0.0, sr = 0.0;
-    for (int k = 0; k < AX; ++k) {
-      sa += c_a[k];
-      sA2 += c_A2[k];
-      sr += c_r[k];
+    if (need_out) {
+      ghost_row_vjp(a, lp, P, false, y, l1, l2);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        gv[(2 * 9 + i) * ny + y] = l1[i];
+        gv[(3 * 9 + i) * ny + y] = l2[i];
+      }
     }
-    for (int j = 0; j < AY; ++j)
-      for (int k = 0; k < AX; ++k) sr += r_r[j][k];
-    double* gp = a.gpart + 3 * blockIdx.x;
-    gp[0] += sa;
-    gp[1] += sA2;
-    gp[2] += sr;
   }
 }
 
-// lambda_n = G^T lpre (+ reverse of the ghost columns), one thread per node.
-__global__ __launch_bounds__(256) void k_adj_gather(AdjArgs a) {
+__device__ __forceinline__ void transposed_gather(const AdjArgs& a, const double* __restrict__ lp,
+                                                  const double* __restrict__ P, int x, int y, double out[9],
+                                                  const double* gv = nullptr) {
 #pragma clang fp contract(off)
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
   const int nx = a.g.nx, ny = a.g.ny, t = ny - 1;
-  if (x >= nx) return;
   const double r = a.r, omr = 1.0 - a.r;
-  auto L = [&](int i, int xx, int yy) { return a.lpre[a.g.index(i, xx, yy)]; };
-  double out[9];
+  auto L = [&](int i, int xx, int yy) { return lp[a.g.index(i, xx, yy)]; };
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int ex = ex_of(i), ey = ey_of(i);
@@ -224,43 +182,210 @@ __global__ __launch_bounds__(256) void k_adj_gather(AdjArgs a) {
     }
     out[i] = acc;
   }
-  // Reverse of the ghost columns: inlet ghost row y is built from columns 0, 1.
+  // Reverse of the ghost columns (pressure mode): the inlet ghost row y is
+  // built from columns 0, 1, the outlet one from nx - 1, nx - 2.
   if (x <= 1) {
-    double lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    lg[1] = L(1, 0, y);
-    if (y + 1 <= t) lg[5] += L(5, 0, y + 1);
-    if (y == t && a.shift) lg[5] += omr * L(8, 0, t);
-    if (y - 1 >= 0) lg[8] += L(8, 0, y - 1);
-    if (y == 0 && a.shift) lg[8] += omr * L(5, 0, 0);
-    double f1[9], f2[9], l1[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, l2[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (gv) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      f1[i] = a.P[a.g.index(i, 0, y)];
-      f2[i] = a.P[a.g.index(i, 1, y)];
+      for (int i = 0; i < 9; ++i) out[i] += gv[(x * 9 + i) * ny + y];
+    } else {
+      double l1[9], l2[9];
+      ghost_row_vjp(a, lp, P, true, y, l1, l2);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) out[i] += (x == 0) ? l1[i] : l2[i];
     }
-    ghost_vjp(f1, f2, a.rho_in, lg, l1, l2);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) out[i] += (x == 0) ? l1[i] : l2[i];
   }
-  // Outlet ghost row y is built from columns nx - 1, nx - 2.
   if (x >= nx - 2) {
-    const int c1 = nx - 1;
-    double lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    lg[3] = L(3, c1, y);
-    if (y + 1 <= t) lg[6] += L(6, c1, y + 1);
-    if (y == t && a.shift) lg[6] += omr * L(7, c1, t);
-    if (y - 1 >= 0) lg[7] += L(7, c1, y - 1);
-    if (y == 0 && a.shift) lg[7] += omr * L(6, c1, 0);
-    double f1[9], f2[9], l1[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, l2[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int c = nx - 1 - x;   // 0: adjacent column, 1: the next one
+    if (gv) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      f1[i] = a.P[a.g.index(i, c1, y)];
-      f2[i] = a.P[a.g.index(i, nx - 2, y)];
+      for (int i = 0; i < 9; ++i) out[i] += gv[((2 + c) * 9 + i) * ny + y];
+    } else {
+      double l1[9], l2[9];
+      ghost_row_vjp(a, lp, P, false, y, l1, l2);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) out[i] += (c == 0) ? l1[i] : l2[i];
     }
-    ghost_vjp(f1, f2, a.rho_out, lg, l1, l2);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) out[i] += (x == c1) ? l1[i] : l2[i];
   }
+}
+
+// One reverse step n.  lambda_{n+1}(x, y) is either pulled on the fly from
+// lpre_{n+1} (PULL: the transposed gather of step n + 1, ghosts at P_{n+1})
+// or read from a.lam.  Then lpre_n = (dC/dpre_n)^T lambda_{n+1} at
+// pre_n = G(P_n), the rate sensitivities of each column flow through
+// s(tau(Kn(rho_c))) into lpre_n at the centre rows and into dL/da, dL/dA2,
+// and wall rows add lpre . dpre/dr to dL/dr.  Up to ny = RY each thread owns
+// one node and keeps it in registers across the column reductions.
+template <int RY, bool PULL>
+__global__ __launch_bounds__(256) void k_adj_step(AdjArgs a) {
+#pragma clang fp contract(off)
+  constexpr int CX = 256 / RY;
+  __shared__ double s_rcr[2][CX];
+  __shared__ double r_nu[RY][CX], r_q[RY][CX], r_r[RY][CX];
+  __shared__ double c_lrc[CX], c_a[CX], c_A2[CX], c_r[CX];
+  // first / last workgroup: ghost columns of P_n [2][9][ny], then (PULL)
+  // the reverse of the ghost rows of P_{n+1} [4][9][ny]
+  extern __shared__ double s_dyn[];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int x = blockIdx.x * CX + tx;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const View v{a.P, a.g};
+  const bool edge_in = a.ghost_lds && blockIdx.x == 0;
+  const bool edge_out = a.ghost_lds && blockIdx.x == gridDim.x - 1;
+  double* s_ghost = s_dyn;
+  double* s_gv = s_dyn + 18 * ny;
+  if (edge_in || edge_out) {
+    const int tid = ty * CX + tx;
+    if (tid < 128)
+      fill_ghosts(v, a.rho_in, a.rho_out, edge_in, edge_out, s_ghost, s_ghost + 9 * ny, tid, 128);
+    else if (PULL)
+      fill_ghost_vjp(a, a.lin, a.Pn1, edge_in, edge_out, s_gv, tid - 128, 128);
+  }
+  __syncthreads();
+  const double* gv = (PULL && (edge_in || edge_out)) ? s_gv : nullptr;
+  const Gather<1, View> gat{v, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out, edge_in ? s_ghost : nullptr,
+                            edge_out ? s_ghost + 9 * ny : nullptr};
+  const int yc = ny / 2;
+  const bool even = (ny & 1) == 0;
+  const size_t stride = (size_t)1 << a.g.lshift;
+  const bool one = ny <= RY;   // one node per thread
+  double f[9], lo[9];
+  bool active = false;
+  if (one) {
+    active = x < nx && ty < ny;
+    if (active) {
+      gat(x, ty, f);
+      if (PULL) {
+        transposed_gather(a, a.lin, a.Pn1, x, ty, lo, gv);
+      } else {
+        const size_t base = a.g.index(0, x, ty);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lo[i] = a.lam[base + i * stride];
+      }
+      if (ty == yc) s_rcr[0][tx] = sum9(f);
+      if (even && ty == yc - 1) s_rcr[1][tx] = sum9(f);
+    }
+  } else if (ty < 2 && x < nx && (ty == 0 || even)) {
+    double g[9];
+    gat(x, yc - ty, g);
+    s_rcr[ty][tx] = sum9(g);
+  }
+  __syncthreads();
+  double snu = 0.0, sq = 0.0, kn = 0.0, tt = 0.0, rc = 1.0;
+  if (x < nx) {
+    rc = even ? 0.5 * (s_rcr[1][tx] + s_rcr[0][tx]) : s_rcr[0][tx];
+    local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq, kn, tt);
+  }
+  const Rates s{a.s3, snu, sq, a.s8};
+  double acc_nu = 0.0, acc_q = 0.0, acc_r = 0.0;
+  double lf[9];
+  bool hold = false;   // this thread's centre-row lpre waits for the rate correction
+  if (one) {
+    if (active) {
+      double lsnu, lsq;
+      collide_vjp(f, lo, s, lf, lsnu, lsq);
+      acc_nu = lsnu;
+      acc_q = lsq;
+      if (ty == 0 || ty == ny - 1) acc_r = wall_dr(gat, x, ty, lf);
+      hold = ty == yc || (even && ty == yc - 1);
+      if (!hold) {
+        const size_t base = a.g.index(0, x, ty);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] = lf[i];
+      }
+    }
+  } else if (x < nx) {
+    for (int y = ty; y < ny; y += RY) {
+      double g[9], l[9], lg[9];
+      gat(x, y, g);
+      const size_t base = a.g.index(0, x, y);
+      if (PULL) {
+        transposed_gather(a, a.lin, a.Pn1, x, y, l, gv);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) l[i] = a.lam[base + i * stride];
+      }
+      double lsnu, lsq;
+      collide_vjp(g, l, s, lg, lsnu, lsq);
+      acc_nu += lsnu;
+      acc_q += lsq;
+      if (y == 0 || y == ny - 1) acc_r += wall_dr(gat, x, y, lg);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] = lg[i];
+    }
+  }
+  r_nu[ty][tx] = acc_nu;
+  r_q[ty][tx] = acc_q;
+  r_r[ty][tx] = acc_r;
+  __syncthreads();
+  const double w = even ? 0.5 : 1.0;
+  if (ty == 0) {
+    double da = 0.0, dA2 = 0.0, dr = 0.0, l_rc = 0.0;
+    if (x < nx) {
+      double lnu = r_nu[0][tx], lq = r_q[0][tx];
+      dr = r_r[0][tx];
+      for (int k = 1; k < RY; ++k) {
+        lnu += r_nu[k][tx];
+        lq += r_q[k][tx];
+        dr += r_r[k][tx];
+      }
+      // s_nu = 1/(1/2 + tt);  s_q = 1/(1/2 + 3/(D tt) + 4 pi A2 tt / D)   (Eqs. 18, 21)
+      const double D = a.tq_den;
+      const double l_tt = -snu * snu * lnu + (-sq * sq) * (4.0 * M_PI * a.A2 / D - 3.0 / (D * tt * tt)) * lq;
+      const double den = 1.0 + a.a * kn;
+      // tt = c_tau Kn / (1 + a Kn),  Kn = Kn_out rho_out / rho_c
+      const double dtt_dkn = a.c_tau / (den * den);
+      l_rc = l_tt * dtt_dkn * (-kn / rc);
+      da = l_tt * (-a.c_tau * kn * kn / (den * den));
+      dA2 = (-sq * sq) * (4.0 * M_PI * tt / D) * lq;
+      // rho_c = mean of the centre rows of pre: l_rc reaches every population
+      // there; centre rows that are wall rows also carry an r dependence.
+      double lp[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lp[i] = w * l_rc;
+      for (int k = 0; k < (even ? 2 : 1); ++k) {
+        const int yy = yc - k;
+        if (yy == 0 || yy == ny - 1) dr += wall_dr(gat, x, yy, lp);
+        if (!one) {
+          const size_t base = a.g.index(0, x, yy);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] += lp[i];
+        }
+      }
+    }
+    c_lrc[tx] = l_rc;
+    c_a[tx] = da;
+    c_A2[tx] = dA2;
+    c_r[tx] = dr;
+  }
+  __syncthreads();
+  if (hold) {
+    const double add = w * c_lrc[tx];
+    const size_t base = a.g.index(0, x, ty);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] = lf[i] + add;
+  }
+  if (tx == 0 && ty == 0) {
+    double sa = 0.0, sA2 = 0.0, sr = 0.0;
+    for (int k = 0; k < CX; ++k) {
+      sa += c_a[k];
+      sA2 += c_A2[k];
+      sr += c_r[k];
+    }
+    double* gp = a.gpart + 3 * blockIdx.x;
+    gp[0] += sa;
+    gp[1] += sA2;
+    gp[2] += sr;
+  }
+}
+
+// lambda_n = G^T lpre (+ reverse of the ghost columns), one thread per node.
+__global__ __launch_bounds__(256) void k_adj_gather(AdjArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= a.g.nx) return;
+  double out[9];
+  transposed_gather(a, a.lpre, a.P, x, y, out);
 #pragma unroll
   for (int i = 0; i < 9; ++i) a.out[a.g.index(i, x, y)] = out[i];
 }
@@ -387,7 +512,9 @@ struct clb_adjoint {
   double* dpt;             // [nx] target dp*
   double* scal;            // [16]: loss, m - m*, m, grads
   int nblk;
-  hipStream_t stream;
+  hipStream_t stream;      // caller's stream: forward run and reverse sweep
+  hipStream_t rstream;     // private stream: checkpoint recompute of the next segment
+  hipEvent_t ev_start, ev_ready[2], ev_free[2];
   double m_target;
   int forward_done;
   double host_scal[8];
@@ -405,8 +532,10 @@ AdjLayout adj_layout(const clb_params* p, int32_t T, int32_t K) {
   const clb::Geo g = clb::make_geo(p->nx, p->ny);
   L.S = g.size();
   L.nck = (T + K - 1) / K;
-  L.nseg = K < 2 ? 2 : K;
-  L.nblk = (p->nx + clb::AX - 1) / clb::AX;
+  // two sets of K - 1 recompute buffers (segment s recomputes while s + 1 reverses)
+  L.nseg = 2 * (K - 1) < 2 ? 2 : 2 * (K - 1);
+  const int cx = 256 / clb::adj_rows(p->ny);
+  L.nblk = (p->nx + cx - 1) / cx;
   const size_t buf = clb::align256(L.S * sizeof(double));
   const size_t col = clb::align256((size_t)p->nx * sizeof(double));
   L.total = ((size_t)L.nck + (size_t)L.nseg + 4) * buf + 7 * col + clb::align256((size_t)L.nblk * 3 * sizeof(double)) +
@@ -437,12 +566,10 @@ clb::StepArgs adj_step_args(const clb_adjoint* a, const double* src, double* dst
   return s;
 }
 
-clb::AdjArgs adj_args(const clb_adjoint* a, const double* P, const double* lam, double* out) {
+clb::AdjArgs adj_args(const clb_adjoint* a, const double* P, double* lpre) {
   clb::AdjArgs r{};
   r.P = P;
-  r.lam = lam;
-  r.lpre = a->lpre;
-  r.out = out;
+  r.lpre = lpre;
   r.gpart = a->gpart;
   r.g = a->g;
   r.shift = a->p.cbbsr_shift;
@@ -456,22 +583,61 @@ clb::AdjArgs adj_args(const clb_adjoint* a, const double* P, const double* lam, 
   r.c_tau = std::sqrt(6.0 / M_PI) * (double)a->p.ny;
   r.rho_in = a->p.p_ratio * a->p.rho_out;
   r.rho_out = a->p.rho_out;
+  r.ghost_lds = a->p.ny <= clb::kAdjGhostLdsMaxNy ? 1 : 0;
   return r;
 }
 
-clb_status step(clb_adjoint* a, const double* src, double* dst) {
+clb_status step(clb_adjoint* a, const double* src, double* dst, hipStream_t st) {
   const clb::StepArgs s = adj_step_args(a, src, dst);
-  ADJ_HIP(clb::launch_step(s, 256, a->stream));
+  ADJ_HIP(clb::launch_step(s, 256, st));
   return CLB_OK;
 }
 
-clb_status reverse_step(clb_adjoint* a, const double* P, const double* lam_next, double* lam_out) {
-  const clb::AdjArgs r = adj_args(a, P, lam_next, lam_out);
-  clb::k_adj_collide<<<a->nblk, dim3(clb::AX, clb::AY), 0, a->stream>>>(r);
-  const dim3 grid((unsigned)((a->g.nx + 255) / 256), (unsigned)a->g.ny);
-  clb::k_adj_gather<<<grid, 256, 0, a->stream>>>(r);
+clb_status step(clb_adjoint* a, const double* src, double* dst) { return step(a, src, dst, a->stream); }
+
+// State n of segment s when its recompute uses buffer set `set`.
+double* seg_state(clb_adjoint* a, int s, int set, int n) {
+  const int start = s * a->K;
+  if (n == start) return a->ck + (size_t)s * a->S;
+  return a->seg + ((size_t)set * (size_t)(a->K - 1) + (size_t)(n - start - 1)) * a->S;
+}
+
+// Recompute the states of segment s from its checkpoint on the private
+// stream, then mark buffer set `set` ready.
+clb_status recompute(clb_adjoint* a, int s, int set) {
+  const int start = s * a->K;
+  const int end = (start + a->K < a->T) ? start + a->K : a->T;
+  for (int n = start; n + 1 < end; ++n) {
+    clb_status st = step(a, seg_state(a, s, set, n), seg_state(a, s, set, n + 1), a->rstream);
+    if (st != CLB_OK) return st;
+  }
+  ADJ_HIP(hipEventRecord(a->ev_ready[set], a->rstream));
+  return CLB_OK;
+}
+
+template <bool PULL>
+clb_status launch_adj_step(clb_adjoint* a, const clb::AdjArgs& r) {
+  // ghost columns [2][9][ny] plus, when pulling, their reverse [4][9][ny]
+  const size_t lds = r.ghost_lds ? (PULL ? 54 : 18) * (size_t)a->p.ny * sizeof(double) : 0;
+  const int ry = clb::adj_rows(a->p.ny), cx = 256 / ry;
+  if (ry == 16)
+    clb::k_adj_step<16, PULL><<<a->nblk, dim3(cx, ry), lds, a->stream>>>(r);
+  else if (ry == 32)
+    clb::k_adj_step<32, PULL><<<a->nblk, dim3(cx, ry), lds, a->stream>>>(r);
+  else
+    clb::k_adj_step<64, PULL><<<a->nblk, dim3(cx, ry), lds, a->stream>>>(r);
   ADJ_HIP(hipGetLastError());
   return CLB_OK;
+}
+
+// Reverse step n of the sweep: lpre_n from lpre_{n+1} (pulled, ghosts at
+// P_{n+1}) and the state P_n.
+clb_status reverse_step(clb_adjoint* a, const double* Pn, const double* Pn1, const double* lpre_next,
+                        double* lpre_out) {
+  clb::AdjArgs r = adj_args(a, Pn, lpre_out);
+  r.Pn1 = Pn1;
+  r.lin = lpre_next;
+  return launch_adj_step<true>(a, r);
 }
 
 // Observables and loss of the state P (pre-collision at its time level).
@@ -555,11 +721,19 @@ clb_status clb_adjoint_init(const clb_params* p, int32_t T, int32_t K, void* d_w
   a->scal = reinterpret_cast<double*>(q);
   a->stream = static_cast<hipStream_t>(hip_stream);
   a->forward_done = 0;
+  hipError_t e = hipStreamCreateWithFlags(&a->rstream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&a->ev_start, hipEventDisableTiming);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&a->ev_ready[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&a->ev_free[k], hipEventDisableTiming);
+  }
   // Padding lanes of every buffer are never read, but start them at zero.
-  clb::k_fill<<<1024, 256, 0, a->stream>>>(reinterpret_cast<double*>(d_workspace), need / sizeof(double), 0.0);
-  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    clb::k_fill<<<1024, 256, 0, a->stream>>>(reinterpret_cast<double*>(d_workspace), need / sizeof(double), 0.0);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) {
-    delete a;
+    clb_adjoint_destroy(a);
     return clb::set_error(CLB_EHIP, hipGetErrorString(e));
   }
   *out = a;
@@ -617,28 +791,41 @@ clb_status clb_adjoint_backward(clb_adjoint* a, double* h_grad) {
   clb::k_fill<<<1, 256, 0, a->stream>>>(a->gpart, (size_t)a->nblk * 3, 0.0);
   // lambda_T = G^T dL/dpre_T
   const dim3 grid((unsigned)((a->g.nx + 255) / 256), (unsigned)a->g.ny);
+  // lpre of the final gather (the loss seed); lpre buffers alternate between
+  // a->lpre and a->lam[0] through the sweep.
+  double* lbuf[2] = {a->lpre, a->lam[0]};
   {
-    const clb::AdjArgs r = adj_args(a, a->pT, nullptr, a->lam[0]);
+    const clb::AdjArgs r = adj_args(a, a->pT, lbuf[0]);
     double* dr_wall = a->col + 4 * a->p.nx;   // 2 * nx entries (bottom, top)
     clb::k_fill<<<1, 256, 0, a->stream>>>(dr_wall, 2 * (size_t)a->p.nx, 0.0);
     clb::k_adj_seed<<<grid, 256, 0, a->stream>>>(r, a->col + 3 * a->p.nx, a->scal, a->m_target, dr_wall);
     clb::k_adj_seed_dr<<<1, 256, 0, a->stream>>>(dr_wall, 2 * a->p.nx, a->gpart);
-    clb::k_adj_gather<<<grid, 256, 0, a->stream>>>(r);
   }
   ADJ_HIP(hipGetLastError());
-  int cur = 0;   // lam[cur] holds lambda_{n+1}
+  // Segments are reversed from the last to the first.  The recompute of
+  // segment s - 1 (private stream, buffer set (s - 1) & 1) overlaps the
+  // reverse sweep of segment s (caller's stream, set s & 1); events order a
+  // set's reuse after the sweep that read it.
+  ADJ_HIP(hipEventRecord(a->ev_start, a->stream));
+  ADJ_HIP(hipStreamWaitEvent(a->rstream, a->ev_start, 0));
+  if ((st = recompute(a, a->nck - 1, (a->nck - 1) & 1)) != CLB_OK) return st;
+  int cur = 0;   // lbuf[cur] holds lpre_{n+1}
   for (int s = a->nck - 1; s >= 0; --s) {
+    const int set = s & 1;
+    if (s >= 1) {
+      if (s + 1 <= a->nck - 1) ADJ_HIP(hipStreamWaitEvent(a->rstream, a->ev_free[(s - 1) & 1], 0));
+      if ((st = recompute(a, s - 1, (s - 1) & 1)) != CLB_OK) return st;
+    }
+    ADJ_HIP(hipStreamWaitEvent(a->stream, a->ev_ready[set], 0));
     const int start = s * a->K;
     const int end = (start + a->K < a->T) ? start + a->K : a->T;
-    auto buf = [&](int n) -> double* {
-      return n == start ? a->ck + (size_t)s * a->S : a->seg + (size_t)(n - start - 1) * a->S;
-    };
-    for (int n = start; n + 1 < end; ++n)
-      if ((st = step(a, buf(n), buf(n + 1))) != CLB_OK) return st;
     for (int n = end - 1; n >= start; --n) {
-      if ((st = reverse_step(a, buf(n), a->lam[cur], a->lam[cur ^ 1])) != CLB_OK) return st;
+      const double* Pn1 = n + 1 < end ? seg_state(a, s, set, n + 1)
+                                      : (end == a->T ? a->pT : a->ck + (size_t)(s + 1) * a->S);
+      if ((st = reverse_step(a, seg_state(a, s, set, n), Pn1, lbuf[cur], lbuf[cur ^ 1])) != CLB_OK) return st;
       cur ^= 1;
     }
+    ADJ_HIP(hipEventRecord(a->ev_free[set], a->stream));
   }
   clb::k_adj_grad_sum<<<1, 64, 0, a->stream>>>(a->gpart, a->nblk, a->scal + 4);
   ADJ_HIP(hipGetLastError());
@@ -694,8 +881,16 @@ clb_status clb_adjoint_vjp_step(clb_adjoint* a, const double* d_P, const double*
   ADJ_HIP(clb::launch_import(d_P, a->g, P, a->stream));
   ADJ_HIP(clb::launch_import(d_lam_next, a->g, lam, a->stream));
   clb::k_fill<<<1, 256, 0, a->stream>>>(a->gpart, (size_t)a->nblk * 3, 0.0);
-  if ((st = reverse_step(a, P, lam, a->lam[0])) != CLB_OK) return st;
-  ADJ_HIP(clb::launch_export(a->lam[0], a->g, d_lam_prev, a->stream));
+  {
+    clb::AdjArgs r = adj_args(a, P, a->lpre);
+    r.lam = lam;
+    if ((st = launch_adj_step<false>(a, r)) != CLB_OK) return st;
+    r.out = a->lam[1];
+    const dim3 grid((unsigned)((a->g.nx + 255) / 256), (unsigned)a->g.ny);
+    clb::k_adj_gather<<<grid, 256, 0, a->stream>>>(r);
+    ADJ_HIP(hipGetLastError());
+  }
+  ADJ_HIP(clb::launch_export(a->lam[1], a->g, d_lam_prev, a->stream));
   clb::k_adj_grad_sum<<<1, 64, 0, a->stream>>>(a->gpart, a->nblk, a->scal + 4);
   ADJ_HIP(hipGetLastError());
   if (h_grad3) {
@@ -711,6 +906,13 @@ clb_status clb_adjoint_vjp_step(clb_adjoint* a, const double* d_P, const double*
 clb_status clb_adjoint_destroy(clb_adjoint* a) {
   if (!a) return clb::set_error(CLB_EINVAL, "adjoint: NULL");
   (void)hipStreamSynchronize(a->stream);
+  if (a->rstream) (void)hipStreamSynchronize(a->rstream);
+  for (int k = 0; k < 2; ++k) {
+    if (a->ev_ready[k]) (void)hipEventDestroy(a->ev_ready[k]);
+    if (a->ev_free[k]) (void)hipEventDestroy(a->ev_free[k]);
+  }
+  if (a->ev_start) (void)hipEventDestroy(a->ev_start);
+  if (a->rstream) (void)hipStreamDestroy(a->rstream);
   delete a;
   return CLB_OK;
 }

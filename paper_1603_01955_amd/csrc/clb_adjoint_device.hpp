@@ -38,8 +38,7 @@ __device__ __forceinline__ void collide_vjp(const double f[9], const double lo[9
   const double c5 = rho * uxy - k_xy;
   const double c6 = 2.0 * rho * ux2 * uy + k_xxy - 2.0 * ux * k_xy - uy * k_xx;
   const double c7 = 2.0 * rho * ux * uy2 + k_xyy - 2.0 * uy * k_xy - ux * k_yy;
-  const double c8 = rho * (1.0 / 9.0) + 3.0 * rho * ux2 * uy2 -
-                    (diag - 2.0 * ux * k_xyy - 2.0 * uy * k_xxy + ux2 * k_yy + uy2 * k_xx + 4.0 * uxy * k_xy);
+  // (c8 itself is not needed: g8 enters the outputs linearly)
   const double g3 = s.s3 * (1.0 / 12.0) * c3;
   const double g4 = 0.25 * s.snu * c4;
   const double g5 = 0.25 * s.snu * c5;

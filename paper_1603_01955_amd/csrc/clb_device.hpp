@@ -1,8 +1,8 @@
 // Device-side building blocks of the D2Q9 cascaded LB step for gfx950.
 //
 // Method: Liu & He, arXiv:1603.01955, Section 2.  All arithmetic is FP64.
-// Populations are stored structure-of-arrays, P[i][y][x] with x fastest;
-// direction order as in Eq. (1).
+// These functions work on one node's nine populations in registers; the
+// memory layout belongs to the callers.  Direction order as in Eq. (1).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -133,6 +133,31 @@ __device__ __forceinline__ void equilibrium(double rho, double ux, double uy, do
   e[6] = rho * axm * ayp;
   e[7] = rho * axm * aym;
   e[8] = rho * axp * aym;
+}
+
+__device__ __forceinline__ double sum9(const double f[9]) {
+#pragma clang fp contract(off)
+  return f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+}
+
+// Relaxation rates of a column of the pressure-driven channel from its
+// centre-line density rc (Section 3.2): Kn = Kn_out rho_out / rho_c,
+// tt = s_nu^-1 - 1/2 = c_tau Kn / (1 + a Kn) with c_tau = sqrt(6/pi) N
+// (Eq. 18), s_q^-1 = 1/2 + (3 + 4 pi tt^2 A2) / (D tt) (Eq. 21).
+__device__ __forceinline__ void local_rates(double kn_out, double rho_out, double rc, double c_tau, double a,
+                                            double A2, double D, double& snu, double& sq, double& kn,
+                                            double& tt) {
+#pragma clang fp contract(off)
+  kn = kn_out * rho_out / rc;
+  tt = c_tau * kn / (1.0 + a * kn);
+  snu = 1.0 / (0.5 + tt);
+  sq = 1.0 / (0.5 + (3.0 + 4.0 * M_PI * tt * tt * A2) / (D * tt));
+}
+
+__device__ __forceinline__ void local_rates(double kn_out, double rho_out, double rc, double c_tau, double a,
+                                            double A2, double D, double& snu, double& sq) {
+  double kn, tt;
+  local_rates(kn_out, rho_out, rc, c_tau, a, A2, D, snu, sq, kn, tt);
 }
 
 // Density and velocity of a population vector without force (Eqs. 12-13).

@@ -33,13 +33,14 @@ struct LdsView {
   __device__ __forceinline__ int ny() const { return ny_; }
 };
 
-// Population i of a pressure ghost column at row y.  Reading adopted for the
-// extrapolation scheme the paper cites (Section 3.2): density extrapolated
-// so that the boundary plane carries rho_b, velocity extrapolated linearly
-// from the two adjacent columns, non-equilibrium part copied from the
-// adjacent column: f_g = f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1).
+// The nine populations of a pressure ghost column at row y.  Reading adopted
+// for the extrapolation scheme the paper cites (Section 3.2): density
+// extrapolated so that the boundary plane carries rho_b, velocity
+// extrapolated linearly from the two adjacent columns, non-equilibrium part
+// copied from the adjacent column:
+//   f_g = f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1).
 template <class V>
-__device__ __noinline__ double ghost_pop(V v, bool inlet, int y, double rho_b, int i) {
+__device__ __forceinline__ void ghost_row(const V& v, bool inlet, int y, double rho_b, double g[9]) {
 #pragma clang fp contract(off)
   const int c1 = inlet ? 0 : v.nx() - 1;
   const int c2 = inlet ? 1 : v.nx() - 2;
@@ -55,11 +56,44 @@ __device__ __noinline__ double ghost_pop(V v, bool inlet, int y, double rho_b, i
   double eg[9], e1[9];
   equilibrium(2.0 * rho_b - rho1, 2.0 * ux1 - ux2, 2.0 * uy1 - uy2, eg);
   equilibrium(rho1, ux1, uy1, e1);
-  double out = eg[0] + (f1[0] - e1[0]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) g[k] = eg[k] + (f1[k] - e1[k]);
+}
+
+// Population i of a ghost column, evaluated on the spot.
+template <class V>
+__device__ __noinline__ double ghost_pop(V v, bool inlet, int y, double rho_b, int i) {
+  double g[9];
+  ghost_row(v, inlet, y, rho_b, g);
+  double out = g[0];
 #pragma unroll
   for (int k = 1; k < 9; ++k)
-    if (k == i) out = eg[k] + (f1[k] - e1[k]);
+    if (k == i) out = g[k];
   return out;
+}
+
+// Largest ny whose two ghost columns ([2][9][ny] doubles) are staged in LDS.
+constexpr int kGhostLdsMaxNy = 512;
+
+// The workgroups at the inlet / outlet build the ghost columns they read once
+// per step, one row per thread, into s_in / s_out ([9][ny] each).
+template <class V>
+__device__ __forceinline__ void fill_ghosts(const V& v, double rho_in, double rho_out, bool need_in, bool need_out,
+                                            double* s_in, double* s_out, int tid, int nthreads) {
+  const int ny = v.ny();
+  for (int y = tid; y < ny; y += nthreads) {
+    double g[9];
+    if (need_in) {
+      ghost_row(v, true, y, rho_in, g);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) s_in[k * ny + y] = g[k];
+    }
+    if (need_out) {
+      ghost_row(v, false, y, rho_out, g);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) s_out[k * ny + y] = g[k];
+    }
+  }
 }
 
 template <int MODE, class V>
@@ -68,6 +102,10 @@ struct Gather {
   double r, omr;        // bounce-back fraction r and 1 - r (Eq. 20)
   int shift;            // specular source from x -/+ 1 (1) or the same node (0)
   double rho_in, rho_out;
+  // Optional precomputed ghost columns [9][ny] (LDS) for x = -1 and x = nx;
+  // when null the ghost population is evaluated on the spot.
+  const double* gin = nullptr;
+  const double* gout = nullptr;
 
   // P_i at column xs (possibly -1 or nx) and row ys (always inside).
   __device__ __forceinline__ double pop(int i, int xs, int ys) const {
@@ -76,7 +114,8 @@ struct Gather {
       else if (xs >= v.nx()) xs -= v.nx();
       return v.at(i, xs, ys);
     } else {
-      if (xs < 0 || xs >= v.nx()) return ghost_pop(v, xs < 0, ys, xs < 0 ? rho_in : rho_out, i);
+      if (xs < 0) return gin ? gin[i * v.ny() + ys] : ghost_pop(v, true, ys, rho_in, i);
+      if (xs >= v.nx()) return gout ? gout[i * v.ny() + ys] : ghost_pop(v, false, ys, rho_out, i);
       return v.at(i, xs, ys);
     }
   }

@@ -50,6 +50,7 @@ struct StepArgs {
   double tq_den;        // denominator of Eq. (21)
   double c_tau;         // sqrt(6/pi) * N, N = ny
   double rho_in, rho_out;
+  int ghost_lds;        // pressure mode: ghost columns staged in LDS (set by the launcher)
 };
 
 struct InitArgs {

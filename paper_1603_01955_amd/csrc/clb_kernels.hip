@@ -67,38 +67,66 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K2: fused pressure-driven step.  Block = PX columns x PY row lanes.  The
-// centre-line density of each column (same step, pre-collision) sets the
-// local Knudsen number Kn(x) = Kn_out rho_out / rho_c(x) (Section 3.2) and
-// through Eqs. (18), (21) the column's s_nu and s_q, shared through LDS.
+// K2: fused pressure-driven step.  Block = (256 / RY) columns x RY row lanes
+// with RY the smallest of 16, 32, 64 covering ny, so that up to ny = 64 each
+// thread owns one node and long narrow channels (2000 x 20: 250 workgroups)
+// fill the chip.  The centre-line density of each column (same step,
+// pre-collision) sets the local Knudsen number Kn(x) = Kn_out rho_out /
+// rho_c(x) (Section 3.2) and through Eqs. (18), (21) the column's s_nu and
+// s_q.  With one node per thread the centre-row threads publish their own
+// density through LDS; otherwise the first row lane gathers the centre rows.
 // ---------------------------------------------------------------------------
-constexpr int PX = 64;
-constexpr int PY = 4;
+constexpr int PX = 16;   // column-sum diagnostics: 16 columns x 16 row lanes
+constexpr int PY = 16;
 
-__global__ __launch_bounds__(PX * PY) void k_step_pressure(StepArgs a) {
-  __shared__ double s_nu[PX], s_q[PX];
+template <int RY>
+__global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
+  constexpr int CX = 256 / RY;
+  extern __shared__ double s_ghost[];   // [2][9][ny] in the first / last workgroup
+  __shared__ double s_rc[2][CX];
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * PX + tx;
-  Gather<1, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
-  if (ty == 0 && x < a.g.nx) {
+  const int x = blockIdx.x * CX + tx;
+  const int ny = a.g.ny, yc = ny / 2;
+  const bool even = (ny & 1) == 0;
+  const View v{a.src, a.g};
+  const bool edge_in = a.ghost_lds && blockIdx.x == 0;
+  const bool edge_out = a.ghost_lds && blockIdx.x == gridDim.x - 1;
+  double* gin = s_ghost;
+  double* gout = s_ghost + 9 * ny;
+  if (edge_in || edge_out)
+    fill_ghosts(v, a.rho_in, a.rho_out, edge_in, edge_out, gin, gout, ty * CX + tx, 256);
+  __syncthreads();
+  Gather<1, View> gat{v, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out, edge_in ? gin : nullptr,
+                      edge_out ? gout : nullptr};
+  if (ny <= RY) {
+    const bool active = x < a.g.nx && ty < ny;
     double f[9];
-    const int yc = a.g.ny / 2;
-    gat(x, yc, f);
-    double rc = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    if ((a.g.ny & 1) == 0) {
-      gat(x, yc - 1, f);
-      const double r2 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-      rc = 0.5 * (r2 + rc);
+    if (active) {
+      gat(x, ty, f);
+      if (ty == yc) s_rc[0][tx] = sum9(f);
+      if (even && ty == yc - 1) s_rc[1][tx] = sum9(f);
     }
-    const double kn = a.kn * a.rho_out / rc;
-    const double tt = a.c_tau * kn / (1.0 + a.a * kn);   // Eq. (18): c_tau = sqrt(6/pi) N
-    s_nu[tx] = 1.0 / (0.5 + tt);
-    s_q[tx] = 1.0 / (0.5 + (3.0 + 4.0 * M_PI * tt * tt * a.A2) / (a.tq_den * tt));  // Eq. (21)
+    __syncthreads();
+    if (!active) return;
+    const double rc = even ? 0.5 * (s_rc[1][tx] + s_rc[0][tx]) : s_rc[0][tx];
+    double snu, sq;
+    local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
+    collide<false>(f, 0.0, 0.0, Rates{a.s3, snu, sq, a.s8});
+    store9(a.dst, a.g, x, ty, f);
+    return;
+  }
+  if (ty < 2 && x < a.g.nx && (ty == 0 || even)) {
+    double f[9];
+    gat(x, yc - ty, f);
+    s_rc[ty][tx] = sum9(f);
   }
   __syncthreads();
   if (x >= a.g.nx) return;
-  const Rates s{a.s3, s_nu[tx], s_q[tx], a.s8};
-  for (int y = ty; y < a.g.ny; y += PY) {
+  const double rc = even ? 0.5 * (s_rc[1][tx] + s_rc[0][tx]) : s_rc[0][tx];
+  double snu, sq;
+  local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
+  const Rates s{a.s3, snu, sq, a.s8};
+  for (int y = ty; y < ny; y += RY) {
     double f[9];
     gat(x, y, f);
     collide<false>(f, 0.0, 0.0, s);
@@ -290,8 +318,18 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st) {
     else
       k_step_periodic<false><<<grid, block_x, 0, st>>>(a);
   } else {
-    const dim3 grid((unsigned)((a.g.nx + PX - 1) / PX));
-    k_step_pressure<<<grid, dim3(PX, PY), 0, st>>>(a);
+    StepArgs b = a;
+    b.ghost_lds = a.g.ny <= kGhostLdsMaxNy ? 1 : 0;
+    const size_t lds = b.ghost_lds ? 2 * 9 * (size_t)a.g.ny * sizeof(double) : 0;
+    const int ry = a.g.ny <= 16 ? 16 : (a.g.ny <= 32 ? 32 : 64);
+    const int cx = 256 / ry;
+    const dim3 pgrid((unsigned)((a.g.nx + cx - 1) / cx));
+    if (ry == 16)
+      k_step_pressure<16><<<pgrid, dim3(cx, ry), lds, st>>>(b);
+    else if (ry == 32)
+      k_step_pressure<32><<<pgrid, dim3(cx, ry), lds, st>>>(b);
+    else
+      k_step_pressure<64><<<pgrid, dim3(cx, ry), lds, st>>>(b);
   }
   return hipGetLastError();
 }
