@@ -41,12 +41,9 @@ namespace {
 // smallest of 16, 32, 64 covering ny (one node per thread up to ny = 64).
 inline int adj_rows(int ny) { return ny <= 16 ? 16 : (ny <= 32 ? 32 : 64); }
 
-// Largest ny whose ghost columns and their reverse ([6][9][ny] doubles) are
-// staged in LDS by the edge workgroups of the reverse step.
-constexpr int kAdjGhostLdsMaxNy = 256;
-
 struct AdjArgs {
   const double* P;       // state P_n (device layout)
+  const double* gh;      // ghost columns of P_n, [2][9][ny] (inlet, outlet)
   const double* Pn1;     // state P_{n+1} (ghost reverse of the pulled adjoint)
   const double* lam;     // lambda_{n+1} (device layout), when not pulled
   const double* lin;     // lpre_{n+1}, pulled through the transposed gather
@@ -59,11 +56,12 @@ struct AdjArgs {
   double s3, s8;
   double kn, a, A2, tq_den, c_tau;
   double rho_in, rho_out;
-  int ghost_lds;         // ghost columns staged in LDS by the edge workgroups
 };
 
-// lpre . d pre / d r for the wall-replaced entries of node (x, y) (Eq. 20).
-__device__ double wall_dr(const Gather<1, View>& gat, int x, int y, const double lp[9]) {
+// lpre . d pre / d r for the wall-replaced entries of node (x, y) (Eq. 20),
+// reading the sources again (used off the hot path).
+template <class G>
+__device__ __forceinline__ double wall_dr(const G& gat, int x, int y, const double lp[9]) {
 #pragma clang fp contract(off)
   const int t = gat.v.g.ny - 1;
   const int xsm = gat.shift ? x - 1 : x;
@@ -80,135 +78,149 @@ __device__ double wall_dr(const Gather<1, View>& gat, int x, int y, const double
   return dr;
 }
 
+// ---------------------------------------------------------------------------
 // lambda(x, y) = (G^T lp)(x, y): the adjoint of P_i(x, y) gathered over its
-// uses in the gather G(P) (regular streaming, the CBBSR mixes of Eq. 20, and
-// the reverse of the ghost extrapolation at the first two / last two
-// columns, which needs P itself there).
-// Reverse of ghost row y (inlet or outlet): the adjoint reaching the ghost
-// populations from their uses in G(P), pushed back onto the two adjacent
-// columns (l1: the column next to the boundary, l2: the one after).
-__device__ __forceinline__ void ghost_row_vjp(const AdjArgs& a, const double* __restrict__ lp,
-                                              const double* __restrict__ P, bool inlet, int y, double l1[9],
-                                              double l2[9]) {
+// uses in the gather G(P): regular streaming, the CBBSR mixes of Eq. (20),
+// and the reverse of the ghost extrapolation at the first two / last two
+// columns (which needs P itself there).  Written branch-free like the forward
+// gather: tg_sources selects every address and issues all loads, tg_combine
+// does the arithmetic.  XB = 3: x - 1 and x + 1 lie inside the grid; XB = 1:
+// any column (uses beyond x = -1 or nx are dropped).
+// ---------------------------------------------------------------------------
+template <int XB>
+__device__ __forceinline__ void tg_sources(const AdjArgs& a, const double* __restrict__ lp, int x, int y, double Lp[9],
+                                           double Lq[4]) {
+  const int nx = a.g.nx, t = a.g.ny - 1;
+  const bool bot = y == 0, top = y == t;
+  auto cl = [&](int xx) { return XB == 3 ? xx : (xx < 0 ? 0 : (xx >= nx ? nx - 1 : xx)); };
+  auto A = [&](int i, int xx, int yy) { return lp + a.g.index(i, cl(xx), yy); };
+  const int ym = bot ? 0 : y - 1, yp = top ? t : y + 1;
+  const int xsm = a.shift ? x - 1 : x, xsp = a.shift ? x + 1 : x;
+  const double* p[9];
+  const double* q[4];
+  p[0] = A(0, x, y);
+  p[1] = A(1, x + 1, y);
+  p[3] = A(3, x - 1, y);
+  // directions with e_y = +1 are used at row y + 1, or by the top wall mixes
+  p[2] = top ? A(4, x, t) : A(2, x, yp);
+  p[5] = top ? A(7, x, t) : A(5, x + 1, yp);
+  p[6] = top ? A(8, x, t) : A(6, x - 1, yp);
+  // directions with e_y = -1 are used at row y - 1, or by the bottom wall mixes
+  p[4] = bot ? A(2, x, 0) : A(4, x, ym);
+  p[7] = bot ? A(5, x, 0) : A(7, x - 1, ym);
+  p[8] = bot ? A(6, x, 0) : A(8, x + 1, ym);
+  // specular uses: pre8(x_s) takes P5(x_s - 1), pre7(x_s) takes P6(x_s + 1),
+  // pre6(x_s) takes P7(x_s + 1), pre5(x_s) takes P8(x_s - 1)
+  q[0] = top ? A(8, xsp, t) : p[5];
+  q[1] = top ? A(7, xsm, t) : p[6];
+  q[2] = bot ? A(6, xsm, 0) : p[7];
+  q[3] = bot ? A(5, xsp, 0) : p[8];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Lp[i] = *p[i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Lq[k] = *q[k];
+}
+
+template <int XB>
+__device__ __forceinline__ void tg_combine(const AdjArgs& a, int x, int y, const double Lp[9], const double Lq[4],
+                                           double out[9]) {
 #pragma clang fp contract(off)
   const int nx = a.g.nx, t = a.g.ny - 1;
-  const double omr = 1.0 - a.r;
-  auto L = [&](int i, int xx, int yy) { return lp[a.g.index(i, xx, yy)]; };
-  const int c1 = inlet ? 0 : nx - 1, c2 = inlet ? 1 : nx - 2;
-  // ghost directions entering the channel: 1, 5, 8 at the inlet; 3, 6, 7 at the outlet
-  const int d0 = inlet ? 1 : 3, dup = inlet ? 5 : 6, ddn = inlet ? 8 : 7;
-  double lg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  lg[d0] = L(d0, c1, y);
-  if (y + 1 <= t) lg[dup] += L(dup, c1, y + 1);
-  if (y == t && a.shift) lg[dup] += omr * L(inlet ? 8 : 7, c1, t);
-  if (y - 1 >= 0) lg[ddn] += L(ddn, c1, y - 1);
-  if (y == 0 && a.shift) lg[ddn] += omr * L(inlet ? 5 : 6, c1, 0);
+  const bool bot = y == 0, top = y == t;
+  const double r = a.r, omr = 1.0 - a.r;
+  auto in = [&](int xx) { return XB == 3 || (xx >= 0 && xx < nx); };
+  const int xsm = a.shift ? x - 1 : x, xsp = a.shift ? x + 1 : x;
+  out[0] = Lp[0];
+  out[1] = in(x + 1) ? Lp[1] : 0.0;
+  out[3] = in(x - 1) ? Lp[3] : 0.0;
+  out[2] = Lp[2];
+  out[4] = Lp[4];
+  out[5] = top ? r * Lp[5] + (in(xsp) ? omr * Lq[0] : 0.0) : (in(x + 1) ? Lp[5] : 0.0);
+  out[6] = top ? r * Lp[6] + (in(xsm) ? omr * Lq[1] : 0.0) : (in(x - 1) ? Lp[6] : 0.0);
+  out[7] = bot ? r * Lp[7] + (in(xsm) ? omr * Lq[2] : 0.0) : (in(x - 1) ? Lp[7] : 0.0);
+  out[8] = bot ? r * Lp[8] + (in(xsp) ? omr * Lq[3] : 0.0) : (in(x + 1) ? Lp[8] : 0.0);
+}
+
+// Inputs of the reverse of one ghost row y (inlet or outlet): the adjoint of
+// the three ghost directions that enter the channel, read from lp at the
+// adjacent column c1 (with the specular corner terms of Eq. 20), and the
+// populations of P at c1 and at the next column c2.
+struct GhostIn {
+  double l0, lup, ldn, ltop, lbot;
   double f1[9], f2[9];
+};
+
+template <bool INLET>
+__device__ __forceinline__ void ghost_sources(const AdjArgs& a, const double* __restrict__ lp,
+                                              const double* __restrict__ P, int y, GhostIn& gi) {
+  const int nx = a.g.nx, t = a.g.ny - 1;
+  const int c1 = INLET ? 0 : nx - 1, c2 = INLET ? 1 : nx - 2;
+  constexpr int d0 = INLET ? 1 : 3, dup = INLET ? 5 : 6, ddn = INLET ? 8 : 7;
+  gi.l0 = lp[a.g.index(d0, c1, y)];
+  gi.lup = lp[a.g.index(dup, c1, y < t ? y + 1 : t)];
+  gi.ldn = lp[a.g.index(ddn, c1, y > 0 ? y - 1 : 0)];
+  gi.ltop = lp[a.g.index(INLET ? 8 : 7, c1, t)];
+  gi.lbot = lp[a.g.index(INLET ? 5 : 6, c1, 0)];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    f1[i] = P[a.g.index(i, c1, y)];
-    f2[i] = P[a.g.index(i, c2, y)];
+    gi.f1[i] = P[a.g.index(i, c1, y)];
+    gi.f2[i] = P[a.g.index(i, c2, y)];
+  }
+}
+
+// l1 / l2: the adjoint pushed back onto columns c1 / c2 at row y.
+template <bool INLET>
+__device__ __forceinline__ void ghost_apply(const AdjArgs& a, int y, const GhostIn& gi, double l1[9], double l2[9]) {
+#pragma clang fp contract(off)
+  const int t = a.g.ny - 1;
+  const double omr = 1.0 - a.r;
+  double lg[3];   // directions (1, 5, 8) at the inlet, (3, 6, 7) at the outlet
+  lg[0] = gi.l0;
+  lg[1] = y + 1 <= t ? gi.lup : ((y == t && a.shift) ? omr * gi.ltop : 0.0);
+  lg[2] = y - 1 >= 0 ? gi.ldn : ((y == 0 && a.shift) ? omr * gi.lbot : 0.0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
     l1[i] = 0.0;
     l2[i] = 0.0;
   }
-  ghost_vjp(f1, f2, inlet ? a.rho_in : a.rho_out, lg, l1, l2);
+  ghost_vjp<INLET>(gi.f1, gi.f2, INLET ? a.rho_in : a.rho_out, lg, l1, l2);
 }
 
-// Edge workgroups: the reverse of every ghost row, one row per thread, into
-// gv[4][9][ny] (inlet l1, inlet l2, outlet l1, outlet l2).
-__device__ __forceinline__ void fill_ghost_vjp(const AdjArgs& a, const double* __restrict__ lp,
-                                               const double* __restrict__ P, bool need_in, bool need_out,
-                                               double* gv, int tid, int nthreads) {
-  const int ny = a.g.ny;
-  for (int y = tid; y < ny; y += nthreads) {
-    double l1[9], l2[9];
-    if (need_in) {
-      ghost_row_vjp(a, lp, P, true, y, l1, l2);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        gv[(0 * 9 + i) * ny + y] = l1[i];
-        gv[(1 * 9 + i) * ny + y] = l2[i];
-      }
-    }
-    if (need_out) {
-      ghost_row_vjp(a, lp, P, false, y, l1, l2);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        gv[(2 * 9 + i) * ny + y] = l1[i];
-        gv[(3 * 9 + i) * ny + y] = l2[i];
-      }
-    }
-  }
-}
-
-__device__ __forceinline__ void transposed_gather(const AdjArgs& a, const double* __restrict__ lp,
-                                                  const double* __restrict__ P, int x, int y, double out[9],
-                                                  const double* gv = nullptr) {
+// Adds the ghost-row reverse to out[9] for nodes in the first two / last two
+// columns (XB = 1 only).
+__device__ __forceinline__ void ghost_add(const AdjArgs& a, int x, int y, bool need_in, bool need_out,
+                                          const GhostIn& gi, const GhostIn& go, double out[9]) {
 #pragma clang fp contract(off)
-  const int nx = a.g.nx, ny = a.g.ny, t = ny - 1;
-  const double r = a.r, omr = 1.0 - a.r;
-  auto L = [&](int i, int xx, int yy) { return lp[a.g.index(i, xx, yy)]; };
+  const int nx = a.g.nx;
+  if (need_in) {
+    double l1[9], l2[9];
+    ghost_apply<true>(a, y, gi, l1, l2);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const int ex = ex_of(i), ey = ey_of(i);
-    double acc = 0.0;
-    const int xd = x + ex, yd = y + ey;
-    if (yd >= 0 && yd < ny) {
-      if (xd >= 0 && xd < nx) acc += L(i, xd, yd);   // regular streaming use
-    } else if (ey < 0) {                            // below the bottom wall (Eq. 20)
-      if (i == 4) acc += L(2, x, 0);
-      if (i == 7) {
-        acc += r * L(5, x, 0);
-        const int xs = a.shift ? x - 1 : x;            // pre6(xs) takes P7(xs + 1)
-        if (xs >= 0) acc += omr * L(6, xs, 0);
-      }
-      if (i == 8) {
-        acc += r * L(6, x, 0);
-        const int xs = a.shift ? x + 1 : x;            // pre5(xs) takes P8(xs - 1)
-        if (xs < nx) acc += omr * L(5, xs, 0);
-      }
-    } else {                                        // above the top wall (mirror)
-      if (i == 2) acc += L(4, x, t);
-      if (i == 5) {
-        acc += r * L(7, x, t);
-        const int xs = a.shift ? x + 1 : x;            // pre8(xs) takes P5(xs - 1)
-        if (xs < nx) acc += omr * L(8, xs, t);
-      }
-      if (i == 6) {
-        acc += r * L(8, x, t);
-        const int xs = a.shift ? x - 1 : x;            // pre7(xs) takes P6(xs + 1)
-        if (xs >= 0) acc += omr * L(7, xs, t);
-      }
-    }
-    out[i] = acc;
+    for (int i = 0; i < 9; ++i) out[i] += (x == 0) ? l1[i] : l2[i];
   }
-  // Reverse of the ghost columns (pressure mode): the inlet ghost row y is
-  // built from columns 0, 1, the outlet one from nx - 1, nx - 2.
-  if (x <= 1) {
-    if (gv) {
+  if (need_out) {
+    double l1[9], l2[9];
+    ghost_apply<false>(a, y, go, l1, l2);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) out[i] += gv[(x * 9 + i) * ny + y];
-    } else {
-      double l1[9], l2[9];
-      ghost_row_vjp(a, lp, P, true, y, l1, l2);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) out[i] += (x == 0) ? l1[i] : l2[i];
-    }
-  }
-  if (x >= nx - 2) {
-    const int c = nx - 1 - x;   // 0: adjacent column, 1: the next one
-    if (gv) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) out[i] += gv[((2 + c) * 9 + i) * ny + y];
-    } else {
-      double l1[9], l2[9];
-      ghost_row_vjp(a, lp, P, false, y, l1, l2);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) out[i] += (c == 0) ? l1[i] : l2[i];
-    }
+    for (int i = 0; i < 9; ++i) out[i] += (x == nx - 1) ? l1[i] : l2[i];
   }
 }
 
+// The whole transposed gather of one node (any column).
+__device__ __forceinline__ void transposed_gather(const AdjArgs& a, const double* __restrict__ lp,
+                                                  const double* __restrict__ P, int x, int y, double out[9]) {
+  const int nx = a.g.nx;
+  const bool need_in = x <= 1, need_out = x >= nx - 2;
+  GhostIn gi, go;
+  if (need_in) ghost_sources<true>(a, lp, P, y, gi);
+  if (need_out) ghost_sources<false>(a, lp, P, y, go);
+  double Lp[9], Lq[4];
+  tg_sources<1>(a, lp, x, y, Lp, Lq);
+  tg_combine<1>(a, x, y, Lp, Lq, out);
+  ghost_add(a, x, y, need_in, need_out, gi, go, out);
+}
+
+// ---------------------------------------------------------------------------
 // One reverse step n.  lambda_{n+1}(x, y) is either pulled on the fly from
 // lpre_{n+1} (PULL: the transposed gather of step n + 1, ghosts at P_{n+1})
 // or read from a.lam.  Then lpre_n = (dC/dpre_n)^T lambda_{n+1} at
@@ -216,65 +228,103 @@ __device__ __forceinline__ void transposed_gather(const AdjArgs& a, const double
 // s(tau(Kn(rho_c))) into lpre_n at the centre rows and into dL/da, dL/dA2,
 // and wall rows add lpre . dpre/dr to dL/dr.  Up to ny = RY each thread owns
 // one node and keeps it in registers across the column reductions.
-template <int RY, bool PULL>
-__global__ __launch_bounds__(256) void k_adj_step(AdjArgs a) {
+// ---------------------------------------------------------------------------
+// Workgroup scratch of the reverse step: centre-row densities, per-row rate
+// sensitivities and per-column results.
+template <int RY>
+struct AdjShared {
+  static constexpr int CX = 256 / RY;
+  double rcr[2][CX];
+  double nu[RY][CX], q[RY][CX], rr[RY][CX];
+  double lrc[CX], ca[CX], cA2[CX], cr[CX];
+};
+
+// Gathered state and pulled adjoint of node (x, y): all loads first, then
+// the arithmetic.  XB = 3 for interior workgroups (columns 2 .. nx - 3, no
+// boundary code), XB = 1 for the others.
+template <int XB, bool PULL>
+__device__ __forceinline__ void adj_node_inputs(const AdjArgs& a, const Gather<XB == 3 ? 3 : 2, View>& gat, int x,
+                                                int y, double f[9], double lo[9], double A[9], double B[4]) {
+#pragma clang fp contract(off)
+  const int nx = a.g.nx;
+  const bool need_in = XB == 1 && PULL && x <= 1;
+  const bool need_out = XB == 1 && PULL && x >= nx - 2;
+  GhostIn gi, go;
+  if (need_in) ghost_sources<true>(a, a.lin, a.Pn1, y, gi);
+  if (need_out) ghost_sources<false>(a, a.lin, a.Pn1, y, go);
+  double Lp[9], Lq[4];
+  gat.sources(x, y, A, B);
+  if (PULL) {
+    tg_sources<XB>(a, a.lin, x, y, Lp, Lq);
+  } else {
+    const size_t base = a.g.index(0, x, y);
+    const size_t stride = (size_t)1 << a.g.lshift;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lo[i] = a.lam[base + i * stride];
+  }
+  gat.combine(y, A, B, f);
+  if (PULL) {
+    tg_combine<XB>(a, x, y, Lp, Lq, lo);
+    if (XB == 1) ghost_add(a, x, y, need_in, need_out, gi, go, lo);
+  }
+}
+
+template <int RY, bool PULL, int XB>
+__device__ __forceinline__ void adj_columns(const AdjArgs& a, const Gather<XB == 3 ? 3 : 2, View>& gat,
+                                            AdjShared<RY>& sh) {
 #pragma clang fp contract(off)
   constexpr int CX = 256 / RY;
-  __shared__ double s_rcr[2][CX];
-  __shared__ double r_nu[RY][CX], r_q[RY][CX], r_r[RY][CX];
-  __shared__ double c_lrc[CX], c_a[CX], c_A2[CX], c_r[CX];
-  // first / last workgroup: ghost columns of P_n [2][9][ny], then (PULL)
-  // the reverse of the ghost rows of P_{n+1} [4][9][ny]
-  extern __shared__ double s_dyn[];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x = blockIdx.x * CX + tx;
   const int nx = a.g.nx, ny = a.g.ny;
-  const View v{a.P, a.g};
-  const bool edge_in = a.ghost_lds && blockIdx.x == 0;
-  const bool edge_out = a.ghost_lds && blockIdx.x == gridDim.x - 1;
-  double* s_ghost = s_dyn;
-  double* s_gv = s_dyn + 18 * ny;
-  if (edge_in || edge_out) {
-    const int tid = ty * CX + tx;
-    if (tid < 128)
-      fill_ghosts(v, a.rho_in, a.rho_out, edge_in, edge_out, s_ghost, s_ghost + 9 * ny, tid, 128);
-    else if (PULL)
-      fill_ghost_vjp(a, a.lin, a.Pn1, edge_in, edge_out, s_gv, tid - 128, 128);
+  const bool lead = tx == 0 && ty == 0;
+  // this workgroup's running gradient partials, fetched early
+  double gp0 = 0.0, gp1 = 0.0, gp2 = 0.0;
+  if (lead) {
+    gp0 = a.gpart[3 * blockIdx.x];
+    gp1 = a.gpart[3 * blockIdx.x + 1];
+    gp2 = a.gpart[3 * blockIdx.x + 2];
   }
-  __syncthreads();
-  const double* gv = (PULL && (edge_in || edge_out)) ? s_gv : nullptr;
-  const Gather<1, View> gat{v, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out, edge_in ? s_ghost : nullptr,
-                            edge_out ? s_ghost + 9 * ny : nullptr};
   const int yc = ny / 2;
   const bool even = (ny & 1) == 0;
   const size_t stride = (size_t)1 << a.g.lshift;
   const bool one = ny <= RY;   // one node per thread
-  double f[9], lo[9];
+  double f[9], lo[9], A[9], B[4];
   bool active = false;
   if (one) {
     active = x < nx && ty < ny;
     if (active) {
-      gat(x, ty, f);
-      if (PULL) {
-        transposed_gather(a, a.lin, a.Pn1, x, ty, lo, gv);
-      } else {
-        const size_t base = a.g.index(0, x, ty);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) lo[i] = a.lam[base + i * stride];
-      }
-      if (ty == yc) s_rcr[0][tx] = sum9(f);
-      if (even && ty == yc - 1) s_rcr[1][tx] = sum9(f);
+      adj_node_inputs<XB, PULL>(a, gat, x, ty, f, lo, A, B);
+      if (ty == yc) sh.rcr[0][tx] = sum9(f);
+      if (even && ty == yc - 1) sh.rcr[1][tx] = sum9(f);
     }
   } else if (ty < 2 && x < nx && (ty == 0 || even)) {
     double g[9];
-    gat(x, yc - ty, g);
-    s_rcr[ty][tx] = sum9(g);
+    gat.flat(x, yc - ty, g);
+    sh.rcr[ty][tx] = sum9(g);
   }
   __syncthreads();
   double snu = 0.0, sq = 0.0, kn = 0.0, tt = 0.0, rc = 1.0;
   if (x < nx) {
-    rc = even ? 0.5 * (s_rcr[1][tx] + s_rcr[0][tx]) : s_rcr[0][tx];
+    rc = even ? 0.5 * (sh.rcr[1][tx] + sh.rcr[0][tx]) : sh.rcr[0][tx];
     local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq, kn, tt);
+  }
+  // Derivatives of the column's rates, needed once its sums are in:
+  //   s_nu = 1/(1/2 + tt),  s_q = 1/(1/2 + 3/(D tt) + 4 pi A2 tt / D)   (Eqs. 18, 21)
+  //   tt = c_tau Kn / (1 + a Kn),  Kn = Kn_out rho_out / rho_c
+  double k_nu_rc = 0.0, k_q_rc = 0.0, k_nu_a = 0.0, k_q_a = 0.0, k_q_A2 = 0.0;
+  if (ty == 0 && x < nx) {
+    const double D = a.tq_den;
+    const double dsnu_dtt = -snu * snu;
+    const double dsq_dtt = (-sq * sq) * (4.0 * M_PI * a.A2 / D - 3.0 / (D * tt * tt));
+    const double den = 1.0 + a.a * kn;
+    const double dtt_drc = a.c_tau / (den * den) * (-kn / rc);
+    const double dtt_da = -a.c_tau * kn * kn / (den * den);
+    k_nu_rc = dsnu_dtt * dtt_drc;
+    k_q_rc = dsq_dtt * dtt_drc;
+    k_nu_a = dsnu_dtt * dtt_da;
+    k_q_a = dsq_dtt * dtt_da;
+    k_q_A2 = (-sq * sq) * (4.0 * M_PI * tt / D);
   }
   const Rates s{a.s3, snu, sq, a.s8};
   double acc_nu = 0.0, acc_q = 0.0, acc_r = 0.0;
@@ -286,7 +336,7 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjArgs a) {
       collide_vjp(f, lo, s, lf, lsnu, lsq);
       acc_nu = lsnu;
       acc_q = lsq;
-      if (ty == 0 || ty == ny - 1) acc_r = wall_dr(gat, x, ty, lf);
+      acc_r = gat.wall_dr(ty, A, B, lf);
       hold = ty == yc || (even && ty == yc - 1);
       if (!hold) {
         const size_t base = a.g.index(0, x, ty);
@@ -296,48 +346,36 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjArgs a) {
     }
   } else if (x < nx) {
     for (int y = ty; y < ny; y += RY) {
-      double g[9], l[9], lg[9];
-      gat(x, y, g);
-      const size_t base = a.g.index(0, x, y);
-      if (PULL) {
-        transposed_gather(a, a.lin, a.Pn1, x, y, l, gv);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) l[i] = a.lam[base + i * stride];
-      }
+      double g[9], l[9], lg[9], Ay[9], By[4];
+      adj_node_inputs<XB, PULL>(a, gat, x, y, g, l, Ay, By);
       double lsnu, lsq;
       collide_vjp(g, l, s, lg, lsnu, lsq);
       acc_nu += lsnu;
       acc_q += lsq;
-      if (y == 0 || y == ny - 1) acc_r += wall_dr(gat, x, y, lg);
+      acc_r += gat.wall_dr(y, Ay, By, lg);
+      const size_t base = a.g.index(0, x, y);
 #pragma unroll
       for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] = lg[i];
     }
   }
-  r_nu[ty][tx] = acc_nu;
-  r_q[ty][tx] = acc_q;
-  r_r[ty][tx] = acc_r;
+  sh.nu[ty][tx] = acc_nu;
+  sh.q[ty][tx] = acc_q;
+  sh.rr[ty][tx] = acc_r;
   __syncthreads();
   const double w = even ? 0.5 : 1.0;
   if (ty == 0) {
     double da = 0.0, dA2 = 0.0, dr = 0.0, l_rc = 0.0;
     if (x < nx) {
-      double lnu = r_nu[0][tx], lq = r_q[0][tx];
-      dr = r_r[0][tx];
+      double lnu = sh.nu[0][tx], lq = sh.q[0][tx];
+      dr = sh.rr[0][tx];
       for (int k = 1; k < RY; ++k) {
-        lnu += r_nu[k][tx];
-        lq += r_q[k][tx];
-        dr += r_r[k][tx];
+        lnu += sh.nu[k][tx];
+        lq += sh.q[k][tx];
+        dr += sh.rr[k][tx];
       }
-      // s_nu = 1/(1/2 + tt);  s_q = 1/(1/2 + 3/(D tt) + 4 pi A2 tt / D)   (Eqs. 18, 21)
-      const double D = a.tq_den;
-      const double l_tt = -snu * snu * lnu + (-sq * sq) * (4.0 * M_PI * a.A2 / D - 3.0 / (D * tt * tt)) * lq;
-      const double den = 1.0 + a.a * kn;
-      // tt = c_tau Kn / (1 + a Kn),  Kn = Kn_out rho_out / rho_c
-      const double dtt_dkn = a.c_tau / (den * den);
-      l_rc = l_tt * dtt_dkn * (-kn / rc);
-      da = l_tt * (-a.c_tau * kn * kn / (den * den));
-      dA2 = (-sq * sq) * (4.0 * M_PI * tt / D) * lq;
+      l_rc = k_nu_rc * lnu + k_q_rc * lq;
+      da = k_nu_a * lnu + k_q_a * lq;
+      dA2 = k_q_A2 * lq;
       // rho_c = mean of the centre rows of pre: l_rc reaches every population
       // there; centre rows that are wall rows also carry an r dependence.
       double lp[9];
@@ -353,30 +391,47 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjArgs a) {
         }
       }
     }
-    c_lrc[tx] = l_rc;
-    c_a[tx] = da;
-    c_A2[tx] = dA2;
-    c_r[tx] = dr;
+    sh.lrc[tx] = l_rc;
+    sh.ca[tx] = da;
+    sh.cA2[tx] = dA2;
+    sh.cr[tx] = dr;
   }
   __syncthreads();
   if (hold) {
-    const double add = w * c_lrc[tx];
+    const double add = w * sh.lrc[tx];
     const size_t base = a.g.index(0, x, ty);
 #pragma unroll
     for (int i = 0; i < 9; ++i) a.lpre[base + i * stride] = lf[i] + add;
   }
-  if (tx == 0 && ty == 0) {
+  if (lead) {
     double sa = 0.0, sA2 = 0.0, sr = 0.0;
     for (int k = 0; k < CX; ++k) {
-      sa += c_a[k];
-      sA2 += c_A2[k];
-      sr += c_r[k];
+      sa += sh.ca[k];
+      sA2 += sh.cA2[k];
+      sr += sh.cr[k];
     }
-    double* gp = a.gpart + 3 * blockIdx.x;
-    gp[0] += sa;
-    gp[1] += sA2;
-    gp[2] += sr;
+    a.gpart[3 * blockIdx.x] = gp0 + sa;
+    a.gpart[3 * blockIdx.x + 1] = gp1 + sA2;
+    a.gpart[3 * blockIdx.x + 2] = gp2 + sr;
   }
+}
+
+// The reverse step, dispatched per workgroup: workgroups whose columns all
+// lie in 2 .. nx - 3 run with no x-boundary code; the others read the ghost
+// columns of P_n from a.gh and reverse the ghost rows of P_{n+1} in place.
+template <int RY, bool PULL>
+__global__ __launch_bounds__(256) void k_adj_step(AdjArgs a) {
+  constexpr int CX = 256 / RY;
+  __shared__ AdjShared<RY> sh;
+  const View v{a.P, a.g};
+  const double omr = 1.0 - a.r;
+  const int ny = a.g.ny;
+  const bool interior = blockIdx.x > 0 && (int)(blockIdx.x + 1) * CX <= a.g.nx - 2;
+  if (interior)
+    adj_columns<RY, PULL, 3>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, sh);
+  else
+    adj_columns<RY, PULL, 1>(a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, a.gh, a.gh + 9 * ny},
+                             sh);
 }
 
 // lambda_n = G^T lpre (+ reverse of the ghost columns), one thread per node.
@@ -388,6 +443,25 @@ __global__ __launch_bounds__(256) void k_adj_gather(AdjArgs a) {
   transposed_gather(a, a.lpre, a.P, x, y, out);
 #pragma unroll
   for (int i = 0; i < 9; ++i) a.out[a.g.index(i, x, y)] = out[i];
+}
+
+// Ghost columns of nstate states into gh[k][2][9][ny]: state 0 at `first`,
+// state k >= 1 at rest + (k - 1) * S.  One workgroup per state.
+__global__ __launch_bounds__(256) void k_ghosts(const double* __restrict__ first, const double* __restrict__ rest,
+                                                size_t S, Geo g, double rho_in, double rho_out,
+                                                double* __restrict__ gh) {
+  const int k = blockIdx.x;
+  const View v{k == 0 ? first : rest + (size_t)(k - 1) * S, g};
+  const int ny = g.ny;
+  double* out = gh + (size_t)k * 18 * ny;
+  for (int j = threadIdx.x; j < 2 * ny; j += blockDim.x) {
+    const bool inlet = j < ny;
+    const int y = inlet ? j : j - ny;
+    double gr[9];
+    ghost_row(v, inlet, y, inlet ? rho_in : rho_out, gr);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[(inlet ? 0 : 9 * ny) + i * ny + y] = gr[i];
+  }
 }
 
 // Loss of the final state from per-column sums m(x) and rho_c(x):
@@ -507,6 +581,7 @@ struct clb_adjoint {
   double* pT;              // P at step T
   double* lam[2];
   double* lpre;
+  double* gh;              // [2][K][2][9][ny] ghost columns of the recomputed states
   double* gpart;           // [nblk][3]
   double* col;             // [6][nx]: m, su, rho_c, diff, final-gather r terms (2 nx)
   double* dpt;             // [nx] target dp*
@@ -523,7 +598,7 @@ struct clb_adjoint {
 namespace {
 
 struct AdjLayout {
-  size_t S, total;
+  size_t S, total, gh;
   int nck, nseg, nblk;
 };
 
@@ -538,8 +613,9 @@ AdjLayout adj_layout(const clb_params* p, int32_t T, int32_t K) {
   L.nblk = (p->nx + cx - 1) / cx;
   const size_t buf = clb::align256(L.S * sizeof(double));
   const size_t col = clb::align256((size_t)p->nx * sizeof(double));
-  L.total = ((size_t)L.nck + (size_t)L.nseg + 4) * buf + 7 * col + clb::align256((size_t)L.nblk * 3 * sizeof(double)) +
-            clb::align256(16 * sizeof(double));
+  L.gh = clb::align256(2 * (size_t)K * 18 * (size_t)p->ny * sizeof(double));
+  L.total = ((size_t)L.nck + (size_t)L.nseg + 4) * buf + L.gh + 7 * col +
+            clb::align256((size_t)L.nblk * 3 * sizeof(double)) + clb::align256(16 * sizeof(double));
   return L;
 }
 
@@ -583,7 +659,6 @@ clb::AdjArgs adj_args(const clb_adjoint* a, const double* P, double* lpre) {
   r.c_tau = std::sqrt(6.0 / M_PI) * (double)a->p.ny;
   r.rho_in = a->p.p_ratio * a->p.rho_out;
   r.rho_out = a->p.rho_out;
-  r.ghost_lds = a->p.ny <= clb::kAdjGhostLdsMaxNy ? 1 : 0;
   return r;
 }
 
@@ -602,8 +677,13 @@ double* seg_state(clb_adjoint* a, int s, int set, int n) {
   return a->seg + ((size_t)set * (size_t)(a->K - 1) + (size_t)(n - start - 1)) * a->S;
 }
 
+// Ghost columns of state n of a segment recomputed into buffer set `set`.
+double* seg_ghosts(clb_adjoint* a, int set, int k) {
+  return a->gh + ((size_t)set * (size_t)a->K + (size_t)k) * 18 * (size_t)a->p.ny;
+}
+
 // Recompute the states of segment s from its checkpoint on the private
-// stream, then mark buffer set `set` ready.
+// stream, build their ghost columns, then mark buffer set `set` ready.
 clb_status recompute(clb_adjoint* a, int s, int set) {
   const int start = s * a->K;
   const int end = (start + a->K < a->T) ? start + a->K : a->T;
@@ -611,30 +691,33 @@ clb_status recompute(clb_adjoint* a, int s, int set) {
     clb_status st = step(a, seg_state(a, s, set, n), seg_state(a, s, set, n + 1), a->rstream);
     if (st != CLB_OK) return st;
   }
+  clb::k_ghosts<<<end - start, 256, 0, a->rstream>>>(seg_state(a, s, set, start),
+                                                     a->seg + (size_t)set * (size_t)(a->K - 1) * a->S, a->S, a->g,
+                                                     a->p.p_ratio * a->p.rho_out, a->p.rho_out, seg_ghosts(a, set, 0));
+  ADJ_HIP(hipGetLastError());
   ADJ_HIP(hipEventRecord(a->ev_ready[set], a->rstream));
   return CLB_OK;
 }
 
 template <bool PULL>
 clb_status launch_adj_step(clb_adjoint* a, const clb::AdjArgs& r) {
-  // ghost columns [2][9][ny] plus, when pulling, their reverse [4][9][ny]
-  const size_t lds = r.ghost_lds ? (PULL ? 54 : 18) * (size_t)a->p.ny * sizeof(double) : 0;
   const int ry = clb::adj_rows(a->p.ny), cx = 256 / ry;
   if (ry == 16)
-    clb::k_adj_step<16, PULL><<<a->nblk, dim3(cx, ry), lds, a->stream>>>(r);
+    clb::k_adj_step<16, PULL><<<a->nblk, dim3(cx, ry), 0, a->stream>>>(r);
   else if (ry == 32)
-    clb::k_adj_step<32, PULL><<<a->nblk, dim3(cx, ry), lds, a->stream>>>(r);
+    clb::k_adj_step<32, PULL><<<a->nblk, dim3(cx, ry), 0, a->stream>>>(r);
   else
-    clb::k_adj_step<64, PULL><<<a->nblk, dim3(cx, ry), lds, a->stream>>>(r);
+    clb::k_adj_step<64, PULL><<<a->nblk, dim3(cx, ry), 0, a->stream>>>(r);
   ADJ_HIP(hipGetLastError());
   return CLB_OK;
 }
 
 // Reverse step n of the sweep: lpre_n from lpre_{n+1} (pulled, ghosts at
-// P_{n+1}) and the state P_n.
-clb_status reverse_step(clb_adjoint* a, const double* Pn, const double* Pn1, const double* lpre_next,
-                        double* lpre_out) {
+// P_{n+1}) and the state P_n with its ghost columns gh.
+clb_status reverse_step(clb_adjoint* a, const double* Pn, const double* gh, const double* Pn1,
+                        const double* lpre_next, double* lpre_out) {
   clb::AdjArgs r = adj_args(a, Pn, lpre_out);
+  r.gh = gh;
   r.Pn1 = Pn1;
   r.lin = lpre_next;
   return launch_adj_step<true>(a, r);
@@ -712,6 +795,8 @@ clb_status clb_adjoint_init(const clb_params* p, int32_t T, int32_t K, void* d_w
   q += buf;
   a->lpre = reinterpret_cast<double*>(q);
   q += buf;
+  a->gh = reinterpret_cast<double*>(q);
+  q += L.gh;
   a->col = reinterpret_cast<double*>(q);
   q += 6 * col;   // m, su, rho_c, diff, final-gather r terms (2 nx)
   a->dpt = reinterpret_cast<double*>(q);
@@ -822,7 +907,9 @@ clb_status clb_adjoint_backward(clb_adjoint* a, double* h_grad) {
     for (int n = end - 1; n >= start; --n) {
       const double* Pn1 = n + 1 < end ? seg_state(a, s, set, n + 1)
                                       : (end == a->T ? a->pT : a->ck + (size_t)(s + 1) * a->S);
-      if ((st = reverse_step(a, seg_state(a, s, set, n), Pn1, lbuf[cur], lbuf[cur ^ 1])) != CLB_OK) return st;
+      if ((st = reverse_step(a, seg_state(a, s, set, n), seg_ghosts(a, set, n - start), Pn1, lbuf[cur],
+                             lbuf[cur ^ 1])) != CLB_OK)
+        return st;
       cur ^= 1;
     }
     ADJ_HIP(hipEventRecord(a->ev_free[set], a->stream));
@@ -881,8 +968,10 @@ clb_status clb_adjoint_vjp_step(clb_adjoint* a, const double* d_P, const double*
   ADJ_HIP(clb::launch_import(d_P, a->g, P, a->stream));
   ADJ_HIP(clb::launch_import(d_lam_next, a->g, lam, a->stream));
   clb::k_fill<<<1, 256, 0, a->stream>>>(a->gpart, (size_t)a->nblk * 3, 0.0);
+  clb::k_ghosts<<<1, 256, 0, a->stream>>>(P, P, a->S, a->g, a->p.p_ratio * a->p.rho_out, a->p.rho_out, a->gh);
   {
     clb::AdjArgs r = adj_args(a, P, a->lpre);
+    r.gh = a->gh;
     r.lam = lam;
     if ((st = launch_adj_step<false>(a, r)) != CLB_OK) return st;
     r.out = a->lam[1];

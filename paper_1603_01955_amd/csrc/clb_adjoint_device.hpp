@@ -187,10 +187,14 @@ __device__ __forceinline__ int ey_of(int i) {
 // Reverse of the pressure ghost column of one row (the extrapolation used by
 // the forward gather): g = f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1)
 // with (rho_1, u_1) from f1 (adjacent column) and u_2 from f2 (next column).
-// Given lg = dL/dg, adds dL/df1 to l1 and dL/df2 to l2.
-__device__ __forceinline__ void ghost_vjp(const double f1[9], const double f2[9], double rho_b, const double lg[9],
+// Only the directions entering the channel are used downstream (1, 5, 8 at
+// the inlet, 3, 6, 7 at the outlet), so lg = dL/dg has those three entries;
+// adds dL/df1 to l1 and dL/df2 to l2.
+template <bool INLET>
+__device__ __forceinline__ void ghost_vjp(const double f1[9], const double f2[9], double rho_b, const double lg[3],
                                           double l1[9], double l2[9]) {
 #pragma clang fp contract(off)
+  constexpr int dirs[3] = {INLET ? 1 : 3, INLET ? 5 : 6, INLET ? 8 : 7};
   double rho1, ux1, uy1, rho2, ux2, uy2;
   rho_u(f1, rho1, ux1, uy1);
   rho_u(f2, rho2, ux2, uy2);
@@ -198,17 +202,18 @@ __device__ __forceinline__ void ghost_vjp(const double f1[9], const double f2[9]
   const double ugx = 2.0 * ux1 - ux2, ugy = 2.0 * uy1 - uy2;
   double l_rhog = 0.0, l_ugx = 0.0, l_ugy = 0.0, l_rho1 = 0.0, l_u1x = 0.0, l_u1y = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
+  for (int k = 0; k < 3; ++k) {
+    const int i = dirs[k];
     const int ex = ex_of(i), ey = ey_of(i);
     const double wgx = eq_w(ex, ugx), wgy = eq_w(ey, ugy);
     const double w1x = eq_w(ex, ux1), w1y = eq_w(ey, uy1);
-    l_rhog += lg[i] * (wgx * wgy);
-    l_ugx += lg[i] * rhog * (eq_dw(ex, ugx) * wgy);
-    l_ugy += lg[i] * rhog * (wgx * eq_dw(ey, ugy));
-    l_rho1 -= lg[i] * (w1x * w1y);
-    l_u1x -= lg[i] * rho1 * (eq_dw(ex, ux1) * w1y);
-    l_u1y -= lg[i] * rho1 * (w1x * eq_dw(ey, uy1));
-    l1[i] += lg[i];   // the copied f_1 term
+    l_rhog += lg[k] * (wgx * wgy);
+    l_ugx += lg[k] * rhog * (eq_dw(ex, ugx) * wgy);
+    l_ugy += lg[k] * rhog * (wgx * eq_dw(ey, ugy));
+    l_rho1 -= lg[k] * (w1x * w1y);
+    l_u1x -= lg[k] * rho1 * (eq_dw(ex, ux1) * w1y);
+    l_u1y -= lg[k] * rho1 * (w1x * eq_dw(ey, uy1));
+    l1[i] += lg[k];   // the copied f_1 term
   }
   // rho_g = 2 rho_b - rho_1, u_g = 2 u_1 - u_2
   l_rho1 -= l_rhog;

@@ -13,7 +13,13 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Gather of the pre-collision populations of node (x, y).
-// MODE 0: periodic x.  MODE 1: pressure ghost columns at x = -1 and x = nx.
+// MODE 0: periodic x.
+// MODE 1: pressure ghost columns at x = -1 and x = nx, evaluated on the spot.
+// MODE 2: pressure ghost columns read from LDS (gin, gout: [9][ny] each).
+// MODE 3: a node whose x - 1 and x + 1 both lie inside the grid (interior
+//         workgroups of the pressure kernels): no x-boundary code at all.
+// Modes 2 and 3 keep out-of-line calls (and the full memory waits a call
+// implies) out of the kernels that run every step.
 // ---------------------------------------------------------------------------
 // Populations in the device layout of a single-channel buffer (HBM).
 struct View {
@@ -102,8 +108,7 @@ struct Gather {
   double r, omr;        // bounce-back fraction r and 1 - r (Eq. 20)
   int shift;            // specular source from x -/+ 1 (1) or the same node (0)
   double rho_in, rho_out;
-  // Optional precomputed ghost columns [9][ny] (LDS) for x = -1 and x = nx;
-  // when null the ghost population is evaluated on the spot.
+  // MODE 2: ghost columns [9][ny] (LDS) for x = -1 and x = nx.
   const double* gin = nullptr;
   const double* gout = nullptr;
 
@@ -112,12 +117,88 @@ struct Gather {
     if (MODE == 0) {
       if (xs < 0) xs += v.nx();
       else if (xs >= v.nx()) xs -= v.nx();
-      return v.at(i, xs, ys);
-    } else {
-      if (xs < 0) return gin ? gin[i * v.ny() + ys] : ghost_pop(v, true, ys, rho_in, i);
-      if (xs >= v.nx()) return gout ? gout[i * v.ny() + ys] : ghost_pop(v, false, ys, rho_out, i);
-      return v.at(i, xs, ys);
+    } else if (MODE == 1) {
+      if (xs < 0) return ghost_pop(v, true, ys, rho_in, i);
+      if (xs >= v.nx()) return ghost_pop(v, false, ys, rho_out, i);
+    } else if (MODE == 2) {
+      if (xs < 0) return gin[i * v.ny() + ys];
+      if (xs >= v.nx()) return gout[i * v.ny() + ys];
     }
+    return v.at(i, xs, ys);
+  }
+
+  // Branch-free form (MODES 2 and 3): every source address is selected
+  // first and all loads issue together, so a wave waits on memory once.
+  // A[i] is the population pulled into direction i, or for a wall-replaced
+  // direction its bounce-back part; B[k] (k = 0..3 for directions 5..8) is
+  // the specular part (Eq. 20), a duplicate of A's address off the walls.
+  __device__ __forceinline__ const double* addr(int i, int xs, int ys) const {
+    static_assert(MODE == 2 || MODE == 3, "addresses exist for MODES 2 and 3 only");
+    const double* p = v.P + v.g.index(i, xs, ys);
+    if (MODE == 2) {
+      p = xs < 0 ? gin + i * v.ny() + ys : p;
+      p = xs >= v.nx() ? gout + i * v.ny() + ys : p;
+    }
+    return p;
+  }
+
+  __device__ __forceinline__ void sources(int x, int y, double A[9], double B[4]) const {
+    const int t = v.ny() - 1;
+    const bool bot = y == 0, top = y == t;
+    const int ym = bot ? 0 : y - 1, yp = top ? t : y + 1;
+    const int xsm = shift ? x - 1 : x;
+    const int xsp = shift ? x + 1 : x;
+    const double* a[9];
+    const double* b[4];
+    a[0] = addr(0, x, y);
+    a[1] = addr(1, x - 1, y);
+    a[3] = addr(3, x + 1, y);
+    a[2] = bot ? addr(4, x, 0) : addr(2, x, ym);
+    a[5] = bot ? addr(7, x, 0) : addr(5, x - 1, ym);
+    a[6] = bot ? addr(8, x, 0) : addr(6, x + 1, ym);
+    a[4] = top ? addr(2, x, t) : addr(4, x, yp);
+    a[7] = top ? addr(5, x, t) : addr(7, x + 1, yp);
+    a[8] = top ? addr(6, x, t) : addr(8, x - 1, yp);
+    b[0] = bot ? addr(8, xsm, 0) : a[5];
+    b[1] = bot ? addr(7, xsp, 0) : a[6];
+    b[2] = top ? addr(6, xsp, t) : a[7];
+    b[3] = top ? addr(5, xsm, t) : a[8];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A[i] = *a[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) B[k] = *b[k];
+  }
+
+  __device__ __forceinline__ void combine(int y, const double A[9], const double B[4], double f[9]) const {
+#pragma clang fp contract(off)
+    const bool bot = y == 0, top = y == v.ny() - 1;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) f[i] = A[i];
+    f[5] = bot ? r * A[5] + omr * B[0] : A[5];
+    f[6] = bot ? r * A[6] + omr * B[1] : A[6];
+    f[7] = top ? r * A[7] + omr * B[2] : A[7];
+    f[8] = top ? r * A[8] + omr * B[3] : A[8];
+  }
+
+  // lp . d pre / d r of a wall node from its sources (Eq. 20); 0 off the walls.
+  __device__ __forceinline__ double wall_dr(int y, const double A[9], const double B[4], const double lp[9]) const {
+#pragma clang fp contract(off)
+    double dr = 0.0;
+    if (y == 0) {
+      dr += lp[5] * (A[5] - B[0]);
+      dr += lp[6] * (A[6] - B[1]);
+    }
+    if (y == v.ny() - 1) {
+      dr += lp[7] * (A[7] - B[2]);
+      dr += lp[8] * (A[8] - B[3]);
+    }
+    return dr;
+  }
+
+  __device__ __forceinline__ void flat(int x, int y, double f[9]) const {
+    double A[9], B[4];
+    sources(x, y, A, B);
+    combine(y, A, B, f);
   }
 
   __device__ __forceinline__ void operator()(int x, int y, double f[9]) const {
@@ -148,6 +229,15 @@ struct Gather {
     }
   }
 };
+
+// The gather of one node in the best form the mode allows.
+template <int MODE, class V>
+__device__ __forceinline__ void gather_node(const Gather<MODE, V>& g, int x, int y, double f[9]) {
+  if constexpr (MODE == 2 || MODE == 3)
+    g.flat(x, y, f);
+  else
+    g(x, y, f);
+}
 
 }  // namespace
 }  // namespace clb

@@ -79,30 +79,19 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 constexpr int PX = 16;   // column-sum diagnostics: 16 columns x 16 row lanes
 constexpr int PY = 16;
 
-template <int RY>
-__global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
-  constexpr int CX = 256 / RY;
-  extern __shared__ double s_ghost[];   // [2][9][ny] in the first / last workgroup
-  __shared__ double s_rc[2][CX];
+// One workgroup's columns; G is the gather variant of the workgroup (interior,
+// LDS ghosts or ghosts on the spot).  s_rc: [2][CX] centre-row densities.
+template <int RY, class G>
+__device__ __forceinline__ void pressure_columns(const StepArgs& a, const G& gat, double (*s_rc)[256 / RY]) {
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * CX + tx;
+  const int x = blockIdx.x * (256 / RY) + tx;
   const int ny = a.g.ny, yc = ny / 2;
   const bool even = (ny & 1) == 0;
-  const View v{a.src, a.g};
-  const bool edge_in = a.ghost_lds && blockIdx.x == 0;
-  const bool edge_out = a.ghost_lds && blockIdx.x == gridDim.x - 1;
-  double* gin = s_ghost;
-  double* gout = s_ghost + 9 * ny;
-  if (edge_in || edge_out)
-    fill_ghosts(v, a.rho_in, a.rho_out, edge_in, edge_out, gin, gout, ty * CX + tx, 256);
-  __syncthreads();
-  Gather<1, View> gat{v, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out, edge_in ? gin : nullptr,
-                      edge_out ? gout : nullptr};
   if (ny <= RY) {
     const bool active = x < a.g.nx && ty < ny;
     double f[9];
     if (active) {
-      gat(x, ty, f);
+      gather_node(gat, x, ty, f);
       if (ty == yc) s_rc[0][tx] = sum9(f);
       if (even && ty == yc - 1) s_rc[1][tx] = sum9(f);
     }
@@ -117,7 +106,7 @@ __global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
   }
   if (ty < 2 && x < a.g.nx && (ty == 0 || even)) {
     double f[9];
-    gat(x, yc - ty, f);
+    gather_node(gat, x, yc - ty, f);
     s_rc[ty][tx] = sum9(f);
   }
   __syncthreads();
@@ -128,9 +117,32 @@ __global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
   const Rates s{a.s3, snu, sq, a.s8};
   for (int y = ty; y < ny; y += RY) {
     double f[9];
-    gat(x, y, f);
+    gather_node(gat, x, y, f);
     collide<false>(f, 0.0, 0.0, s);
     store9(a.dst, a.g, x, y, f);
+  }
+}
+
+template <int RY>
+__global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
+  constexpr int CX = 256 / RY;
+  extern __shared__ double s_ghost[];   // [2][9][ny] in the first / last workgroup
+  __shared__ double s_rc[2][CX];
+  const View v{a.src, a.g};
+  const double omr = 1.0 - a.r;
+  const bool first = blockIdx.x == 0, last = blockIdx.x == gridDim.x - 1;
+  if (!first && !last) {
+    // every x - 1 and x + 1 of this workgroup lies inside the grid
+    pressure_columns<RY>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, s_rc);
+  } else if (a.ghost_lds) {
+    const int ny = a.g.ny;
+    fill_ghosts(v, a.rho_in, a.rho_out, first, last, s_ghost, s_ghost + 9 * ny,
+                threadIdx.y * CX + threadIdx.x, 256);
+    __syncthreads();
+    pressure_columns<RY>(
+        a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, s_rc);
+  } else {
+    pressure_columns<RY>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, s_rc);
   }
 }
 

@@ -88,6 +88,30 @@ def test_gradient_matches_complex_step(r_free):
     assert abs(g[1] - want[1]) <= 1e-9 * scale
 
 
+@pytest.mark.parametrize("nx,ny,T,K,shift", [
+    (49, 6, 30, 7, 1),     # 16-column workgroups, nx = 1 (mod 16): column nx - 2 in the second-to-last one
+    (50, 6, 30, 7, 1),     # column nx - 2 opens the last workgroup
+    (9, 70, 12, 4, 1),     # ny > 64: several rows per thread, nx = 1 (mod 4)
+    (17, 33, 16, 5, 0),    # odd ny, 4-column workgroups, literal Eq. (20) source
+])
+def test_gradient_workgroup_edges(nx, ny, T, K, shift):
+    """Whole-run gradients where the inlet/outlet columns fall across
+    workgroup boundaries of the reverse step, against complex-step."""
+    prm = C.Params(nx=nx, ny=ny, xbc="pressure", kn=0.15, p_ratio=1.8, cbbsr_shift=shift)
+    tgt = dataclasses.replace(prm, a=2.1, A2=0.52, r=0.64)
+    dps, ms = R.observables(R.run(tgt, T), tgt)
+    A1, r = C.resolved(prm)
+    ref_prm = dataclasses.replace(prm, A1=A1, r=r)
+    ref = R.complex_step_grad(ref_prm, T, dps, ms)
+    adj = _adjoint(prm, T, K)
+    L = adj.forward(torch.from_numpy(dps), ms)
+    assert abs(L - R.loss(ref_prm, T, dps, ms)) <= 1e-10 * abs(L)
+    g = adj.backward()
+    want = np.array([ref["a"], ref["A2"], ref["r"]])
+    assert np.max(np.abs(g[[0, 2, 3]] - want)) <= 1e-9 * np.max(np.abs(want))
+    assert g[1] == 0.0
+
+
 def test_checkpoint_interval_does_not_change_gradients():
     T = 37
     prm, dps, ms = _case(nx=40, ny=5, T=T)
