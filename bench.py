@@ -30,6 +30,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched Kn-sweep comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--part", choices=("all", "step", "sweep", "adjoint"), default="all",
+                    help="run one part alone (step: the periodic step only; sweep / adjoint: that "
+                         "measurement only, printed as its own JSON line) -- for profiling runs")
+    ap.add_argument("--no-loop-baseline", action="store_true",
+                    help="sweep: skip the loop-of-solvers baselines (profiling the batched kernel)")
     ap.add_argument("--block-x", type=int, default=1024)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -72,7 +77,7 @@ def traffic_from_profile():
     return float(rec["bytes_per_launch"])
 
 
-def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12):
+def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True):
     """Batched Kn sweep (64 periodic channels, heights from {16..128}, Kn
     log-spaced 0.01-10, g = 1e-6, each to steady state) in one persistent
     launch, against a loop of single-channel solvers with the same check
@@ -118,9 +123,12 @@ def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12):
             s.close()
         return dt, steps
 
+    kmin = float(np.array(kns)[int(np.argmin(q))])
+    if not baselines:
+        return {"channels": len(params), "all_converged": bool(conv.all()),
+                "steps_total": int(steps_b.sum()), "batched_s": round(t_batch, 4), "kn_at_min_Q": kmin}
     t_loop, steps_l = loop(graph=False)
     t_graph, _ = loop(graph=True)
-    kmin = float(np.array(kns)[int(np.argmin(q))])
     return {
         "channels": len(params), "check_every": check_every, "tol": tol,
         "all_converged": bool(conv.all()),
@@ -208,6 +216,12 @@ def main():
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
         return
+    if args.part == "sweep":
+        print(json.dumps({"kn_sweep": kn_sweep(baselines=not args.no_loop_baseline)}), flush=True)
+        return
+    if args.part == "adjoint":
+        print(json.dumps({"adjoint": adjoint_calibration()}), flush=True)
+        return
     import torch
     from paper_1603_01955_amd import Solver
 
@@ -255,8 +269,11 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if args.part == "step":
+        print(json.dumps(rec), flush=True)
+        return
     if not args.no_sweep:
-        rec["kn_sweep"] = kn_sweep()
+        rec["kn_sweep"] = kn_sweep(baselines=not args.no_loop_baseline)
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_calibration()
     if not args.no_cpu_baseline:
