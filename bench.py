@@ -124,15 +124,18 @@ def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True):
         return dt, steps
 
     kmin = float(np.array(kns)[int(np.argmin(q))])
+    updates = int(sum(4 * int(ny) * int(n) for ny, n in zip(heights, steps_b)))   # node updates
     if not baselines:
         return {"channels": len(params), "all_converged": bool(conv.all()),
-                "steps_total": int(steps_b.sum()), "batched_s": round(t_batch, 4), "kn_at_min_Q": kmin}
+                "steps_total": int(steps_b.sum()), "node_updates": updates, "batched_s": round(t_batch, 4),
+                "batched_mlups": round(updates / t_batch / 1e6, 1), "kn_at_min_Q": kmin}
     t_loop, steps_l = loop(graph=False)
     t_graph, _ = loop(graph=True)
     return {
         "channels": len(params), "check_every": check_every, "tol": tol,
         "all_converged": bool(conv.all()),
-        "steps_total": int(steps_b.sum()), "steps_max": int(steps_b.max()),
+        "steps_total": int(steps_b.sum()), "steps_max": int(steps_b.max()), "node_updates": updates,
+        "batched_mlups": round(updates / t_batch / 1e6, 1),
         "loop_steps_match": bool((np.array(steps_l) == steps_b).all()),
         "batched_s": round(t_batch, 4), "loop_s": round(t_loop, 4), "graph_loop_s": round(t_graph, 4),
         "speedup_vs_loop": round(t_loop / t_batch, 2), "speedup_vs_graph_loop": round(t_graph / t_batch, 2),
