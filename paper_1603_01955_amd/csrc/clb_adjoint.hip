@@ -56,6 +56,7 @@ struct AdjArgs {
   double s3, s8;
   double kn, a, A2, tq_den, c_tau;
   double rho_in, rho_out;
+  int xcd_remap;         // XCD-aware workgroup order (see logical_block)
 };
 
 // lpre . d pre / d r for the wall-replaced entries of node (x, y) (Eq. 20),
@@ -270,20 +271,20 @@ __device__ __forceinline__ void adj_node_inputs(const AdjArgs& a, const Gather<X
 }
 
 template <int RY, bool PULL, int XB>
-__device__ __forceinline__ void adj_columns(const AdjArgs& a, const Gather<XB == 3 ? 3 : 2, View>& gat,
+__device__ __forceinline__ void adj_columns(const AdjArgs& a, const Gather<XB == 3 ? 3 : 2, View>& gat, int blk,
                                             AdjShared<RY>& sh) {
 #pragma clang fp contract(off)
   constexpr int CX = 256 / RY;
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * CX + tx;
+  const int x = blk * CX + tx;
   const int nx = a.g.nx, ny = a.g.ny;
   const bool lead = tx == 0 && ty == 0;
   // this workgroup's running gradient partials, fetched early
   double gp0 = 0.0, gp1 = 0.0, gp2 = 0.0;
   if (lead) {
-    gp0 = a.gpart[3 * blockIdx.x];
-    gp1 = a.gpart[3 * blockIdx.x + 1];
-    gp2 = a.gpart[3 * blockIdx.x + 2];
+    gp0 = a.gpart[3 * blk];
+    gp1 = a.gpart[3 * blk + 1];
+    gp2 = a.gpart[3 * blk + 2];
   }
   const int yc = ny / 2;
   const bool even = (ny & 1) == 0;
@@ -410,9 +411,9 @@ __device__ __forceinline__ void adj_columns(const AdjArgs& a, const Gather<XB ==
       sA2 += sh.cA2[k];
       sr += sh.cr[k];
     }
-    a.gpart[3 * blockIdx.x] = gp0 + sa;
-    a.gpart[3 * blockIdx.x + 1] = gp1 + sA2;
-    a.gpart[3 * blockIdx.x + 2] = gp2 + sr;
+    a.gpart[3 * blk] = gp0 + sa;
+    a.gpart[3 * blk + 1] = gp1 + sA2;
+    a.gpart[3 * blk + 2] = gp2 + sr;
   }
 }
 
@@ -426,12 +427,13 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjArgs a) {
   const View v{a.P, a.g};
   const double omr = 1.0 - a.r;
   const int ny = a.g.ny;
-  const bool interior = blockIdx.x > 0 && (int)(blockIdx.x + 1) * CX <= a.g.nx - 2;
+  const int blk = logical_block(a.xcd_remap);
+  const bool interior = blk > 0 && (blk + 1) * CX <= a.g.nx - 2;
   if (interior)
-    adj_columns<RY, PULL, 3>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, sh);
+    adj_columns<RY, PULL, 3>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, sh);
   else
     adj_columns<RY, PULL, 1>(a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, a.gh, a.gh + 9 * ny},
-                             sh);
+                             blk, sh);
 }
 
 // lambda_n = G^T lpre (+ reverse of the ghost columns), one thread per node.
@@ -626,7 +628,7 @@ clb::StepArgs adj_step_args(const clb_adjoint* a, const double* src, double* dst
   s.g = a->g;
   s.mode = 1;
   s.shift = a->p.cbbsr_shift;
-  s.xcd_remap = 0;
+  s.xcd_remap = 1;
   s.r = a->d.r;
   s.s3 = a->p.s3;
   s.snu = a->d.s_nu;
@@ -659,6 +661,7 @@ clb::AdjArgs adj_args(const clb_adjoint* a, const double* P, double* lpre) {
   r.c_tau = std::sqrt(6.0 / M_PI) * (double)a->p.ny;
   r.rho_in = a->p.p_ratio * a->p.rho_out;
   r.rho_out = a->p.rho_out;
+  r.xcd_remap = 1;
   return r;
 }
 

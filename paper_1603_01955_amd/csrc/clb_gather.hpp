@@ -11,6 +11,20 @@
 namespace clb {
 namespace {
 
+// Block index with optional XCD-aware remap: blocks are dealt to the 8 XCDs
+// round-robin, so logical block (xcd * per + k) makes each XCD walk a
+// contiguous run of row segments or columns (cache lines shared by
+// neighbouring workgroups stay in one L2).
+__device__ __forceinline__ int logical_block(int remap) {
+  int b = blockIdx.x;
+  if (remap) {
+    const int nb = gridDim.x;
+    const int per = nb >> 3;
+    if (b < (per << 3)) b = (b & 7) * per + (b >> 3);
+  }
+  return b;
+}
+
 // ---------------------------------------------------------------------------
 // Gather of the pre-collision populations of node (x, y).
 // MODE 0: periodic x.

@@ -33,19 +33,6 @@ __device__ __forceinline__ void store9(double* __restrict__ Q, const Geo& g, int
   for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], Q + base + (size_t)i * stride);
 }
 
-// Block index with optional XCD-aware remap: blocks are dealt to the 8 XCDs
-// round-robin, so logical block (xcd * per + k) makes each XCD walk a
-// contiguous run of row segments (shared edge cache lines stay in one L2).
-__device__ __forceinline__ int logical_block(int remap) {
-  int b = blockIdx.x;
-  if (remap) {
-    const int nb = gridDim.x;
-    const int per = nb >> 3;
-    if (b < (per << 3)) b = (b & 7) * per + (b >> 3);
-  }
-  return b;
-}
-
 // ---------------------------------------------------------------------------
 // K1: fused periodic step.  One thread per node; threads enumerate the
 // padded nodes in device-layout order (y, segment, lane).
@@ -82,9 +69,9 @@ constexpr int PY = 16;
 // One workgroup's columns; G is the gather variant of the workgroup (interior,
 // LDS ghosts or ghosts on the spot).  s_rc: [2][CX] centre-row densities.
 template <int RY, class G>
-__device__ __forceinline__ void pressure_columns(const StepArgs& a, const G& gat, double (*s_rc)[256 / RY]) {
+__device__ __forceinline__ void pressure_columns(const StepArgs& a, const G& gat, int blk, double (*s_rc)[256 / RY]) {
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * (256 / RY) + tx;
+  const int x = blk * (256 / RY) + tx;
   const int ny = a.g.ny, yc = ny / 2;
   const bool even = (ny & 1) == 0;
   if (ny <= RY) {
@@ -130,19 +117,20 @@ __global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
   __shared__ double s_rc[2][CX];
   const View v{a.src, a.g};
   const double omr = 1.0 - a.r;
-  const bool first = blockIdx.x == 0, last = blockIdx.x == gridDim.x - 1;
+  const int blk = logical_block(a.xcd_remap);
+  const bool first = blk == 0, last = blk == (int)gridDim.x - 1;
   if (!first && !last) {
     // every x - 1 and x + 1 of this workgroup lies inside the grid
-    pressure_columns<RY>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, s_rc);
+    pressure_columns<RY>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc);
   } else if (a.ghost_lds) {
     const int ny = a.g.ny;
     fill_ghosts(v, a.rho_in, a.rho_out, first, last, s_ghost, s_ghost + 9 * ny,
                 threadIdx.y * CX + threadIdx.x, 256);
     __syncthreads();
     pressure_columns<RY>(
-        a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, s_rc);
+        a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, blk, s_rc);
   } else {
-    pressure_columns<RY>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, s_rc);
+    pressure_columns<RY>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc);
   }
 }
 

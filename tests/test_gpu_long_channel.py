@@ -1,0 +1,98 @@
+"""The pressure-driven long channel of Section 3.2 (Liu & He,
+arXiv:1603.01955) at the shape of its figures, L/H = 100 with H = 40
+(4000 x 40), pressure ratio 2, run to steady state on the GPU.
+
+The paper delegates its inlet/outlet scheme to an external reference, so no
+printed number fixes the steady state (parity against the paper unpinned).
+These tests check the GPU run against the CPU reference over the first steps
+and then what any correct steady state of this flow must satisfy: uniform
+mass flow, mirror symmetry, a positive deviation from the linear pressure
+that shrinks as Kn_out grows from 0.194 to 0.388, slip growing downstream,
+and the lubrication model at Kn_out = 0.1.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import analytic as A
+from oracle import clb_ref as C
+
+pytestmark = pytest.mark.gpu
+
+NX, NY = 4000, 40
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+
+
+def _solver(kn):
+    from paper_1603_01955_amd import Solver
+    return Solver(nx=NX, ny=NY, xbc="pressure", kn=kn, p_ratio=2.0, init="linear_rho")
+
+
+def _steady(kn, tol=1e-6, chunk=100000, cap=2000000):
+    s = _solver(kn)
+    n = 0
+    while n < cap:
+        s.step(chunk)
+        n += chunk
+        m = s.massflow()[0].cpu().numpy()
+        if (m.max() - m.min()) / m.mean() <= tol:
+            return s, n
+    raise AssertionError("no steady state within %d steps at Kn_out = %g" % (cap, kn))
+
+
+@pytest.fixture(scope="module")
+def steady():
+    return {kn: _steady(kn)[0] for kn in (0.1, 0.194, 0.388)}
+
+
+def test_first_steps_match_reference():
+    s = _solver(0.1)
+    s.step(4)
+    P = s.populations().cpu().numpy()
+    prm = C.Params(nx=NX, ny=NY, xbc="pressure", kn=0.1, p_ratio=2.0)
+    Pref = C.run(C.init_linear_rho(prm), prm, 4)
+    assert np.max(np.abs(P - Pref)) <= 1e-10 * np.max(np.abs(Pref))
+
+
+def test_mass_flow_uniform_and_symmetric(steady):
+    for kn, s in steady.items():
+        m = s.massflow()[0].cpu().numpy()
+        assert (m.max() - m.min()) / m.mean() <= 1e-6, kn
+        _, ux, uy = (t.cpu().numpy() for t in s.moments())
+        scale = np.max(np.abs(ux))
+        assert np.max(np.abs(ux - ux[::-1])) <= 1e-12 * scale, kn
+        assert np.max(np.abs(uy + uy[::-1])) <= 1e-12 * scale, kn
+
+
+def test_deviation_positive_and_shrinking_with_kn(steady):
+    peaks = []
+    for kn in (0.1, 0.194, 0.388):
+        dp = steady[kn].pressure_deviation()[0].cpu().numpy()
+        assert dp[20:-20].min() > 0, kn
+        peaks.append(dp.max())
+    assert peaks[0] > peaks[1] > peaks[2]
+
+
+def test_slip_grows_downstream(steady):
+    for kn, s in steady.items():
+        _, ux, _ = (t.cpu().numpy() for t in s.moments())
+        slip = ux[0] / ux.max(axis=0)
+        assert slip[NX // 40] < slip[NX // 2] < slip[NX - NX // 40], kn
+
+
+def test_lubrication_model_at_kn_0_1(steady):
+    s = steady[0.1]
+    m = s.massflow()[0].cpu().numpy().mean()
+    dp = s.pressure_deviation()[0].cpu().numpy()
+    A1, _ = C.resolved(C.Params(nx=NX, ny=NY, xbc="pressure", kn=0.1))
+    m_lub, p_lub = A.lubrication_profile(NX, NY, 0.1, 2.0, 2.0, A1, 0.55, nsub=2)
+    p_out = 1.0 / 3.0
+    x = np.arange(NX) + 0.5
+    dp_lub = (np.asarray(p_lub) - (2.0 * p_out - p_out * x / NX)) / p_out
+    assert abs(m / m_lub - 1) < 0.02
+    assert abs(dp.max() / dp_lub.max() - 1) < 0.05

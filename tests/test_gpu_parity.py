@@ -105,6 +105,9 @@ def test_launch_shapes_bitwise_identical():
     (dict(nx=2, ny=3, xbc="pressure", kn=0.05, p_ratio=1.4), 50, "linear"),
     (dict(nx=130, ny=5, xbc="pressure", kn=0.388, p_ratio=1.8, sigma=0.93), 40, "random"),
     (dict(nx=64, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, cbbsr_shift=0), 60, "linear"),
+    (dict(nx=149, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0), 60, "linear"),      # 64-row tiles, nx = 1 (mod 4)
+    (dict(nx=50, ny=70, xbc="pressure", kn=0.2, p_ratio=1.5, cbbsr_shift=0), 40, "random"),  # rows looped
+    (dict(nx=1030, ny=20, xbc="pressure", kn=0.194, p_ratio=2.0), 30, "linear"),   # 129 workgroups, remap tail
 ])
 def test_pressure_mode(kw, steps, start):
     prm = _oracle_params(kw)
