@@ -189,6 +189,27 @@ def adjoint_calibration(T=2000, K=45, repeats=3):
             "backward_over_forward": round(b / f, 3)}
 
 
+def pressure_step(nx=4000, ny=40, steps=20000):
+    """The pressure-driven step of Section 3.2 at its figure shape (L/H = 100,
+    H = 40, ratio 2, Kn_out = 0.1, linear-density start): time per step with
+    HIP events on the solver's stream."""
+    import torch
+    from paper_1603_01955_amd import Solver
+    s = Solver(nx=nx, ny=ny, xbc="pressure", kn=0.1, p_ratio=2.0, init="linear_rho")
+    s.step(200)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    s.close()
+    return {"workload": "pressure_%dx%d" % (nx, ny), "steps": steps, "us_per_step": round(us, 3),
+            "mlups": round(nx * ny / us, 1), "algorithmic_gbs": round(BYTES_PER_NODE * nx * ny / us / 1e3, 1)}
+
+
 def cpu_baseline():
     """The CPU reference, as it stands, on a bounded sample of the workload:
     CPU_SAMPLE_STEPS steps of a 32768 x CPU_SAMPLE_ROWS slab of the same
@@ -277,6 +298,7 @@ def main():
         return
     if not args.no_sweep:
         rec["kn_sweep"] = kn_sweep(baselines=not args.no_loop_baseline)
+    rec["pressure_step"] = pressure_step()
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_calibration()
     if not args.no_cpu_baseline:

@@ -70,6 +70,49 @@ def test_channel_4x32_full_run():
     assert abs(Q / A.discrete_Q(32, 0.1, 2.0, 0.55, r) - 1) <= 1e-6
 
 
+def _gpu_steady(kw, chunk=1000, cap=200000, tol=1e-13):
+    s = _solver(**kw)
+    prev = None
+    for _ in range(cap // chunk):
+        s.step(chunk)
+        cur = s.flow_rate()
+        if prev is not None and abs(cur - prev) <= tol * abs(cur):
+            break
+        prev = cur
+    return s
+
+
+def test_channel_slip_excess_and_denominator_24():
+    """P12 on the GPU: with Eq. (21) as printed the steady flow of the 4 x 32
+    channel exceeds the continuum second-order slip profile (Eq. 19) by
+    3g/(16 tt) + (pi/4) B2 tt g per row (+1.62%); with 24 in place of 16 it
+    reproduces that profile."""
+    from math import pi
+    prm = C.Params(nx=4, ny=32, kn=0.1, gx=1e-6)
+    A1, _ = C.resolved(prm)
+    cont = A.continuum_sum_u(32, 0.1, 2.0, A1, 0.55, 1e-6)
+    tt = C.tau_tilde(0.1, 32, 2.0)
+    excess = 32 * (3e-6 / (16 * tt) + pi / 4 * 0.55 * tt * 1e-6)
+    s = _gpu_steady(dict(nx=4, ny=32, kn=0.1, gx=1e-6))
+    su = float(s.moments()[1].cpu().numpy()[:, 0].sum())
+    assert abs(su - cont - excess) <= 1e-6 * cont
+    assert 0.0160 < su / cont - 1 < 0.0165
+    s24 = _gpu_steady(dict(nx=4, ny=32, kn=0.1, gx=1e-6, tq_den=24.0))
+    su24 = float(s24.moments()[1].cpu().numpy()[:, 0].sum())
+    assert abs(su24 / cont - 1) <= 1e-6
+
+
+def test_channel_no_slip_parabola():
+    """P13 on the GPU: r = 1 with (tau_s - 1/2)(tau_q - 1/2) = 1/8 (B2 = 0,
+    denominator 24) gives the exact no-slip parabola (3g / (2 tt)) y (H - y)."""
+    s = _gpu_steady(dict(nx=4, ny=16, kn=0.1, gx=1e-6, r=1.0, A2=0.0, tq_den=24.0))
+    ux = s.moments()[1].cpu().numpy()[:, 0]
+    tt = C.tau_tilde(0.1, 16, 2.0)
+    y = np.arange(16) + 0.5
+    ref = 1.5e-6 / tt * y * (16 - y)
+    assert np.max(np.abs(ux - ref)) <= 1e-6 * ref.max()
+
+
 @pytest.mark.parametrize("kw,steps", [
     (dict(nx=77, ny=13, kn=0.5, gx=1e-3, gy=2e-4), 40),      # ragged, force in x and y
     (dict(nx=300, ny=3, kn=2.0, gx=1e-4, cbbsr_shift=0), 40),   # literal Eq. (20) source
