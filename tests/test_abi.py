@@ -110,3 +110,60 @@ def test_null_arguments(lib):
     assert lib.clb_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == clb.CLB_EINVAL
     assert lib.clb_init(ctypes.byref(p), ctypes.c_void_p(4096), 16, None, ctypes.byref(out)) == clb.CLB_ENOMEM
     assert out.value is None
+
+
+def test_batch_validation(lib):
+    """Batched channels are periodic, start from a uniform or perturbed state,
+    and the workspace holds at least every channel's populations."""
+    Params = clb.clb_params * 3
+    ps = Params(clb.make_params(4, 16, kn=0.1, gx=1e-6), clb.make_params(4, 32, kn=1.0, gx=1e-6),
+                clb.make_params(2, 8, kn=3.0))
+    n = ctypes.c_size_t()
+    assert lib.clb_batch_workspace_size(ctypes.c_int32(3), ps, ctypes.byref(n)) == clb.CLB_OK
+    assert n.value >= 72 * (4 * 16 + 4 * 32 + 2 * 8)
+    assert lib.clb_batch_workspace_size(ctypes.c_int32(0), ps, ctypes.byref(n)) == clb.CLB_EINVAL
+    assert lib.clb_batch_workspace_size(ctypes.c_int32(3), ps, None) == clb.CLB_EINVAL
+    bad = Params(ps[0], clb.make_params(10, 8, xbc="pressure"), ps[2])
+    assert lib.clb_batch_workspace_size(ctypes.c_int32(3), bad, ctypes.byref(n)) == clb.CLB_EINVAL
+    assert "periodic" in lib.clb_last_error().decode()
+    bad = Params(ps[0], ps[1], clb.make_params(4, 8, init="linear_rho"))
+    assert lib.clb_batch_workspace_size(ctypes.c_int32(3), bad, ctypes.byref(n)) == clb.CLB_EINVAL
+    bad = Params(ps[0], ps[1], clb.make_params(4, 8, kn=-1.0))
+    assert lib.clb_batch_workspace_size(ctypes.c_int32(3), bad, ctypes.byref(n)) == clb.CLB_EINVAL
+    out = ctypes.c_void_p()
+    assert lib.clb_batch_init(ctypes.c_int32(3), ps, None, ctypes.c_size_t(0), None,
+                              ctypes.byref(out)) == clb.CLB_EINVAL
+    assert lib.clb_batch_init(ctypes.c_int32(3), ps, ctypes.c_void_p(4096), ctypes.c_size_t(16), None,
+                              ctypes.byref(out)) == clb.CLB_ENOMEM
+    assert out.value is None
+    assert lib.clb_batch_run(None, ctypes.c_int64(10), ctypes.c_int32(0), ctypes.c_double(0.0), None,
+                             None) == clb.CLB_EINVAL
+    assert lib.clb_batch_destroy(None) == clb.CLB_EINVAL
+
+
+def test_adjoint_validation(lib):
+    """The adjoint covers the pressure-driven channel, T >= 1, 1 <= K <= T;
+    its workspace holds the checkpoints and two recompute sets."""
+    p = clb.make_params(200, 10, xbc="pressure", kn=0.1, p_ratio=2.0)
+    n = ctypes.c_size_t()
+    assert lib.clb_adjoint_workspace_size(ctypes.byref(p), ctypes.c_int32(100), ctypes.c_int32(10),
+                                          ctypes.byref(n)) == clb.CLB_OK
+    state = 72 * 256 * 10                     # one state buffer, rows padded to 256 lanes
+    assert n.value >= (10 + 2 * 9 + 4) * state
+    for T, K in ((0, 1), (10, 0), (10, 11)):
+        assert lib.clb_adjoint_workspace_size(ctypes.byref(p), ctypes.c_int32(T), ctypes.c_int32(K),
+                                              ctypes.byref(n)) == clb.CLB_EINVAL
+    q = clb.make_params(200, 10, kn=0.1)
+    assert lib.clb_adjoint_workspace_size(ctypes.byref(q), ctypes.c_int32(10), ctypes.c_int32(2),
+                                          ctypes.byref(n)) == clb.CLB_EINVAL
+    assert "pressure" in lib.clb_last_error().decode()
+    out = ctypes.c_void_p()
+    assert lib.clb_adjoint_init(ctypes.byref(p), ctypes.c_int32(10), ctypes.c_int32(2), None,
+                                ctypes.c_size_t(0), None, ctypes.byref(out)) == clb.CLB_EINVAL
+    assert lib.clb_adjoint_init(ctypes.byref(p), ctypes.c_int32(10), ctypes.c_int32(2), ctypes.c_void_p(4096),
+                                ctypes.c_size_t(16), None, ctypes.byref(out)) == clb.CLB_ENOMEM
+    assert out.value is None
+    g = (ctypes.c_double * 4)()
+    assert lib.clb_adjoint_forward(None, None, ctypes.c_double(1.0), None) == clb.CLB_EINVAL
+    assert lib.clb_adjoint_backward(None, g) == clb.CLB_EINVAL
+    assert lib.clb_adjoint_destroy(None) == clb.CLB_EINVAL
