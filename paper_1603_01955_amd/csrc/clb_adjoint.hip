@@ -254,7 +254,7 @@ __device__ __forceinline__ void adj_node_inputs(const AdjArgs& a, const Gather<X
   if (need_in) ghost_sources<true>(a, a.lin, a.Pn1, y, gi);
   if (need_out) ghost_sources<false>(a, a.lin, a.Pn1, y, go);
   double Lp[9], Lq[4];
-  gat.sources(x, y, A, B);
+  gat.template load_sources<false>(x, y, A, B);
   if (PULL) {
     tg_sources<XB>(a, a.lin, x, y, Lp, Lq);
   } else {

@@ -28,12 +28,12 @@ __device__ __forceinline__ int logical_block(int remap) {
 // ---------------------------------------------------------------------------
 // Gather of the pre-collision populations of node (x, y).
 // MODE 0: periodic x.
-// MODE 1: pressure ghost columns at x = -1 and x = nx, evaluated on the spot.
-// MODE 2: pressure ghost columns read from LDS (gin, gout: [9][ny] each).
+// MODE 1: pressure ghost columns at x = -1 and x = nx; the nodes of the first
+//         and last column evaluate the ghost populations they pull inline.
+// MODE 2: pressure ghost columns read from precomputed arrays gin, gout
+//         ([9][ny] each, in LDS or global memory).
 // MODE 3: a node whose x - 1 and x + 1 both lie inside the grid (interior
 //         workgroups of the pressure kernels): no x-boundary code at all.
-// Modes 2 and 3 keep out-of-line calls (and the full memory waits a call
-// implies) out of the kernels that run every step.
 // ---------------------------------------------------------------------------
 // Populations in the device layout of a single-channel buffer (HBM).
 struct View {
@@ -80,16 +80,37 @@ __device__ __forceinline__ void ghost_row(const V& v, bool inlet, int y, double 
   for (int k = 0; k < 9; ++k) g[k] = eg[k] + (f1[k] - e1[k]);
 }
 
-// Population i of a ghost column, evaluated on the spot.
+// One factor of the product-form equilibrium (as in `equilibrium`) for a
+// velocity component e = -1, 0, +1.
+__device__ __forceinline__ double eq_factor(int e, double u) {
+#pragma clang fp contract(off)
+  return e == 0 ? 2.0 / 3.0 - u * u : (e > 0 ? 0.5 * (1.0 / 3.0 + u * u + u) : 0.5 * (1.0 / 3.0 + u * u - u));
+}
+
+// Population i of the ghost column at row y, evaluated inline: the same
+// arithmetic as ghost_row for that one direction (bitwise the same value).
 template <class V>
-__device__ __noinline__ double ghost_pop(V v, bool inlet, int y, double rho_b, int i) {
-  double g[9];
-  ghost_row(v, inlet, y, rho_b, g);
-  double out = g[0];
+__device__ __forceinline__ double ghost_value(const V& v, bool inlet, int y, double rho_b, int i) {
+#pragma clang fp contract(off)
+  const int c1 = inlet ? 0 : v.nx() - 1;
+  const int c2 = inlet ? 1 : v.nx() - 2;
+  double f1[9], f2[9];
 #pragma unroll
-  for (int k = 1; k < 9; ++k)
-    if (k == i) out = g[k];
-  return out;
+  for (int k = 0; k < 9; ++k) {
+    f1[k] = v.at(k, c1, y);
+    f2[k] = v.at(k, c2, y);
+  }
+  double rho1, ux1, uy1, rho2, ux2, uy2;
+  rho_u(f1, rho1, ux1, uy1);
+  rho_u(f2, rho2, ux2, uy2);
+  const int ex = (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+  const int ey = (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+  double f1i = f1[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) f1i = k == i ? f1[k] : f1i;
+  const double eg = (2.0 * rho_b - rho1) * eq_factor(ex, 2.0 * ux1 - ux2) * eq_factor(ey, 2.0 * uy1 - uy2);
+  const double e1 = rho1 * eq_factor(ex, ux1) * eq_factor(ey, uy1);
+  return eg + (f1i - e1);
 }
 
 // Largest ny whose two ghost columns ([2][9][ny] doubles) are staged in LDS.
@@ -122,7 +143,7 @@ struct Gather {
   double r, omr;        // bounce-back fraction r and 1 - r (Eq. 20)
   int shift;            // specular source from x -/+ 1 (1) or the same node (0)
   double rho_in, rho_out;
-  // MODE 2: ghost columns [9][ny] (LDS) for x = -1 and x = nx.
+  // MODE 2: ghost columns [9][ny] for x = -1 and x = nx.
   const double* gin = nullptr;
   const double* gout = nullptr;
 
@@ -132,8 +153,8 @@ struct Gather {
       if (xs < 0) xs += v.nx();
       else if (xs >= v.nx()) xs -= v.nx();
     } else if (MODE == 1) {
-      if (xs < 0) return ghost_pop(v, true, ys, rho_in, i);
-      if (xs >= v.nx()) return ghost_pop(v, false, ys, rho_out, i);
+      if (xs < 0) return ghost_value(v, true, ys, rho_in, i);
+      if (xs >= v.nx()) return ghost_value(v, false, ys, rho_out, i);
     } else if (MODE == 2) {
       if (xs < 0) return gin[i * v.ny() + ys];
       if (xs >= v.nx()) return gout[i * v.ny() + ys];
@@ -141,22 +162,41 @@ struct Gather {
     return v.at(i, xs, ys);
   }
 
-  // Branch-free form (MODES 2 and 3): every source address is selected
-  // first and all loads issue together, so a wave waits on memory once.
+  // Branch-free form (MODES 1-3): every source address is selected first
+  // and all loads issue together, so a wave waits on memory once.
   // A[i] is the population pulled into direction i, or for a wall-replaced
   // direction its bounce-back part; B[k] (k = 0..3 for directions 5..8) is
   // the specular part (Eq. 20), a duplicate of A's address off the walls.
+  // MODE 2 addresses a ghost source in gin / gout directly.  With CLAMP
+  // (always for MODE 1) a ghost source is loaded from a clamped in-grid
+  // address instead and its value replaced afterwards (patch_ghosts), so the
+  // loads can be issued before the ghost values exist.
+  template <bool CLAMP>
   __device__ __forceinline__ const double* addr(int i, int xs, int ys) const {
-    static_assert(MODE == 2 || MODE == 3, "addresses exist for MODES 2 and 3 only");
-    const double* p = v.P + v.g.index(i, xs, ys);
-    if (MODE == 2) {
+    static_assert(MODE >= 1 && MODE <= 3, "addresses exist for the pressure modes only");
+    if (MODE == 3) return v.P + v.g.index(i, xs, ys);
+    const int xc = xs < 0 ? 0 : (xs >= v.nx() ? v.nx() - 1 : xs);
+    const double* p = v.P + v.g.index(i, xc, ys);
+    if (MODE == 2 && !CLAMP) {
       p = xs < 0 ? gin + i * v.ny() + ys : p;
       p = xs >= v.nx() ? gout + i * v.ny() + ys : p;
     }
     return p;
   }
 
+  // Population i of ghost row ys (inlet or outlet side).
+  __device__ __forceinline__ double ghost(bool inlet, int ys, int i) const {
+    if (MODE == 2) return (inlet ? gin : gout)[i * v.ny() + ys];
+    return ghost_value(v, inlet, ys, inlet ? rho_in : rho_out, i);
+  }
+
   __device__ __forceinline__ void sources(int x, int y, double A[9], double B[4]) const {
+    load_sources<MODE == 1>(x, y, A, B);
+    if (MODE == 1) patch_ghosts(x, y, A, B);
+  }
+
+  template <bool CLAMP>
+  __device__ __forceinline__ void load_sources(int x, int y, double A[9], double B[4]) const {
     const int t = v.ny() - 1;
     const bool bot = y == 0, top = y == t;
     const int ym = bot ? 0 : y - 1, yp = top ? t : y + 1;
@@ -164,23 +204,54 @@ struct Gather {
     const int xsp = shift ? x + 1 : x;
     const double* a[9];
     const double* b[4];
-    a[0] = addr(0, x, y);
-    a[1] = addr(1, x - 1, y);
-    a[3] = addr(3, x + 1, y);
-    a[2] = bot ? addr(4, x, 0) : addr(2, x, ym);
-    a[5] = bot ? addr(7, x, 0) : addr(5, x - 1, ym);
-    a[6] = bot ? addr(8, x, 0) : addr(6, x + 1, ym);
-    a[4] = top ? addr(2, x, t) : addr(4, x, yp);
-    a[7] = top ? addr(5, x, t) : addr(7, x + 1, yp);
-    a[8] = top ? addr(6, x, t) : addr(8, x - 1, yp);
-    b[0] = bot ? addr(8, xsm, 0) : a[5];
-    b[1] = bot ? addr(7, xsp, 0) : a[6];
-    b[2] = top ? addr(6, xsp, t) : a[7];
-    b[3] = top ? addr(5, xsm, t) : a[8];
+    a[0] = addr<CLAMP>(0, x, y);
+    a[1] = addr<CLAMP>(1, x - 1, y);
+    a[3] = addr<CLAMP>(3, x + 1, y);
+    a[2] = bot ? addr<CLAMP>(4, x, 0) : addr<CLAMP>(2, x, ym);
+    a[5] = bot ? addr<CLAMP>(7, x, 0) : addr<CLAMP>(5, x - 1, ym);
+    a[6] = bot ? addr<CLAMP>(8, x, 0) : addr<CLAMP>(6, x + 1, ym);
+    a[4] = top ? addr<CLAMP>(2, x, t) : addr<CLAMP>(4, x, yp);
+    a[7] = top ? addr<CLAMP>(5, x, t) : addr<CLAMP>(7, x + 1, yp);
+    a[8] = top ? addr<CLAMP>(6, x, t) : addr<CLAMP>(8, x - 1, yp);
+    b[0] = bot ? addr<CLAMP>(8, xsm, 0) : a[5];
+    b[1] = bot ? addr<CLAMP>(7, xsp, 0) : a[6];
+    b[2] = top ? addr<CLAMP>(6, xsp, t) : a[7];
+    b[3] = top ? addr<CLAMP>(5, xsm, t) : a[8];
 #pragma unroll
     for (int i = 0; i < 9; ++i) A[i] = *a[i];
 #pragma unroll
     for (int k = 0; k < 4; ++k) B[k] = *b[k];
+  }
+
+  // The ghost populations node (x, y) pulls (MODES 1, 2).  A first-column node
+  // pulls direction 1 from ghost row y, 5 from row y - 1 and 8 from row
+  // y + 1; on a wall row the ghost enters as the specular partner instead
+  // (8 at the bottom, 5 at the top, when the source is shifted).  The last
+  // column mirrors this with 3, 6, 7.
+  __device__ __forceinline__ void patch_ghosts(int x, int y, double A[9], double B[4]) const {
+    const int t = v.ny() - 1;
+    const bool bot = y == 0, top = y == t;
+    const int rlo = bot ? 0 : y - 1, rhi = top ? t : y + 1;
+    if (x == 0) {
+      const double gm = ghost(true, y, 1);
+      const double gl = ghost(true, rlo, bot ? 8 : 5);
+      const double gh = ghost(true, rhi, top ? 5 : 8);
+      A[1] = gm;
+      if (!bot) A[5] = gl;
+      else if (shift) B[0] = gl;
+      if (!top) A[8] = gh;
+      else if (shift) B[3] = gh;
+    }
+    if (x == v.nx() - 1) {
+      const double gm = ghost(false, y, 3);
+      const double gl = ghost(false, rlo, bot ? 7 : 6);
+      const double gh = ghost(false, rhi, top ? 6 : 7);
+      A[3] = gm;
+      if (!bot) A[6] = gl;
+      else if (shift) B[1] = gl;
+      if (!top) A[7] = gh;
+      else if (shift) B[2] = gh;
+    }
   }
 
   __device__ __forceinline__ void combine(int y, const double A[9], const double B[4], double f[9]) const {
@@ -247,7 +318,7 @@ struct Gather {
 // The gather of one node in the best form the mode allows.
 template <int MODE, class V>
 __device__ __forceinline__ void gather_node(const Gather<MODE, V>& g, int x, int y, double f[9]) {
-  if constexpr (MODE == 2 || MODE == 3)
+  if constexpr (MODE >= 1)
     g.flat(x, y, f);
   else
     g(x, y, f);

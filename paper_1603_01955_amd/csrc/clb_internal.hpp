@@ -40,6 +40,7 @@ struct StepArgs {
   int mode;             // 0 periodic, 1 pressure
   int shift;            // Eq. (20) specular source from x -/+ 1
   int xcd_remap;
+  int ghost_lds;        // pressure mode: ghost columns staged in LDS (set by the launcher)
   double r;             // bounce-back fraction, Eq. (20)
   double gx, gy;        // body acceleration (periodic)
   double s3, snu, sq, s8;
@@ -50,7 +51,6 @@ struct StepArgs {
   double tq_den;        // denominator of Eq. (21)
   double c_tau;         // sqrt(6/pi) * N, N = ny
   double rho_in, rho_out;
-  int ghost_lds;        // pressure mode: ghost columns staged in LDS (set by the launcher)
 };
 
 struct InitArgs {

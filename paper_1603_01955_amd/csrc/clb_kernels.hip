@@ -62,23 +62,41 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 // rho_c(x) (Section 3.2) and through Eqs. (18), (21) the column's s_nu and
 // s_q.  With one node per thread the centre-row threads publish their own
 // density through LDS; otherwise the first row lane gathers the centre rows.
+// Workgroups take the XCD-aware order; interior ones gather with no
+// x-boundary code, the first and last stage the two ghost columns in LDS
+// (channels taller than 512 rows evaluate ghost populations inline).
 // ---------------------------------------------------------------------------
 constexpr int PX = 16;   // column-sum diagnostics: 16 columns x 16 row lanes
 constexpr int PY = 16;
 
-// One workgroup's columns; G is the gather variant of the workgroup (interior,
-// LDS ghosts or ghosts on the spot).  s_rc: [2][CX] centre-row densities.
-template <int RY, class G>
-__device__ __forceinline__ void pressure_columns(const StepArgs& a, const G& gat, int blk, double (*s_rc)[256 / RY]) {
+// One workgroup's columns with the gather of MODE 3 (interior), 2 (ghost
+// columns staged in s_ghost by this workgroup) or 1 (ghosts inline).
+// s_rc: [2][CX] centre-row densities.  With staged ghosts every thread
+// issues its own gather loads before the staging, so the two overlap; the
+// few ghost-sourced values are patched in after the barrier.
+template <int RY, int MODE>
+__device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather<MODE, View>& gat, int blk,
+                                                 double (*s_rc)[256 / RY], double* s_ghost) {
+  constexpr int CX = 256 / RY;
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blk * (256 / RY) + tx;
+  const int x = blk * CX + tx;
   const int ny = a.g.ny, yc = ny / 2;
   const bool even = (ny & 1) == 0;
+  auto stage = [&]() {
+    if (MODE == 2) {
+      fill_ghosts(gat.v, a.rho_in, a.rho_out, blk == 0, blk == (int)gridDim.x - 1, s_ghost, s_ghost + 9 * ny,
+                  ty * CX + tx, 256);
+      __syncthreads();
+    }
+  };
   if (ny <= RY) {
     const bool active = x < a.g.nx && ty < ny;
-    double f[9];
+    double A[9], B[4], f[9];
+    if (active) gat.template load_sources<MODE != 3>(x, ty, A, B);
+    stage();
     if (active) {
-      gather_node(gat, x, ty, f);
+      if (MODE != 3) gat.patch_ghosts(x, ty, A, B);
+      gat.combine(ty, A, B, f);
       if (ty == yc) s_rc[0][tx] = sum9(f);
       if (even && ty == yc - 1) s_rc[1][tx] = sum9(f);
     }
@@ -91,6 +109,7 @@ __device__ __forceinline__ void pressure_columns(const StepArgs& a, const G& gat
     store9(a.dst, a.g, x, ty, f);
     return;
   }
+  stage();
   if (ty < 2 && x < a.g.nx && (ty == 0 || even)) {
     double f[9];
     gather_node(gat, x, yc - ty, f);
@@ -118,19 +137,16 @@ __global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
   const View v{a.src, a.g};
   const double omr = 1.0 - a.r;
   const int blk = logical_block(a.xcd_remap);
-  const bool first = blk == 0, last = blk == (int)gridDim.x - 1;
-  if (!first && !last) {
+  if (blk != 0 && blk != (int)gridDim.x - 1) {
     // every x - 1 and x + 1 of this workgroup lies inside the grid
-    pressure_columns<RY>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc);
+    pressure_columns<RY, 3>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc, nullptr);
   } else if (a.ghost_lds) {
     const int ny = a.g.ny;
-    fill_ghosts(v, a.rho_in, a.rho_out, first, last, s_ghost, s_ghost + 9 * ny,
-                threadIdx.y * CX + threadIdx.x, 256);
-    __syncthreads();
-    pressure_columns<RY>(
-        a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, blk, s_rc);
+    pressure_columns<RY, 2>(
+        a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, blk, s_rc,
+        s_ghost);
   } else {
-    pressure_columns<RY>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc);
+    pressure_columns<RY, 1>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc, nullptr);
   }
 }
 
@@ -192,7 +208,7 @@ __global__ void k_moments(DiagArgs a) {
   if (x >= a.g.nx) return;
   Gather<MODE, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
   double f[9];
-  gat(x, y, f);
+  gather_node(gat, x, y, f);
   double rho, ux, uy;
   rho_u(f, rho, ux, uy);
   ux += 0.5 * a.gx;
@@ -214,7 +230,7 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
   if (x < a.g.nx) {
     for (int y = ty; y < a.g.ny; y += PY) {
       double f[9];
-      gat(x, y, f);
+      gather_node(gat, x, y, f);
       double rho, ux, uy;
       rho_u(f, rho, ux, uy);
       ux += 0.5 * a.gx;
@@ -234,10 +250,10 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
     }
     double f[9];
     const int yc = a.g.ny / 2;
-    gat(x, yc, f);
+    gather_node(gat, x, yc, f);
     double rc = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
     if ((a.g.ny & 1) == 0) {
-      gat(x, yc - 1, f);
+      gather_node(gat, x, yc - 1, f);
       rc = 0.5 * ((f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]) + rc);
     }
     if (a.m) a.m[x] = m;
