@@ -30,9 +30,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched Kn-sweep comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
-    ap.add_argument("--part", choices=("all", "step", "sweep", "adjoint"), default="all",
-                    help="run one part alone (step: the periodic step only; sweep / adjoint: that "
-                         "measurement only, printed as its own JSON line) -- for profiling runs")
+    ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "adjoint"), default="all",
+                    help="run one part alone (step: the periodic step only; sweep / pressure / adjoint: "
+                         "that measurement only, printed as its own JSON line) -- for profiling runs")
     ap.add_argument("--no-loop-baseline", action="store_true",
                     help="sweep: skip the loop-of-solvers baselines (profiling the batched kernel)")
     ap.add_argument("--block-x", type=int, default=1024)
@@ -242,6 +242,9 @@ def main():
         return
     if args.part == "sweep":
         print(json.dumps({"kn_sweep": kn_sweep(baselines=not args.no_loop_baseline)}), flush=True)
+        return
+    if args.part == "pressure":
+        print(json.dumps({"pressure_step": pressure_step()}), flush=True)
         return
     if args.part == "adjoint":
         print(json.dumps({"adjoint": adjoint_calibration()}), flush=True)

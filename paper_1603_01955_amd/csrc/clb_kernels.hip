@@ -91,12 +91,19 @@ __device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather
   };
   if (ny <= RY) {
     const bool active = x < a.g.nx && ty < ny;
-    double A[9], B[4], f[9];
-    if (active) gat.template load_sources<MODE != 3>(x, ty, A, B);
-    stage();
+    double f[9];
+    if constexpr (MODE == 2) {
+      double A[9], B[4];
+      if (active) gat.template load_sources<true>(x, ty, A, B);
+      stage();
+      if (active) {
+        gat.patch_ghosts(x, ty, A, B);
+        gat.combine(ty, A, B, f);
+      }
+    } else {
+      if (active) gather_node(gat, x, ty, f);
+    }
     if (active) {
-      if (MODE != 3) gat.patch_ghosts(x, ty, A, B);
-      gat.combine(ty, A, B, f);
       if (ty == yc) s_rc[0][tx] = sum9(f);
       if (even && ty == yc - 1) s_rc[1][tx] = sum9(f);
     }
