@@ -152,6 +152,7 @@ struct clb_ctx {
   hipStream_t stream;
   int64_t steps;
   int block_x;
+  size_t step_lds;       // LDS reserved per periodic step workgroup (occupancy cap)
   int xcd_remap;
   // optional hipGraph of graph_steps step launches, one per starting buffer
   int graph_steps;
@@ -291,6 +292,14 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->steps = 0;
   c->block_x = 1024;
   c->xcd_remap = 1;
+  c->step_lds = 0;
+  if (p->xbc == CLB_X_PERIODIC) {
+    hipError_t e = clb::periodic_step_lds(c->block_x, &c->step_lds);
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "clb_init: device attributes");
+    }
+  }
 
   clb::InitArgs ia{};
   ia.dst = c->buf[0];
@@ -335,7 +344,7 @@ clb_status record_graph(clb_ctx* c) {
     clb::StepArgs a = step_args(c);
     a.src = c->buf[cur];
     a.dst = c->buf[cur ^ 1];
-    e = clb::launch_step(a, c->block_x, c->capture);
+    e = clb::launch_step(a, c->block_x, c->capture, c->step_lds);
     cur ^= 1;
   }
   hipGraph_t g = nullptr;
@@ -365,7 +374,7 @@ clb_status clb_step(clb_ctx* c, int64_t nsteps) {
   }
   for (int64_t k = 0; k < nsteps; ++k) {
     clb::StepArgs a = step_args(c);
-    CLB_HIP(clb::launch_step(a, c->block_x, c->stream));
+    CLB_HIP(clb::launch_step(a, c->block_x, c->stream, c->step_lds));
     c->cur ^= 1;
     c->steps += 1;
   }
@@ -491,6 +500,7 @@ clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap) {
     CLB_HIP(hipStreamSynchronize(c->stream));
     drop_graphs(c);
   }
+  if (c->p.xbc == CLB_X_PERIODIC) CLB_HIP(clb::periodic_step_lds(block_x, &c->step_lds));
   c->block_x = block_x;
   c->xcd_remap = xcd_remap;
   return CLB_OK;

@@ -26,8 +26,9 @@ struct Rates {
 // ---------------------------------------------------------------------------
 template <bool FORCE>
 __device__ __forceinline__ void collide(double f[9], double gx, double gy, const Rates& s) {
-  // Every product and sum rounded on its own: the same FP64 result in every
-  // kernel that inlines this, whatever the compiler fuses around it.
+  // Products and sums round on their own except where written as fma(): the
+  // same FP64 result in every kernel that inlines this, whatever the
+  // compiler fuses around it.
 #pragma clang fp contract(off)
   const double f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4];
   const double f5 = f[5], f6 = f[6], f7 = f[7], f8 = f[8];
@@ -35,57 +36,61 @@ __device__ __forceinline__ void collide(double f[9], double gx, double gy, const
   // Eq. (8)
   const double d57 = f5 + f7, d68 = f6 + f8;
   const double diag = d57 + d68;                      // k'_xxyy
-  const double k_xx = f1 + f3 + diag;
-  const double k_yy = f2 + f4 + diag;
+  const double s13 = f1 + f3, s24 = f2 + f4;
+  const double k_xx = s13 + diag;
+  const double k_yy = s24 + diag;
   const double k_xy = d57 - d68;
   const double k_xxy = (f5 + f6) - (f7 + f8);
   const double k_xyy = (f5 + f8) - (f6 + f7);
-  const double rho = f0 + (f1 + f3) + (f2 + f4) + diag;
-  const double jx = (f1 - f3) + (f5 - f7) + (f8 - f6);
-  const double jy = (f2 - f4) + (f5 - f7) + (f6 - f8);
+  const double rho = f0 + s13 + s24 + diag;
+  const double m57 = f5 - f7;
+  const double jx = (f1 - f3) + m57 + (f8 - f6);
+  const double jy = (f2 - f4) + m57 + (f6 - f8);
 
   // Eq. (13)
   const double inv_rho = 1.0 / rho;
-  double ux = jx * inv_rho, uy = jy * inv_rho;
-  if (FORCE) {
-    ux += 0.5 * gx;
-    uy += 0.5 * gy;
-  }
+  const double ux = FORCE ? fma(jx, inv_rho, 0.5 * gx) : jx * inv_rho;
+  const double uy = FORCE ? fma(jy, inv_rho, 0.5 * gy) : jy * inv_rho;
   const double ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+  const double tux = 2.0 * ux, tuy = 2.0 * uy, trho = 2.0 * rho;
 
   // Eq. (7): the force corrections are the "-1/2 rho (...)" terms.
-  double c3 = (2.0 / 3.0) * rho + rho * (ux2 + uy2) - (k_xx + k_yy);
-  double c4 = rho * (ux2 - uy2) - (k_xx - k_yy);
-  double c5 = rho * uxy - k_xy;
-  double c6 = 2.0 * rho * ux2 * uy + k_xxy - 2.0 * ux * k_xy - uy * k_xx;
-  double c7 = 2.0 * rho * ux * uy2 + k_xyy - 2.0 * uy * k_xy - ux * k_yy;
-  double c8 = rho * (1.0 / 9.0) + 3.0 * rho * ux2 * uy2 -
-              (diag - 2.0 * ux * k_xyy - 2.0 * uy * k_xxy + ux2 * k_yy + uy2 * k_xx + 4.0 * uxy * k_xy);
+  double c3 = fma(rho, ux2 + uy2, (2.0 / 3.0) * rho) - (k_xx + k_yy);
+  double c4 = fma(rho, ux2 - uy2, -(k_xx - k_yy));
+  double c5 = fma(rho, uxy, -k_xy);
+  double c6 = fma(-uy, k_xx, fma(-tux, k_xy, fma(trho * ux2, uy, k_xxy)));
+  double c7 = fma(-ux, k_yy, fma(-tuy, k_xy, fma(trho * uy2, ux, k_xyy)));
+  const double inner =
+      fma(4.0 * uxy, k_xy, fma(uy2, k_xx, fma(ux2, k_yy, fma(-tuy, k_xxy, fma(-tux, k_xyy, diag)))));
+  double c8 = fma(3.0 * rho * ux2, uy2, rho * (1.0 / 9.0)) - inner;
   if (FORCE) {
-    c3 -= rho * (gx * ux + gy * uy);
-    c4 -= rho * (gx * ux - gy * uy);
-    c5 -= 0.5 * rho * (gx * uy + gy * ux);
-    c6 -= 0.5 * rho * (gy * ux2 + 2.0 * gx * uxy);
-    c7 -= 0.5 * rho * (gx * uy2 + 2.0 * gy * uxy);
-    c8 -= rho * (gx * ux * uy2 + gy * uy * ux2);
+    c3 -= rho * fma(gx, ux, gy * uy);
+    c4 -= rho * fma(gx, ux, -(gy * uy));
+    c5 -= 0.5 * rho * fma(gx, uy, gy * ux);
+    c6 -= 0.5 * rho * fma(gy, ux2, 2.0 * gx * uxy);
+    c7 -= 0.5 * rho * fma(gx, uy2, 2.0 * gy * uxy);
+    c8 -= rho * fma(gx * ux, uy2, gy * uy * ux2);
   }
   const double g3 = s.s3 * (1.0 / 12.0) * c3;
-  const double g4 = 0.25 * s.snu * c4;
-  const double g5 = 0.25 * s.snu * c5;
-  const double a34 = 3.0 * g3 + g4;   // appears in g6 and g8
-  const double b34 = 3.0 * g3 - g4;   // appears in g7 and g8
-  const double g6 = 0.25 * s.sq * c6 - 0.5 * uy * a34 - 2.0 * ux * g5;
-  const double g7 = 0.25 * s.sq * c7 - 0.5 * ux * b34 - 2.0 * uy * g5;
-  const double g8 = 0.25 * s.s8 * c8 - 2.0 * g3 - 0.5 * uy2 * a34 - 0.5 * ux2 * b34 -
-                    4.0 * uxy * g5 - 2.0 * uy * g6 - 2.0 * ux * g7;
+  const double qnu = 0.25 * s.snu;
+  const double g4 = qnu * c4;
+  const double g5 = qnu * c5;
+  const double a34 = fma(3.0, g3, g4);    // appears in g6 and g8
+  const double b34 = fma(3.0, g3, -g4);   // appears in g7 and g8
+  const double qq = 0.25 * s.sq;
+  const double g6 = fma(-tux, g5, fma(-0.5 * uy, a34, qq * c6));
+  const double g7 = fma(-tuy, g5, fma(-0.5 * ux, b34, qq * c7));
+  const double g8 = fma(-tux, g7, fma(-tuy, g6, fma(-4.0 * uxy, g5, fma(-0.5 * ux2, b34,
+                    fma(-0.5 * uy2, a34, fma(-2.0, g3, 0.25 * s.s8 * c8))))));
 
   // Eq. (6): f + K g (columns of K from Eq. 3).
-  double o0 = f0 - 4.0 * (g3 - g8);
-  double o1 = f1 - g3 + g4 + 2.0 * (g7 - g8);
-  double o2 = f2 - g3 - g4 + 2.0 * (g6 - g8);
-  double o3 = f3 - g3 + g4 - 2.0 * (g7 + g8);
-  double o4 = f4 - g3 - g4 - 2.0 * (g6 + g8);
-  const double t = 2.0 * g3 + g8;
+  const double g38 = g3 - g8, g78 = g7 - g8, g68 = g6 - g8;
+  double o0 = fma(-4.0, g38, f0);
+  double o1 = fma(2.0, g78, (f1 - g3) + g4);
+  double o2 = fma(2.0, g68, (f2 - g3) - g4);
+  double o3 = fma(-2.0, g7 + g8, (f3 - g3) + g4);
+  double o4 = fma(-2.0, g6 + g8, (f4 - g3) - g4);
+  const double t = fma(2.0, g3, g8);
   double o5 = f5 + t + g5 - g6 - g7;
   double o6 = f6 + t - g5 - g6 + g7;
   double o7 = f7 + t + g5 + g6 + g7;
@@ -94,12 +99,12 @@ __device__ __forceinline__ void collide(double f[9], double gx, double gy, const
   if (FORCE) {
     // Eq. (9) source moments in the basis of Eq. (10) ...
     const double Sx = rho * gx, Sy = rho * gy;
-    const double Sxy = rho * (ux * gy + uy * gx);
-    const double Sxxy = rho * gy * ux2 + 2.0 * rho * gx * uxy;
-    const double Sxyy = rho * gx * uy2 + 2.0 * rho * gy * uxy;
-    const double Sxxyy = 2.0 * rho * gx * ux * uy2 + 2.0 * rho * gy * uy * ux2;
-    const double Sxx = 2.0 * rho * ux * gx;   // (S3 + S4)/2
-    const double Syy = 2.0 * rho * uy * gy;   // (S3 - S4)/2
+    const double Sxy = rho * fma(ux, gy, uy * gx);
+    const double Sxxy = fma(Sy, ux2, 2.0 * Sx * uxy);
+    const double Sxyy = fma(Sx, uy2, 2.0 * Sy * uxy);
+    const double Sxxyy = 2.0 * fma(Sx * ux, uy2, Sy * uy * ux2);
+    const double Sxx = 2.0 * Sx * ux;   // (S3 + S4)/2
+    const double Syy = 2.0 * Sy * uy;   // (S3 - S4)/2
     // ... mapped back to populations by the inverse of T (closed form).
     o0 += Sxxyy - Sxx - Syy;
     o1 += 0.5 * (Sxx - Sxxyy + Sx - Sxyy);

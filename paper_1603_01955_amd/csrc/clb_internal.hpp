@@ -79,7 +79,11 @@ struct DiagArgs {
   double* rhoc;
 };
 
-hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st);
+// Threads of periodic step workgroups allowed on one CU at a time.
+constexpr int kStepThreadsPerCU = 1024;
+hipError_t periodic_step_lds(int block_x, size_t* bytes);
+// lds_reserve: see periodic_step_lds (periodic mode only).
+hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t lds_reserve = 0);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st);
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);
