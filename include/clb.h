@@ -108,7 +108,8 @@ clb_status clb_derive(const clb_params* p, clb_derived* out);
 
 /* Device workspace in bytes needed by clb_init for *p: two population buffers
  * (72 bytes per node; rows are padded to whole segments of L lanes,
- * L = min(1024, next power of two >= nx)) plus a small diagnostics area.
+ * L = min(1024, next power of two >= nx)) plus small per-column and per-row
+ * scratch (diagnostics, local relaxation rates, ghost columns).
  * The device-side layout of a buffer is internal; populations cross the ABI
  * only in the [9][ny][nx] layout (clb_get_populations / clb_set_populations). */
 clb_status clb_workspace_size(const clb_params* p, size_t* bytes);
@@ -168,6 +169,15 @@ clb_status clb_check_finite(clb_ctx* c, int32_t* h_ok);
  * block_x threads per row segment (64, 128, 256, 512 or 1024) and
  * xcd_remap = 1 to map consecutive row segments onto the same XCD. */
 clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap);
+
+/* Pressure-mode kernel choice (tuning; Section 3.2 step): 0 = by grid size
+ * (default), 1 = column kernel (each workgroup owns whole columns and takes
+ * the local Kn from its own centre rows; best for the small channels of the
+ * paper), 2 = row kernel (a prep launch computes the per-column rates and
+ * ghost columns, then the step streams whole row segments; best for large
+ * grids).  Both give bitwise the same populations.  CLB_EINVAL for other
+ * values; no effect in periodic mode. */
+clb_status clb_set_pressure_path(clb_ctx* c, int32_t path);
 
 /* Launch-overhead control for small grids: with steps_per_graph > 0,
  * clb_step replays a hipGraph of steps_per_graph recorded step launches

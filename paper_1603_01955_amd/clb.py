@@ -67,6 +67,7 @@ _SIGNATURES = {
     "clb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "clb_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "clb_set_pressure_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_set_graph_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "clb_last_error": (ctypes.c_char_p, []),
@@ -165,6 +166,10 @@ class Solver:
 
     def set_launch(self, block_x=1024, xcd_remap=1):
         check(lib().clb_set_launch(self._ctx, int(block_x), int(xcd_remap)))
+
+    def set_pressure_path(self, path=0):
+        """Pressure-mode kernel: 0 by grid size, 1 column kernel, 2 row kernel."""
+        check(lib().clb_set_pressure_path(self._ctx, int(path)))
 
     def set_graph_steps(self, steps_per_graph):
         check(lib().clb_set_graph_steps(self._ctx, int(steps_per_graph)))

@@ -46,6 +46,7 @@ constexpr int kPartials = 1024;
 struct Layout {
   size_t buf;      // bytes of one population buffer
   size_t col;      // bytes of one per-column array
+  size_t ghosts;   // bytes of the ghost-column scratch [2][9][ny]
   size_t total;
 };
 
@@ -54,7 +55,11 @@ Layout layout_of(const clb_params* p) {
   const clb::Geo g = clb::make_geo(p->nx, p->ny);
   L.buf = align256(g.size() * sizeof(double));
   L.col = align256((size_t)p->nx * sizeof(double));
-  L.total = 2 * L.buf + 4 * L.col + align256(kPartials * sizeof(double)) + align256(32 * sizeof(double));
+  L.ghosts = align256(18 * (size_t)p->ny * sizeof(double));
+  // two buffers, four diagnostics columns, two rate columns, ghost scratch,
+  // reduction partials, results
+  L.total = 2 * L.buf + 6 * L.col + L.ghosts + align256(kPartials * sizeof(double)) +
+            align256(32 * sizeof(double));
   return L;
 }
 
@@ -152,7 +157,10 @@ struct clb_ctx {
   hipStream_t stream;
   int64_t steps;
   int block_x;
-  size_t step_lds;       // LDS reserved per periodic step workgroup (occupancy cap)
+  size_t step_lds;       // LDS reserved per row-streaming step workgroup (occupancy cap)
+  int pressure_path;      // clb_set_pressure_path
+  double* col_rates;     // pressure mode, large grids: per-column s_nu, s_q
+  double* ghosts;        // pressure mode, large grids: ghost columns
   int xcd_remap;
   // optional hipGraph of graph_steps step launches, one per starting buffer
   int graph_steps;
@@ -185,6 +193,9 @@ clb::StepArgs step_args(const clb_ctx* c) {
   a.c_tau = std::sqrt(6.0 / kPi) * (double)c->p.ny;
   a.rho_in = c->p.p_ratio * c->p.rho_out;
   a.rho_out = c->p.rho_out;
+  a.col_rates = c->col_rates;
+  a.ghosts = c->ghosts;
+  a.pressure_path = c->pressure_path;
   return a;
 }
 
@@ -287,13 +298,17 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->col_tmp = reinterpret_cast<double*>(q + 3 * L.col);
   c->partial = reinterpret_cast<double*>(q + 4 * L.col);
   c->result = reinterpret_cast<double*>(q + 4 * L.col + align256(kPartials * sizeof(double)));
+  q += 4 * L.col + align256(kPartials * sizeof(double)) + align256(32 * sizeof(double));
+  c->col_rates = reinterpret_cast<double*>(q);   // [2][nx] (two columns of L.col bytes each)
+  c->ghosts = reinterpret_cast<double*>(q + 2 * L.col);
   c->cur = 0;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   c->block_x = 1024;
   c->xcd_remap = 1;
+  c->pressure_path = 0;
   c->step_lds = 0;
-  if (p->xbc == CLB_X_PERIODIC) {
+  {
     hipError_t e = clb::periodic_step_lds(c->block_x, &c->step_lds);
     if (e != hipSuccess) {
       delete c;
@@ -500,9 +515,21 @@ clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap) {
     CLB_HIP(hipStreamSynchronize(c->stream));
     drop_graphs(c);
   }
-  if (c->p.xbc == CLB_X_PERIODIC) CLB_HIP(clb::periodic_step_lds(block_x, &c->step_lds));
+  CLB_HIP(clb::periodic_step_lds(block_x, &c->step_lds));
   c->block_x = block_x;
   c->xcd_remap = xcd_remap;
+  return CLB_OK;
+}
+
+clb_status clb_set_pressure_path(clb_ctx* c, int32_t path) {
+  clb_status st = check_ctx(c);
+  if (st != CLB_OK) return st;
+  if (path < 0 || path > 2) return fail(CLB_EINVAL, "path: must be 0, 1 or 2");
+  if (path != c->pressure_path) {
+    CLB_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+  }
+  c->pressure_path = path;
   return CLB_OK;
 }
 

@@ -51,6 +51,11 @@ struct StepArgs {
   double tq_den;        // denominator of Eq. (21)
   double c_tau;         // sqrt(6/pi) * N, N = ny
   double rho_in, rho_out;
+  // pressure mode, large grids (row kernel): scratch filled by the prep kernel
+  // each step; null when the caller provides none (column kernel only)
+  double* col_rates;    // [2][nx]: s_nu(x), then s_q(x)
+  double* ghosts;       // [2][9][ny]: inlet, outlet ghost columns
+  int pressure_path;    // 0 by size, 1 column kernel, 2 row kernel
 };
 
 struct InitArgs {
@@ -81,6 +86,9 @@ struct DiagArgs {
 
 // Threads of periodic step workgroups allowed on one CU at a time.
 constexpr int kStepThreadsPerCU = 1024;
+// Pressure-mode grids with at least this many nodes take the row kernel
+// (prep + row-streaming step) when the caller provides its scratch.
+constexpr size_t kPressureRowNodes = (size_t)1 << 20;
 hipError_t periodic_step_lds(int block_x, size_t* bytes);
 // lds_reserve: see periodic_step_lds (periodic mode only).
 hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t lds_reserve = 0);

@@ -158,6 +158,65 @@ __global__ __launch_bounds__(256) void k_step_pressure(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// K2b: pressure-driven step for large grids, in two launches.  The prep
+// kernel takes each column's centre-line density from the same step's
+// gather, turns it into the column's s_nu, s_q (same arithmetic as K2), and
+// builds the two ghost columns; the row kernel then streams the grid in the
+// periodic kernel's order (one thread per node, whole row segments per
+// workgroup), reading the rates and ghosts from those arrays.  Bitwise the
+// same result as K2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pressure_prep(StepArgs a) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  const View v{a.src, a.g};
+  const int ncb = (nx + 255) / 256;
+  if ((int)blockIdx.x < ncb) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const Gather<1, View> gat{v, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+    const int yc = ny / 2;
+    double f[9];
+    gather_node(gat, x, yc, f);
+    double rc = sum9(f);
+    if ((ny & 1) == 0) {
+      gather_node(gat, x, yc - 1, f);
+      rc = 0.5 * (sum9(f) + rc);
+    }
+    double snu, sq;
+    local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
+    a.col_rates[x] = snu;
+    a.col_rates[nx + x] = sq;
+  } else {
+    // ghost rows: j < ny inlet row j, else outlet row j - ny
+    const int j = ((int)blockIdx.x - ncb) * 256 + threadIdx.x;
+    if (j >= 2 * ny) return;
+    const bool inlet = j < ny;
+    const int y = inlet ? j : j - ny;
+    double g[9];
+    ghost_row(v, inlet, y, inlet ? a.rho_in : a.rho_out, g);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a.ghosts[(inlet ? 0 : 9 * ny) + i * ny + y] = g[i];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_step_pressure_rows(StepArgs a) {
+  const size_t t = (size_t)logical_block(a.xcd_remap) * blockDim.x + threadIdx.x;
+  const int lane = (int)(t & (((size_t)1 << a.g.lshift) - 1));
+  const size_t rest = t >> a.g.lshift;
+  const int y = (int)(rest / (size_t)a.g.nseg);
+  const int x = (int)(rest - (size_t)y * a.g.nseg) * (1 << a.g.lshift) + lane;
+  if (y >= a.g.ny || x >= a.g.nx) return;
+  const int ny = a.g.ny;
+  const Gather<2, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out, a.ghosts,
+                            a.ghosts + 9 * ny};
+  // a wave covers consecutive x of one row: the wall branches do not diverge
+  double f[9];
+  gat(x, y, f);
+  collide<false>(f, 0.0, 0.0, Rates{a.s3, a.col_rates[x], a.col_rates[a.g.nx + x], a.s8});
+  store9(a.dst, a.g, x, y, f);
+}
+
+// ---------------------------------------------------------------------------
 // K3: initial state (logical node order; node = y * nx + x).
 // ---------------------------------------------------------------------------
 __global__ void k_init(InitArgs a) {
@@ -349,6 +408,8 @@ hipError_t periodic_step_lds(int block_x, size_t* bytes) {
   if (hipFuncSetAttribute((const void*)k_step_periodic<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)want) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_step_periodic<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)want) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_step_pressure_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)want) != hipSuccess) {
     (void)hipGetLastError();
     return hipSuccess;
@@ -365,6 +426,12 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
       k_step_periodic<true><<<grid, block_x, lds_reserve, st>>>(a);
     else
       k_step_periodic<false><<<grid, block_x, lds_reserve, st>>>(a);
+  } else if (a.col_rates && a.ghosts &&
+             (a.pressure_path == 2 || (a.pressure_path == 0 && (size_t)a.g.nx * a.g.ny >= kPressureRowNodes))) {
+    k_pressure_prep<<<(a.g.nx + 255) / 256 + (2 * a.g.ny + 255) / 256, 256, 0, st>>>(a);
+    const size_t threads = a.g.padded_nodes();
+    const dim3 grid((unsigned)((threads + block_x - 1) / block_x));
+    k_step_pressure_rows<<<grid, block_x, lds_reserve, st>>>(a);
   } else {
     StepArgs b = a;
     b.ghost_lds = a.g.ny <= kGhostLdsMaxNy ? 1 : 0;

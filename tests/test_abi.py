@@ -68,10 +68,11 @@ def test_derived_constants_match_reference(lib, nx, ny, kn, sigma, xbc):
 
 def test_workspace_size_arithmetic(lib):
     # rows padded to segments of L = min(1024, next power of two >= nx) lanes
+    # plus six per-column arrays and the ghost columns [2][9][ny]
     for nx, ny, padded in ((1000, 30, 1024), (4, 32, 4), (77, 13, 128), (4000, 40, 4096)):
         n = clb.workspace_size(clb.make_params(nx, ny))
-        assert n >= 2 * 72 * padded * ny + 4 * 8 * nx
-        assert n < 2 * 72 * padded * ny + 4 * 8 * nx + 64 * 1024
+        assert n >= 2 * 72 * padded * ny + 6 * 8 * nx + 144 * ny
+        assert n < 2 * 72 * padded * ny + 6 * 8 * nx + 144 * ny + 64 * 1024
 
 
 @pytest.mark.parametrize("field,value", [

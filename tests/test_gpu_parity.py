@@ -170,6 +170,53 @@ def test_pressure_mode(kw, steps, start):
     assert abs(m_mean - m_ref.mean()) <= 1e-9 * np.max(np.abs(m_ref))
 
 
+@pytest.mark.parametrize("kw,steps,start", [
+    (dict(nx=300, ny=8, xbc="pressure", kn=0.1, p_ratio=2.0), 30, "linear"),
+    (dict(nx=257, ny=7, xbc="pressure", kn=0.194, p_ratio=2.0), 20, "random"),
+    (dict(nx=2, ny=3, xbc="pressure", kn=0.05, p_ratio=1.4), 20, "random"),
+    (dict(nx=64, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, cbbsr_shift=0), 20, "random"),
+    (dict(nx=50, ny=70, xbc="pressure", kn=0.2, p_ratio=1.5), 20, "random"),
+    (dict(nx=149, ny=1, xbc="pressure", kn=0.3, p_ratio=1.2), 20, "random"),
+])
+def test_pressure_row_kernel(kw, steps, start):
+    """The row kernel (prep launch + row-streaming step) gives bitwise the
+    column kernel's populations, and matches the reference."""
+    prm = _oracle_params(kw)
+    if start == "random":
+        P0 = uniform_populations(kw["nx"], kw["ny"], seed=107, lo=0.08, hi=0.12)
+    else:
+        P0 = C.init_linear_rho(prm)
+    out = []
+    for path in (1, 2):
+        s = _solver(**kw)
+        s.set_pressure_path(path)
+        s.set_populations(torch.from_numpy(P0))
+        s.step(steps)
+        out.append(s.populations().cpu().numpy())
+        s.close()
+    assert np.array_equal(out[0], out[1])
+    Pref = C.run(P0, prm, steps)
+    assert _rel(out[1], Pref) <= TOL
+
+
+def test_pressure_large_grid_takes_row_kernel():
+    """4096 x 256 (1 M nodes, above the size threshold): the default choice
+    equals the column kernel bit for bit; path values are validated."""
+    from paper_1603_01955_amd import ClbError
+    kw = dict(nx=4096, ny=256, xbc="pressure", kn=0.2, p_ratio=1.5, init="linear_rho")
+    out = []
+    for path in (0, 1):
+        s = _solver(**kw)
+        s.set_pressure_path(path)
+        s.step(6)
+        out.append(s.populations().cpu().numpy())
+        if path == 1:
+            with pytest.raises(ClbError):
+                s.set_pressure_path(3)
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("kind", ["uniform", "linear_rho", "perturbed"])
 def test_initial_states(kind):
     kw = dict(nx=97, ny=11, kn=0.2, rho0=1.3, ux0=0.01, uy0=-0.02, init=kind, init_amp=1e-4,
