@@ -20,8 +20,10 @@
 //     centre rows and into dL/da, dL/dA2; wall rows add lpre . dpre/dr to
 //     dL/dr.
 // Both halves run in one kernel per reverse step (k_adj_step).
-// The forward run keeps ceil(T/K) checkpoints; the backward sweep recomputes
-// each segment of K steps from its checkpoint and then reverses it.
+// The forward run keeps ceil(T/K) checkpoints.  The backward sweep reverses
+// the segments of K steps from last to first; each segment is recomputed from
+// its checkpoint (with its ghost columns, k_ghosts) on a second stream while
+// the segment after it is being reversed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
