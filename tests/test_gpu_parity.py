@@ -303,6 +303,21 @@ def test_graph_replay_identical(graph_steps):
     assert np.array_equal(s.populations().cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("kw", [dict(nx=33, ny=5, kn=0.2, gx=1e-4),
+                                dict(nx=40, ny=6, xbc="pressure", kn=0.1, p_ratio=2.0)])
+def test_zero_steps_is_a_no_op(kw):
+    s = _solver(**kw)
+    s.step(3)
+    P = s.populations().cpu().numpy()
+    s.step(0)
+    assert s.steps_done == 3
+    assert np.array_equal(s.populations().cpu().numpy(), P)
+    from paper_1603_01955_amd import ClbError
+    with pytest.raises(ClbError):
+        s.step(-1)
+    s.close()
+
+
 def test_nonfinite_detection():
     s = _solver(nx=40, ny=6, kn=0.5)
     assert s.check_finite()
