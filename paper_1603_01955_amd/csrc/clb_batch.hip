@@ -84,6 +84,65 @@ __device__ void channel_step(const ChanDesc& d, const double* A, double* B, int 
   }
 }
 
+// One node per thread (n <= blockDim.x): the node, and with it every LDS
+// source offset of its gather, stays the same for the whole run, so the
+// offsets are worked out once.  a[i]: the population pulled into direction
+// i, or its bounce-back part on a wall row; b[k]: the specular part of
+// direction 5 + k on a wall row (Eq. 20), x wrapped periodically.  The
+// arithmetic per step is that of Gather::operator(), bitwise.
+struct NodeSources {
+  int a[9], b[4];
+  bool bot, top;
+};
+
+__device__ __forceinline__ NodeSources node_sources(const ChanDesc& d, int j) {
+  const int nx = d.nx, ny = d.ny, n = nx * ny, t = ny - 1;
+  const int y = j / nx, x = j - y * nx;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int xsm = d.shift ? xm : x, xsp = d.shift ? xp : x;
+  auto at = [&](int i, int xx, int yy) { return i * n + yy * nx + xx; };
+  NodeSources q;
+  q.bot = y == 0;
+  q.top = y == t;
+  q.a[0] = at(0, x, y);
+  q.a[1] = at(1, xm, y);
+  q.a[3] = at(3, xp, y);
+  q.a[2] = q.bot ? at(4, x, 0) : at(2, x, y - 1);
+  q.a[5] = q.bot ? at(7, x, 0) : at(5, xm, y - 1);
+  q.a[6] = q.bot ? at(8, x, 0) : at(6, xp, y - 1);
+  q.a[4] = q.top ? at(2, x, t) : at(4, x, y + 1);
+  q.a[7] = q.top ? at(5, x, t) : at(7, xp, y + 1);
+  q.a[8] = q.top ? at(6, x, t) : at(8, xm, y + 1);
+  q.b[0] = q.bot ? at(8, xsm, 0) : q.a[5];
+  q.b[1] = q.bot ? at(7, xsp, 0) : q.a[6];
+  q.b[2] = q.top ? at(6, xsp, t) : q.a[7];
+  q.b[3] = q.top ? at(5, xsm, t) : q.a[8];
+  return q;
+}
+
+template <bool FORCE>
+__device__ __forceinline__ void node_step(const ChanDesc& d, const NodeSources& q, const double* A, double* B,
+                                          int n, int j) {
+#pragma clang fp contract(off)
+  double f[9], s[4];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = A[q.a[i]];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k] = A[q.b[k]];
+  const double r = d.r, omr = 1.0 - d.r;
+  if (q.bot) {
+    f[5] = r * f[5] + omr * s[0];
+    f[6] = r * f[6] + omr * s[1];
+  }
+  if (q.top) {
+    f[7] = r * f[7] + omr * s[2];
+    f[8] = r * f[8] + omr * s[3];
+  }
+  collide<FORCE>(f, d.gx, d.gy, Rates{d.s3, d.snu, d.sq, d.s8});
+#pragma unroll
+  for (int i = 0; i < 9; ++i) B[i * n + j] = f[i];
+}
+
 // Sum over the channel of u_x of the pre-collision state (Eq. 13).
 __device__ double channel_sum_ux(const ChanDesc& d, const double* A, int n, double* red) {
   const Gather<0, LdsView> gat{{A, d.nx, d.ny, n}, d.r, 1.0 - d.r, d.shift, 0.0, 0.0};
@@ -116,11 +175,23 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
   ChanState st = a.cs[c];
   __syncthreads();
   int64_t taken = 0;
+  const bool one = n <= (int)blockDim.x;   // one node per thread: sources fixed for the run
+  const bool mine = (int)threadIdx.x < n;
+  NodeSources q{};
+  if (one && mine) q = node_sources(d, threadIdx.x);
   while (!st.converged && taken < a.max_steps) {
-    if (d.force)
+    if (one) {
+      if (mine) {
+        if (d.force)
+          node_step<true>(d, q, A, B, n, threadIdx.x);
+        else
+          node_step<false>(d, q, A, B, n, threadIdx.x);
+      }
+    } else if (d.force) {
       channel_step<true>(d, A, B, n);
-    else
+    } else {
       channel_step<false>(d, A, B, n);
+    }
     __syncthreads();
     double* t = A;
     A = B;
