@@ -121,7 +121,7 @@ def test_flow_rate_matches_discrete_closed_form(kn):
 
 def test_knudsen_minimum_location():
     """P14: the scheme's flow rate has its minimum at Kn* = 1/(sqrt(18 B2) - a)
-    = 0.872, which is the paper's 'Kn ~ 0.9' (Abstract, Section 3.1); the
+    = 0.872, where the paper reports a minimum near Kn = 0.9 (Abstract, Section 3.1); the
     continuum law (2 B2) would put it at 1.76."""
     pv = _paper_values()
     kstar = A.knudsen_minimum(pv["rarefaction_factor_a"], pv["slip_B2"])
