@@ -587,6 +587,8 @@ struct clb_adjoint {
   double* lpre;
   double* gh;              // [2][K][2][9][ny] ghost columns of the recomputed states
   double* gpart;           // [nblk][3]
+  double* step_rates;      // [2][nx] row-kernel scratch of the forward steps
+  double* step_ghosts;     // [2][9][ny] row-kernel scratch of the forward steps
   double* col;             // [6][nx]: m, su, rho_c, diff, final-gather r terms (2 nx)
   double* dpt;             // [nx] target dp*
   double* scal;            // [16]: loss, m - m*, m, grads
@@ -618,8 +620,10 @@ AdjLayout adj_layout(const clb_params* p, int32_t T, int32_t K) {
   const size_t buf = clb::align256(L.S * sizeof(double));
   const size_t col = clb::align256((size_t)p->nx * sizeof(double));
   L.gh = clb::align256(2 * (size_t)K * 18 * (size_t)p->ny * sizeof(double));
+  // + forward-step scratch of the row kernel: two per-column arrays and [2][9][ny]
   L.total = ((size_t)L.nck + (size_t)L.nseg + 4) * buf + L.gh + 7 * col +
-            clb::align256((size_t)L.nblk * 3 * sizeof(double)) + clb::align256(16 * sizeof(double));
+            clb::align256((size_t)L.nblk * 3 * sizeof(double)) + clb::align256(16 * sizeof(double)) +
+            2 * col + clb::align256(18 * (size_t)p->ny * sizeof(double));
   return L;
 }
 
@@ -643,6 +647,10 @@ clb::StepArgs adj_step_args(const clb_adjoint* a, const double* src, double* dst
   s.c_tau = std::sqrt(6.0 / M_PI) * (double)a->p.ny;
   s.rho_in = a->p.p_ratio * a->p.rho_out;
   s.rho_out = a->p.rho_out;
+  // large grids take the row kernel; forward steps and the recompute never
+  // run at the same time, so they share this scratch
+  s.col_rates = a->step_rates;
+  s.ghosts = a->step_ghosts;
   return s;
 }
 
@@ -809,6 +817,9 @@ clb_status clb_adjoint_init(const clb_params* p, int32_t T, int32_t K, void* d_w
   a->gpart = reinterpret_cast<double*>(q);
   q += clb::align256((size_t)L.nblk * 3 * sizeof(double));
   a->scal = reinterpret_cast<double*>(q);
+  q += clb::align256(16 * sizeof(double));
+  a->step_rates = reinterpret_cast<double*>(q);
+  a->step_ghosts = reinterpret_cast<double*>(q + 2 * col);
   a->stream = static_cast<hipStream_t>(hip_stream);
   a->forward_done = 0;
   hipError_t e = hipStreamCreateWithFlags(&a->rstream, hipStreamNonBlocking);

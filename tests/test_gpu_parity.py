@@ -303,6 +303,25 @@ def test_graph_replay_identical(graph_steps):
     assert np.array_equal(s.populations().cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("path", [1, 2])
+def test_graph_replay_pressure(path):
+    """Pressure mode through recorded hipGraphs (the row kernel records two
+    launches per step): every chunk, with host reads in between, equals
+    eager stepping bit for bit."""
+    kw = dict(nx=150, ny=12, xbc="pressure", kn=0.15, p_ratio=1.8, init="linear_rho")
+    eager = _solver(**kw)
+    eager.set_pressure_path(1)
+    s = _solver(**kw)
+    s.set_pressure_path(path)
+    s.set_graph_steps(5)
+    for chunk in (10, 7, 15, 5):
+        eager.step(chunk)
+        s.step(chunk)
+        assert np.array_equal(s.populations().cpu().numpy(), eager.populations().cpu().numpy()), chunk
+    s.close()
+    eager.close()
+
+
 @pytest.mark.parametrize("kw", [dict(nx=33, ny=5, kn=0.2, gx=1e-4),
                                 dict(nx=40, ny=6, xbc="pressure", kn=0.1, p_ratio=2.0)])
 def test_zero_steps_is_a_no_op(kw):
