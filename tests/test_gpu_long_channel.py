@@ -59,6 +59,19 @@ def test_first_steps_match_reference():
     assert np.max(np.abs(P - Pref)) <= 1e-10 * np.max(np.abs(Pref))
 
 
+def test_first_thousand_steps_match_reference():
+    """The first 1000 steps at this channel height and pressure ratio
+    (80 x 40, a shorter channel so that the reference finishes in seconds)."""
+    from paper_1603_01955_amd import Solver
+    s = Solver(nx=80, ny=NY, xbc="pressure", kn=0.1, p_ratio=2.0, init="linear_rho")
+    s.step(1000)
+    P = s.populations().cpu().numpy()
+    prm = C.Params(nx=80, ny=NY, xbc="pressure", kn=0.1, p_ratio=2.0)
+    Pref = C.run(C.init_linear_rho(prm), prm, 1000)
+    assert np.max(np.abs(P - Pref)) <= 1e-10 * np.max(np.abs(Pref))
+    s.close()
+
+
 def test_mass_flow_uniform_and_symmetric(steady):
     for kn, s in steady.items():
         m = s.massflow()[0].cpu().numpy()
