@@ -589,6 +589,7 @@ struct clb_adjoint {
   double* gpart;           // [nblk][3]
   double* step_rates;      // [2][nx] row-kernel scratch of the forward steps
   double* step_ghosts;     // [2][9][ny] row-kernel scratch of the forward steps
+  int cus;                 // compute units of the device (launch shapes)
   double* col;             // [6][nx]: m, su, rho_c, diff, final-gather r terms (2 nx)
   double* dpt;             // [nx] target dp*
   double* scal;            // [16]: loss, m - m*, m, grads
@@ -651,6 +652,7 @@ clb::StepArgs adj_step_args(const clb_adjoint* a, const double* src, double* dst
   // run at the same time, so they share this scratch
   s.col_rates = a->step_rates;
   s.ghosts = a->step_ghosts;
+  s.cus = a->cus;
   return s;
 }
 
@@ -822,6 +824,7 @@ clb_status clb_adjoint_init(const clb_params* p, int32_t T, int32_t K, void* d_w
   a->step_ghosts = reinterpret_cast<double*>(q + 2 * col);
   a->stream = static_cast<hipStream_t>(hip_stream);
   a->forward_done = 0;
+  a->cus = clb::device_cus();
   hipError_t e = hipStreamCreateWithFlags(&a->rstream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&a->ev_start, hipEventDisableTiming);
   for (int k = 0; k < 2 && e == hipSuccess; ++k) {

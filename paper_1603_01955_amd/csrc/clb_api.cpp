@@ -159,6 +159,7 @@ struct clb_ctx {
   int block_x;
   size_t step_lds;       // LDS reserved per row-streaming step workgroup (occupancy cap)
   int pressure_path;      // clb_set_pressure_path
+  int cus;               // compute units of the device
   double* col_rates;     // pressure mode, large grids: per-column s_nu, s_q
   double* ghosts;        // pressure mode, large grids: ghost columns
   int xcd_remap;
@@ -196,6 +197,7 @@ clb::StepArgs step_args(const clb_ctx* c) {
   a.col_rates = c->col_rates;
   a.ghosts = c->ghosts;
   a.pressure_path = c->pressure_path;
+  a.cus = c->cus;
   return a;
 }
 
@@ -307,6 +309,7 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->block_x = 1024;
   c->xcd_remap = 1;
   c->pressure_path = 0;
+  c->cus = clb::device_cus();
   c->step_lds = 0;
   {
     hipError_t e = clb::periodic_step_lds(c->block_x, &c->step_lds);

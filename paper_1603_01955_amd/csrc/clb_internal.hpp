@@ -56,7 +56,10 @@ struct StepArgs {
   double* col_rates;    // [2][nx]: s_nu(x), then s_q(x)
   double* ghosts;       // [2][9][ny]: inlet, outlet ghost columns
   int pressure_path;    // 0 by size, 1 column kernel, 2 row kernel
+  int cus;              // compute units of the device (launch-shape choice; 0: unknown)
 };
+// Compute units of the current device (0 if the query fails).
+int device_cus();
 
 struct InitArgs {
   double* dst;
@@ -87,8 +90,9 @@ struct DiagArgs {
 // Threads of periodic step workgroups allowed on one CU at a time.
 constexpr int kStepThreadsPerCU = 1024;
 // Pressure-mode grids with at least this many nodes take the row kernel
-// (prep + row-streaming step) when the caller provides its scratch.
-constexpr size_t kPressureRowNodes = (size_t)1 << 20;
+// (prep + row-streaming step) when the caller provides its scratch; below it
+// the column kernel with wide workgroups is as fast or faster (measured).
+constexpr size_t kPressureRowNodes = (size_t)1 << 21;
 hipError_t periodic_step_lds(int block_x, size_t* bytes);
 // lds_reserve: see periodic_step_lds (periodic mode only).
 hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t lds_reserve = 0);

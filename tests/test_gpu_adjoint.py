@@ -176,12 +176,12 @@ def test_autograd_function():
 
 
 def test_large_grid_forward_takes_row_kernel():
-    """4096 x 256 (1 M nodes): the adjoint's forward steps take the row
+    """8192 x 256 (2 M nodes): the adjoint's forward steps take the row
     kernel; its final observables equal a column-kernel solver's bit for bit,
     and the backward sweep runs at this size with finite gradients."""
     from paper_1603_01955_amd import Solver, clb
     from paper_1603_01955_amd.adjoint import Adjoint
-    nx, ny, T = 4096, 256, 3
+    nx, ny, T = 8192, 256, 3
     p = clb.make_params(nx, ny, xbc="pressure", kn=0.2, p_ratio=1.5)
     adj = Adjoint(p, T, 2)
     adj.forward(torch.zeros(nx, dtype=torch.float64), 1.0)

@@ -151,6 +151,9 @@ def test_launch_shapes_bitwise_identical():
     (dict(nx=149, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0), 60, "linear"),      # 64-row tiles, nx = 1 (mod 4)
     (dict(nx=50, ny=70, xbc="pressure", kn=0.2, p_ratio=1.5, cbbsr_shift=0), 40, "random"),  # rows looped
     (dict(nx=1030, ny=20, xbc="pressure", kn=0.194, p_ratio=2.0), 30, "linear"),   # 129 workgroups, remap tail
+    (dict(nx=2500, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0), 6, "linear"),      # 512-thread workgroups
+    (dict(nx=8001, ny=12, xbc="pressure", kn=0.3, p_ratio=1.5), 6, "random"),      # 512 threads, 16 rows
+    (dict(nx=7401, ny=24, xbc="pressure", kn=0.2, p_ratio=1.8, cbbsr_shift=0), 4, "random"),  # 1024 threads
 ])
 def test_pressure_mode(kw, steps, start):
     prm = _oracle_params(kw)
@@ -200,10 +203,10 @@ def test_pressure_row_kernel(kw, steps, start):
 
 
 def test_pressure_large_grid_takes_row_kernel():
-    """4096 x 256 (1 M nodes, above the size threshold): the default choice
+    """8192 x 256 (2 M nodes, at the size threshold): the default choice
     equals the column kernel bit for bit; path values are validated."""
     from paper_1603_01955_amd import ClbError
-    kw = dict(nx=4096, ny=256, xbc="pressure", kn=0.2, p_ratio=1.5, init="linear_rho")
+    kw = dict(nx=8192, ny=256, xbc="pressure", kn=0.2, p_ratio=1.5, init="linear_rho")
     out = []
     for path in (0, 1):
         s = _solver(**kw)
