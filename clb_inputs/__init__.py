@@ -45,6 +45,19 @@ def kn_sweep_channels(count=64, seed=7, heights=(16, 24, 32, 48, 64, 96, 128),
     return [int(v) for v in ny], [float(v) for v in kn]
 
 
+# Pressure ratio and TMAC of the paper's mass-flow study (Section 3.2).
+MASS_FLOW_P_RATIO = 1.8
+MASS_FLOW_SIGMA = 0.93
+
+
+def mass_flow_sweep_kn(count=16, kn_lo=0.01, kn_hi=1.0):
+    """Outlet Knudsen numbers of the pressure-driven mass-flow sweep:
+    ``count`` values log-spaced over [kn_lo, kn_hi] (the study covers Kn_out
+    up to about 0.5 and Kn_ave up to about 0.8)."""
+    kn = kn_lo * (kn_hi / kn_lo) ** (np.arange(count) / max(count - 1, 1))
+    return [float(v) for v in kn]
+
+
 # Workloads (sizes follow the paper's two test problems, Section 3).
 WORKLOADS = {
     # Force-driven periodic channel, small: steady state after 20,000 steps.
@@ -56,4 +69,7 @@ WORKLOADS = {
                                 init="perturbed", init_amp=1e-4, seed=12345),
     # Long channel for the adjoint calibration, L/H = 100.
     "long_2000x20": dict(nx=2000, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, steps=2000),
+    # Mass-flow sweep: 16 long channels, L/H = 100, Kn_out 0.01 .. 1.
+    "mass_flow_sweep_16x2000x20": dict(nx=2000, ny=20, xbc="pressure", p_ratio=MASS_FLOW_P_RATIO,
+                                       sigma=MASS_FLOW_SIGMA, channels=16, kn_lo=0.01, kn_hi=1.0),
 }

@@ -242,6 +242,67 @@ clb_status clb_batch_reset(clb_batch* b);
 clb_status clb_batch_destroy(clb_batch* b);
 
 /* ---------------------------------------------------------------------------
+ * Batch of pressure-driven long channels (Section 3.2, the mass-flow study:
+ * dimensionless mass flow S = m / m_ns against Kn_out, or against
+ * Kn_ave = (Kn_in + Kn_out) / 2, at a fixed pressure ratio and TMAC).
+ * Channel c is described by params[c]: every channel is in pressure mode and
+ * all share nx, ny and cbbsr_shift; Kn_out (kn), p_ratio, rho_out, a, sigma
+ * or A1, A2, r, s3, s8, tq_den and the start may differ.  One launch per step
+ * advances every channel that is still running; each channel advances
+ * bitwise as a single-channel context with the same parameters would.
+ * Populations stay in the caller's workspace (device layout, two buffers
+ * per channel, 144 * nx * ny bytes per channel plus padding).
+ * ------------------------------------------------------------------------- */
+typedef struct clb_pbatch clb_pbatch;
+
+/* Device workspace in bytes for nch channels; CLB_EINVAL names the first
+ * field that is invalid or differs between channels. */
+clb_status clb_pbatch_workspace_size(int32_t nch, const clb_params* params, size_t* bytes);
+
+/* Create the batch over the caller's workspace and enqueue every channel's
+ * start; params is copied.  Synchronises hip_stream once (table upload). */
+clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_workspace, size_t bytes,
+                           void* hip_stream, clb_pbatch** out);
+
+/* Advance every running channel by nsteps steps (asynchronous). */
+clb_status clb_pbatch_step(clb_pbatch* b, int64_t nsteps);
+
+/* Advance the running channels by up to max_steps steps.  With
+ * check_every > 0 (at most 100000), after every check_every steps of this
+ * call each running channel compares its column-mean mass flow
+ * m = (1/nx) sum_x sum_y rho u_x (pre-collision state) with its value at the
+ * previous check and stops once |m - m_previous| <= tol * |m|; the chunk of
+ * steps and its check are recorded once as a hipGraph and replayed, and the
+ * call returns early when every channel has stopped.  Synchronises once per
+ * chunk.  h_steps[nch] (steps per channel) and h_converged[nch] are written
+ * if non-NULL. */
+clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every, double tol,
+                          int64_t* h_steps, int32_t* h_converged);
+
+/* Host arrays of nch values, either may be NULL (not both): h_m the
+ * column-mean mass flow of each channel's current state (as in
+ * clb_pbatch_run; synchronises), h_m_ns the continuum no-slip mass flow of a
+ * long channel with the same pressures and gas (isothermal lubrication
+ * limit, m_ns = H^3 (p_in^2 - p_out^2) / (24 mu RT L) with RT = 1/3,
+ * p = rho/3, H = ny, L = nx, mu = (1/3) sqrt(6/pi) rho_out Kn_out H from
+ * Eqs. 15-17 without the Bosanquet factor).  S = h_m / h_m_ns. */
+clb_status clb_pbatch_massflow(clb_pbatch* b, double* h_m, double* h_m_ns);
+
+/* Per-column sums of channel ch, as clb_column_sums (device arrays [nx],
+ * each may be NULL). */
+clb_status clb_pbatch_column_sums(clb_pbatch* b, int32_t ch, double* d_m, double* d_su, double* d_rhoc);
+
+/* Centre-line pressure deviation of channel ch, as clb_pressure_deviation
+ * (device array [nx]). */
+clb_status clb_pbatch_pressure_deviation(clb_pbatch* b, int32_t ch, double* d_dp);
+
+/* Copy channel ch's post-collision populations out ([9][ny][nx], device). */
+clb_status clb_pbatch_get_populations(clb_pbatch* b, int32_t ch, double* d_out);
+
+/* Release the host context (synchronises the stream first). */
+clb_status clb_pbatch_destroy(clb_pbatch* b);
+
+/* ---------------------------------------------------------------------------
  * Differentiation: hand-written adjoint of the pressure-driven run (Section
  * 3.2).  A run is T steps from the start of *p (normally the linear-density
  * start, CLB_INIT_LINEAR_RHO); its loss is

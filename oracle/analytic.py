@@ -92,17 +92,25 @@ def knudsen_minimum(a, A2):
 
 # ---------------------------------------------------------------------------
 # Long pressure-driven channel, lubrication limit (Section 3.2).  Locally the
-# flow is the force-driven channel above with rho g = -dp/dx, p = rho/3 and a
+# flow is a fully developed channel flow with rho g = -dp/dx, p = rho/3 and a
 # local Knudsen number Kn = Kn_out p_out / p, so rho Kn is constant and
 # mu_e = mu/(1 + a Kn) with mu = (1/3) sqrt(6/pi) rho_out Kn_out H (Eqs. 15-18).
 # The mass flow m = rho sum_y u is then
-#   m = rho g H^3 / (12 nu_e) [1 + 6 A1 k_e + 18 B2 k_e^2 + 3/(4 H^2)]
+#   m = rho g H^3 / (12 nu_e) [1 + 6 A1 k_e + c2 B2 k_e^2 + 3/(4 H^2)]
 # (the last term is the small discrete part of the slip), and m is the same at
-# every x; integrating -dp/dx from the outlet with the trapezoid rule and
-# choosing m so that p(0) = p_in gives the reference pressure profile.
+# every x; integrating -dp/dx from the outlet with RK4 and choosing m so that
+# p(0) = p_in gives the reference pressure profile.  The second-order slip
+# coefficient c2 is 12 for the slip law of Eq. (19) itself (a parabola with
+# slip u_s = A1 lambda_e u' - A2 lambda_e^2 u'' carries
+# 1 + 6 A1 k_e + 12 A2 k_e^2 times the no-slip flow) and 18 for the
+# force-driven periodic channel above, whose body-force source adds the
+# discrete excess of half of B2 (discrete_channel).  A pressure-driven channel
+# has no body force; its steady states follow c2 = 12.
 # ---------------------------------------------------------------------------
-def lubrication_profile(nx, ny, kn_out, p_ratio, a, A1, A2, rho_out=1.0, nsub=20):
-    """Returns (m, p(x_i)) at node centres x_i = i + 1/2 for the lubrication model."""
+def lubrication_profile(nx, ny, kn_out, p_ratio, a, A1, A2, rho_out=1.0, nsub=20, discrete=True, c2=18.0):
+    """Returns (m, p(x_i)) at node centres x_i = i + 1/2 for the lubrication
+    model; discrete=False drops the 3/(4 H^2) term (the continuum model), c2
+    is the coefficient of B2 k_e^2 in the slip bracket."""
     H = float(ny)
     p_out = rho_out / 3.0
     p_in = p_ratio * p_out
@@ -112,7 +120,7 @@ def lubrication_profile(nx, ny, kn_out, p_ratio, a, A1, A2, rho_out=1.0, nsub=20
         kn = kn_out * p_out / p
         ke = kn / (1.0 + a * kn)
         mu_e = mu / (1.0 + a * kn)
-        bracket = 1.0 + 6.0 * A1 * ke + 18.0 * A2 * ke * ke + 0.75 / (H * H)
+        bracket = 1.0 + 6.0 * A1 * ke + c2 * A2 * ke * ke + (0.75 / (H * H) if discrete else 0.0)
         # m = rho (-dp/dx) H^3 / (12 mu_e) * bracket / rho ... with rho = 3 p:
         # m = 3 p (-dp/dx) H^3 bracket / (12 mu_e)
         return -12.0 * mu_e * m / (3.0 * p * H ** 3 * bracket)
@@ -155,3 +163,22 @@ def lubrication_profile(nx, ny, kn_out, p_ratio, a, A1, A2, rho_out=1.0, nsub=20
     xs = [i + 0.5 for i in range(nx)]
     _, prof = integrate(m, xs)
     return m, [prof[x] for x in xs]
+
+
+# ---------------------------------------------------------------------------
+# Continuum no-slip mass flow of the long channel, the m_ns of the
+# dimensionless mass flow S = m / m_ns in Section 3.2.  Without rarefaction
+# the gas has its plain viscosity mu (Eq. 17 without the Bosanquet factor,
+# mu = (1/3) sqrt(6/pi) rho Kn H, the same at every x because rho Kn is
+# constant) and sticks to the walls, so locally m = rho H^3 (-dp/dx) / (12 mu)
+# (plane Poiseuille flow) with rho = p / RT, RT = 1/3.  m is the same at
+# every x, so m dx = -(H^3 / (12 mu RT)) p dp integrates from inlet to outlet
+# to  m_ns = H^3 (p_in^2 - p_out^2) / (24 mu RT L).
+# ---------------------------------------------------------------------------
+def noslip_massflow(nx, ny, kn_out, p_ratio, rho_out=1.0):
+    H, L = float(ny), float(nx)
+    RT = 1.0 / 3.0
+    p_out = rho_out * RT
+    p_in = p_ratio * p_out
+    mu = sqrt(6.0 / pi) * rho_out * kn_out * H / 3.0
+    return H ** 3 * (p_in * p_in - p_out * p_out) / (24.0 * mu * RT * L)

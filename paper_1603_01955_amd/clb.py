@@ -330,3 +330,99 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+_PBATCH_SIGNATURES = {
+    "clb_pbatch_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "clb_pbatch_init": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "clb_pbatch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "clb_pbatch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_pbatch_massflow": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "clb_pbatch_column_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+    "clb_pbatch_pressure_deviation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "clb_pbatch_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "clb_pbatch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+}
+_SIGNATURES.update(_PBATCH_SIGNATURES)
+
+
+def pbatch_workspace_size(params_list):
+    arr = (clb_params * len(params_list))(*params_list)
+    n = ctypes.c_size_t()
+    check(lib().clb_pbatch_workspace_size(len(params_list), arr, ctypes.byref(n)))
+    return n.value
+
+
+class PressureBatch:
+    """Many pressure-driven channels of one grid advanced together (the
+    mass-flow study of Section 3.2).  ``params_list`` holds one clb_params per
+    channel (see make_params, xbc="pressure"); all share nx, ny and
+    cbbsr_shift."""
+
+    def __init__(self, params_list, device="cuda", stream=None):
+        import numpy as np
+        self.params = list(params_list)
+        self.nch = len(self.params)
+        self.nx, self.ny = self.params[0].nx, self.params[0].ny
+        self.device = torch.device(device)
+        self._arr = (clb_params * self.nch)(*self.params)
+        nbytes = pbatch_workspace_size(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib().clb_pbatch_init(self.nch, self._arr, _ptr(self.workspace), nbytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._steps = np.zeros(self.nch, dtype=np.int64)
+        self._conv = np.zeros(self.nch, dtype=np.int32)
+
+    def step(self, n=1):
+        check(lib().clb_pbatch_step(self._h, int(n)))
+
+    def run(self, max_steps, check_every=0, tol=0.0):
+        """Returns (steps per channel, converged flags) as numpy arrays."""
+        check(lib().clb_pbatch_run(self._h, int(max_steps), int(check_every), float(tol),
+                                   self._steps.ctypes.data_as(ctypes.c_void_p),
+                                   self._conv.ctypes.data_as(ctypes.c_void_p)))
+        return self._steps.copy(), self._conv.astype(bool)
+
+    def massflow(self):
+        """(m, m_ns): column-mean mass flow of each channel and the continuum
+        no-slip mass flow of the same channel; S = m / m_ns."""
+        import numpy as np
+        m = np.zeros(self.nch, dtype=np.float64)
+        mns = np.zeros(self.nch, dtype=np.float64)
+        check(lib().clb_pbatch_massflow(self._h, m.ctypes.data_as(ctypes.c_void_p),
+                                        mns.ctypes.data_as(ctypes.c_void_p)))
+        return m, mns
+
+    def column_sums(self, ch):
+        """(m(x), sum_y u_x(x), rho_c(x)) of channel ch, device tensors [nx]."""
+        m, su, rc = (torch.empty(self.nx, dtype=torch.float64, device=self.device) for _ in range(3))
+        check(lib().clb_pbatch_column_sums(self._h, int(ch), _ptr(m), _ptr(su), _ptr(rc)))
+        return m, su, rc
+
+    def pressure_deviation(self, ch):
+        dp = torch.empty(self.nx, dtype=torch.float64, device=self.device)
+        check(lib().clb_pbatch_pressure_deviation(self._h, int(ch), _ptr(dp)))
+        return dp
+
+    def populations(self, ch):
+        out = torch.empty(9, self.ny, self.nx, dtype=torch.float64, device=self.device)
+        check(lib().clb_pbatch_get_populations(self._h, int(ch), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().clb_pbatch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -61,6 +61,41 @@ struct StepArgs {
 // Compute units of the current device (0 if the query fails).
 int device_cus();
 
+// Batch of pressure-driven channels on one grid (nx, ny, wall source shift
+// shared): per-channel parameters of the step.
+struct PChan {
+  double r;             // bounce-back fraction, Eq. (20)
+  double s3, s8;
+  double kn, a, A2, tq_den;
+  double rho_in, rho_out;
+};
+
+// Run state of one channel of such a batch.  Every channel starts at step 0
+// and the channels still running share one step count, so a channel's
+// current populations are in buffer (steps & 1).
+struct PChanState {
+  int64_t steps;        // steps taken
+  int32_t active;       // 0 once converged: no further steps
+  int32_t have_prev;    // prev holds the mass flow of the previous check
+  double prev;          // column-mean mass flow at the previous check
+};
+
+struct PBatchArgs {
+  double* buf[2];       // buffer k of channel c at buf[k] + c * stride
+  size_t stride;        // doubles per channel buffer (Geo::size, padded)
+  Geo g;
+  int nch;
+  int shift;            // Eq. (20) specular source from x -/+ 1
+  int xcd_remap;
+  int par;              // step: read buf[par], write buf[par ^ 1]
+  int ghost_lds;        // set by the launcher
+  int nblk;             // column workgroups per channel, set by the launcher
+  int cus;
+  double c_tau;         // sqrt(6/pi) * ny
+  const PChan* ch;      // [nch]
+  const PChanState* state;   // [nch]
+};
+
 struct InitArgs {
   double* dst;
   Geo g;
@@ -96,6 +131,8 @@ constexpr size_t kPressureRowNodes = (size_t)1 << 21;
 hipError_t periodic_step_lds(int block_x, size_t* bytes);
 // lds_reserve: see periodic_step_lds (periodic mode only).
 hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t lds_reserve = 0);
+// One step of every active channel of a pressure-driven batch.
+hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st);
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);

@@ -75,7 +75,7 @@ constexpr int PY = 16;
 // issues its own gather loads before the staging, so the two overlap; the
 // few ghost-sourced values are patched in after the barrier.
 template <int RY, int MODE, int NT>
-__device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather<MODE, View>& gat, int blk,
+__device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather<MODE, View>& gat, int blk, int nblk,
                                                  double (*s_rc)[NT / RY], double* s_ghost) {
   constexpr int CX = NT / RY;
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -84,8 +84,8 @@ __device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather
   const bool even = (ny & 1) == 0;
   auto stage = [&]() {
     if (MODE == 2) {
-      fill_ghosts(gat.v, a.rho_in, a.rho_out, blk == 0, blk == (int)gridDim.x - 1, s_ghost, s_ghost + 9 * ny,
-                  ty * CX + tx, NT);
+      fill_ghosts(gat.v, a.rho_in, a.rho_out, blk == 0, blk == nblk - 1, s_ghost, s_ghost + 9 * ny, ty * CX + tx,
+                  NT);
       __syncthreads();
     }
   };
@@ -136,25 +136,67 @@ __device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather
   }
 }
 
+// Column workgroup blk of nblk covering one channel.
 template <int RY, int NT>
-__global__ __launch_bounds__(NT) void k_step_pressure(StepArgs a) {
-  constexpr int CX = NT / RY;
-  extern __shared__ double s_ghost[];   // [2][9][ny] in the first / last workgroup
-  __shared__ double s_rc[2][CX];
+__device__ __forceinline__ void pressure_block(const StepArgs& a, int blk, int nblk, double (*s_rc)[NT / RY],
+                                               double* s_ghost) {
   const View v{a.src, a.g};
   const double omr = 1.0 - a.r;
-  const int blk = logical_block(a.xcd_remap);
-  if (blk != 0 && blk != (int)gridDim.x - 1) {
+  if (blk != 0 && blk != nblk - 1) {
     // every x - 1 and x + 1 of this workgroup lies inside the grid
-    pressure_columns<RY, 3, NT>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc, nullptr);
+    pressure_columns<RY, 3, NT>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, nblk, s_rc,
+                                nullptr);
   } else if (a.ghost_lds) {
     const int ny = a.g.ny;
     pressure_columns<RY, 2, NT>(
-        a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, blk, s_rc,
+        a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, blk, nblk, s_rc,
         s_ghost);
   } else {
-    pressure_columns<RY, 1, NT>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, s_rc, nullptr);
+    pressure_columns<RY, 1, NT>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, nblk, s_rc,
+                                nullptr);
   }
+}
+
+template <int RY, int NT>
+__global__ __launch_bounds__(NT) void k_step_pressure(StepArgs a) {
+  extern __shared__ double s_ghost[];   // [2][9][ny] in the first / last workgroup
+  __shared__ double s_rc[2][NT / RY];
+  pressure_block<RY, NT>(a, logical_block(a.xcd_remap), (int)gridDim.x, s_rc, s_ghost);
+}
+
+// ---------------------------------------------------------------------------
+// K2c: one step of a batch of pressure-driven channels of the same grid
+// (the mass-flow sweep of Section 3.2), in one launch: workgroup b serves
+// column block b % nblk of channel b / nblk with that channel's parameters,
+// the same arithmetic as K2 (bitwise the same populations).  Channels that
+// have stopped (converged) are skipped.
+// ---------------------------------------------------------------------------
+template <int RY, int NT>
+__global__ __launch_bounds__(NT) void k_pbatch_step(PBatchArgs p) {
+  extern __shared__ double s_ghost[];
+  __shared__ double s_rc[2][NT / RY];
+  const int b = logical_block(p.xcd_remap);
+  const int c = b / p.nblk;
+  if (!p.state[c].active) return;
+  const PChan ch = p.ch[c];
+  StepArgs a{};
+  a.src = p.buf[p.par] + (size_t)c * p.stride;
+  a.dst = p.buf[p.par ^ 1] + (size_t)c * p.stride;
+  a.g = p.g;
+  a.mode = 1;
+  a.shift = p.shift;
+  a.ghost_lds = p.ghost_lds;
+  a.r = ch.r;
+  a.s3 = ch.s3;
+  a.s8 = ch.s8;
+  a.kn = ch.kn;
+  a.a = ch.a;
+  a.A2 = ch.A2;
+  a.tq_den = ch.tq_den;
+  a.c_tau = p.c_tau;
+  a.rho_in = ch.rho_in;
+  a.rho_out = ch.rho_out;
+  pressure_block<RY, NT>(a, b - c * p.nblk, p.nblk, s_rc, s_ghost);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,6 +428,53 @@ unsigned grid_for(size_t n, unsigned cap = 65536) {
   return (unsigned)b;
 }
 
+// Shape of the column kernels: RY row lanes (the smallest of 16, 32, 64
+// covering ny) and the widest workgroup, NT threads = NT / RY adjacent
+// columns (longer coalesced row pieces per wave), that still leaves about
+// one workgroup per CU over all nch channels.  Measured on one channel:
+// 4000 x 40 10.2 -> 6.9 us per step with 1024 threads; 2000 x 20 stays
+// fastest at 256.
+struct ColumnShape {
+  int ry, nt, nblk;   // nblk: column workgroups per channel
+};
+
+ColumnShape column_shape(const Geo& g, int nch, int cus) {
+  ColumnShape s;
+  s.ry = g.ny <= 16 ? 16 : (g.ny <= 32 ? 32 : 64);
+  const long enough = cus > 0 ? cus - cus / 10 : 230;
+  s.nt = 256;
+  for (const int cand : {1024, 512})
+    if ((long)nch * ((g.nx + cand / s.ry - 1) / (cand / s.ry)) >= enough) {
+      s.nt = cand;
+      break;
+    }
+  const int cx = s.nt / s.ry;
+  s.nblk = (g.nx + cx - 1) / cx;
+  return s;
+}
+
+size_t ghost_lds_bytes(const Geo& g) {
+  return g.ny <= kGhostLdsMaxNy ? 2 * 9 * (size_t)g.ny * sizeof(double) : 0;
+}
+
+// Launch LAUNCH(RY, NT) for the template instance that shape s names.
+#define CLB_COLUMN_DISPATCH(s, LAUNCH)          \
+  do {                                          \
+    if ((s).nt == 1024) {                       \
+      if ((s).ry == 16) LAUNCH(16, 1024);       \
+      else if ((s).ry == 32) LAUNCH(32, 1024);  \
+      else LAUNCH(64, 1024);                    \
+    } else if ((s).nt == 512) {                 \
+      if ((s).ry == 16) LAUNCH(16, 512);        \
+      else if ((s).ry == 32) LAUNCH(32, 512);   \
+      else LAUNCH(64, 512);                     \
+    } else {                                    \
+      if ((s).ry == 16) LAUNCH(16, 256);        \
+      else if ((s).ry == 32) LAUNCH(32, 256);   \
+      else LAUNCH(64, 256);                     \
+    }                                           \
+  } while (0)
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -445,36 +534,26 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
   } else {
     StepArgs b = a;
     b.ghost_lds = a.g.ny <= kGhostLdsMaxNy ? 1 : 0;
-    const size_t lds = b.ghost_lds ? 2 * 9 * (size_t)a.g.ny * sizeof(double) : 0;
-    const int ry = a.g.ny <= 16 ? 16 : (a.g.ny <= 32 ? 32 : 64);
-    // The widest workgroup (more adjacent columns per wave, better coalesced
-    // rows) that still leaves about one workgroup per CU.  Measured: 4000 x 40
-    // 10.2 -> 6.9 us per step with 1024 threads; 2000 x 20 stays fastest at 256.
-    const int enough = a.cus > 0 ? a.cus - a.cus / 10 : 230;
-    int nt = 256;
-    for (const int cand : {1024, 512})
-      if ((a.g.nx + cand / ry - 1) / (cand / ry) >= enough) {
-        nt = cand;
-        break;
-      }
-    const int cx = nt / ry;
-    const dim3 pgrid((unsigned)((a.g.nx + cx - 1) / cx));
-#define CLB_PRESSURE_LAUNCH(RYV, NTV) k_step_pressure<RYV, NTV><<<pgrid, dim3(cx, ry), lds, st>>>(b)
-    if (nt == 1024) {
-      if (ry == 16) CLB_PRESSURE_LAUNCH(16, 1024);
-      else if (ry == 32) CLB_PRESSURE_LAUNCH(32, 1024);
-      else CLB_PRESSURE_LAUNCH(64, 1024);
-    } else if (nt == 512) {
-      if (ry == 16) CLB_PRESSURE_LAUNCH(16, 512);
-      else if (ry == 32) CLB_PRESSURE_LAUNCH(32, 512);
-      else CLB_PRESSURE_LAUNCH(64, 512);
-    } else {
-      if (ry == 16) CLB_PRESSURE_LAUNCH(16, 256);
-      else if (ry == 32) CLB_PRESSURE_LAUNCH(32, 256);
-      else CLB_PRESSURE_LAUNCH(64, 256);
-    }
+    const ColumnShape s = column_shape(a.g, 1, a.cus);
+    const dim3 pgrid((unsigned)s.nblk);
+#define CLB_PRESSURE_LAUNCH(RYV, NTV) \
+  k_step_pressure<RYV, NTV><<<pgrid, dim3(NTV / RYV, RYV), ghost_lds_bytes(a.g), st>>>(b)
+    CLB_COLUMN_DISPATCH(s, CLB_PRESSURE_LAUNCH);
 #undef CLB_PRESSURE_LAUNCH
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st) {
+  const ColumnShape s = column_shape(a.g, a.nch, a.cus);
+  PBatchArgs b = a;
+  b.ghost_lds = a.g.ny <= kGhostLdsMaxNy ? 1 : 0;
+  b.nblk = s.nblk;
+  const dim3 grid((unsigned)((size_t)s.nblk * a.nch));
+#define CLB_PBATCH_LAUNCH(RYV, NTV) \
+  k_pbatch_step<RYV, NTV><<<grid, dim3(NTV / RYV, RYV), ghost_lds_bytes(a.g), st>>>(b)
+  CLB_COLUMN_DISPATCH(s, CLB_PBATCH_LAUNCH);
+#undef CLB_PBATCH_LAUNCH
   return hipGetLastError();
 }
 

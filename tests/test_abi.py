@@ -142,6 +142,40 @@ def test_batch_validation(lib):
     assert lib.clb_batch_destroy(None) == clb.CLB_EINVAL
 
 
+def test_pressure_batch_validation(lib):
+    """A pressure batch holds pressure-driven channels of one grid and one
+    wall-source shift; its workspace holds two buffers per channel."""
+    Params = clb.clb_params * 3
+    ps = Params(clb.make_params(300, 10, xbc="pressure", kn=0.05, p_ratio=1.8, sigma=0.93),
+                clb.make_params(300, 10, xbc="pressure", kn=0.5, p_ratio=2.0, A2=0.3),
+                clb.make_params(300, 10, xbc="pressure", kn=2.0, p_ratio=1.5, init="uniform"))
+    n = ctypes.c_size_t()
+    assert lib.clb_pbatch_workspace_size(ctypes.c_int32(3), ps, ctypes.byref(n)) == clb.CLB_OK
+    assert n.value >= 3 * 2 * 72 * 512 * 10   # rows padded to 512 lanes
+    assert lib.clb_pbatch_workspace_size(ctypes.c_int32(0), ps, ctypes.byref(n)) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_workspace_size(ctypes.c_int32(3), ps, None) == clb.CLB_EINVAL
+    for bad_ch, field in ((clb.make_params(300, 10, kn=0.1, gx=1e-6), "xbc"),
+                          (clb.make_params(301, 10, xbc="pressure"), "nx/ny"),
+                          (clb.make_params(300, 11, xbc="pressure"), "nx/ny"),
+                          (clb.make_params(300, 10, xbc="pressure", cbbsr_shift=0), "cbbsr_shift"),
+                          (clb.make_params(300, 10, xbc="pressure", kn=-1.0), "kn")):
+        bad = Params(ps[0], bad_ch, ps[2])
+        assert lib.clb_pbatch_workspace_size(ctypes.c_int32(3), bad, ctypes.byref(n)) == clb.CLB_EINVAL
+        assert lib.clb_last_error().decode().startswith(field)
+    out = ctypes.c_void_p()
+    assert lib.clb_pbatch_init(ctypes.c_int32(3), ps, None, ctypes.c_size_t(0), None,
+                               ctypes.byref(out)) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_init(ctypes.c_int32(3), ps, ctypes.c_void_p(4096), ctypes.c_size_t(16), None,
+                               ctypes.byref(out)) == clb.CLB_ENOMEM
+    assert out.value is None
+    assert lib.clb_pbatch_step(None, ctypes.c_int64(1)) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_run(None, ctypes.c_int64(10), ctypes.c_int32(0), ctypes.c_double(0.0), None,
+                              None) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_massflow(None, None, None) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_get_populations(None, ctypes.c_int32(0), None) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_destroy(None) == clb.CLB_EINVAL
+
+
 def test_adjoint_validation(lib):
     """The adjoint covers the pressure-driven channel, T >= 1, 1 <= K <= T;
     its workspace holds the checkpoints and two recompute sets."""

@@ -62,3 +62,58 @@ def test_slip_grows_downstream(steady_long_channel):
     _, ux, _ = C.moments(P, prm)
     slip = ux[0] / ux.max(axis=0)
     assert slip[-10] > slip[10]
+
+
+@pytest.mark.parametrize("nx,ny,kn,ratio", [(2000, 20, 0.1, 1.8), (400, 7, 0.47, 2.0), (100, 40, 0.01, 1.2)])
+def test_noslip_massflow_integrates_the_lubrication_equation(nx, ny, kn, ratio):
+    """The closed-form m_ns equals the lubrication equation integrated
+    numerically (RK4 from the outlet, m by bisection on the inlet pressure)
+    with every rarefaction term switched off: no slip (A1 = A2 = 0), no
+    Bosanquet factor (a = 0), no discrete wall term."""
+    m_num, _ = A.lubrication_profile(nx, ny, kn, ratio, 0.0, 0.0, 0.0, nsub=4, discrete=False)
+    assert abs(A.noslip_massflow(nx, ny, kn, ratio) / m_num - 1.0) <= 1e-9
+
+
+def test_noslip_massflow_is_poiseuille_at_mean_density():
+    """p_in^2 - p_out^2 = 2 p_mean (p_in - p_out), so the compressible m_ns is
+    plane Poiseuille flow, m = rho H^3 (p_in - p_out) / (12 mu L), with rho the
+    mean of the inlet and outlet densities, at any pressure ratio."""
+    nx, ny, kn, rho_out = 500, 16, 0.2, 1.3
+    for ratio in (1.001, 1.8, 3.0):
+        m = A.noslip_massflow(nx, ny, kn, ratio, rho_out=rho_out)
+        rho = rho_out * (1.0 + ratio) / 2.0
+        mu = np.sqrt(6.0 / np.pi) * rho_out * kn * ny / 3.0
+        dp = (ratio - 1.0) * rho_out / 3.0
+        assert abs(m / (rho * ny ** 3 * dp / (12.0 * mu * nx)) - 1.0) <= 1e-12
+
+
+def test_slip_raises_the_lubrication_mass_flow_above_noslip():
+    """With slip and the Bosanquet factor the lubrication model carries more
+    mass than the no-slip channel, more so at larger Kn_out (S > 1 and
+    increasing; at ratio 1.8, sigma = 0.93 as in the paper's mass-flow study)."""
+    A1 = C.slip_A1(0.93)
+    S = [A.lubrication_profile(200, 10, kn, 1.8, 2.0, A1, 0.55, nsub=2)[0] / A.noslip_massflow(200, 10, kn, 1.8)
+         for kn in (0.02, 0.1, 0.4)]
+    assert 1.0 < S[0] < S[1] < S[2]
+
+
+def test_pressure_driven_channel_carries_the_eq19_slip():
+    """Without a body force the steady pressure-driven channel carries the
+    mass flow of the lubrication model built on the slip law of Eq. (19)
+    itself (second-order coefficient 12 B2), not the force-driven periodic
+    channel's discrete 18 B2: at Kn_out = 0.5 (200 x 4, ratio 1.8,
+    sigma = 0.93) the two models differ by 6%."""
+    prm = C.Params(nx=200, ny=4, xbc="pressure", kn=0.5, p_ratio=1.8, sigma=0.93)
+    P = C.init_linear_rho(prm)
+    prev = None
+    for _ in range(60):
+        P = C.run(P, prm, 500)
+        m = C.column_sums(P, prm)[0].mean()
+        if prev is not None and abs(m - prev) <= 1e-7 * abs(m):
+            break
+        prev = m
+    A1, _ = C.resolved(prm)
+    m12, _ = A.lubrication_profile(200, 4, 0.5, 1.8, 2.0, A1, 0.55, nsub=2, c2=12.0)
+    m18, _ = A.lubrication_profile(200, 4, 0.5, 1.8, 2.0, A1, 0.55, nsub=2, c2=18.0)
+    assert abs(m / m12 - 1.0) < 0.01
+    assert m / m18 < 0.95
