@@ -279,6 +279,14 @@ clb_status clb_pbatch_step(clb_pbatch* b, int64_t nsteps);
 clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every, double tol,
                           int64_t* h_steps, int32_t* h_converged);
 
+/* Kernel choice (tuning): 0 = by total size (default; the row form from
+ * 2^21 nodes over all channels), 1 = column kernel (each workgroup owns whole
+ * columns of one channel), 2 = row kernel (a prep launch computes every
+ * running channel's per-column rates and ghost columns, then one launch
+ * streams whole row segments of all channels).  Both give bitwise the same
+ * populations.  CLB_EINVAL for other values. */
+clb_status clb_pbatch_set_path(clb_pbatch* b, int32_t path);
+
 /* Host arrays of nch values, either may be NULL (not both): h_m the
  * column-mean mass flow of each channel's current state (as in
  * clb_pbatch_run; synchronises), h_m_ns the continuum no-slip mass flow of a

@@ -94,6 +94,11 @@ struct PBatchArgs {
   double c_tau;         // sqrt(6/pi) * ny
   const PChan* ch;      // [nch]
   const PChanState* state;   // [nch]
+  // row-kernel form: per-channel scratch filled by its prep launch each step
+  // (null: column kernel only)
+  double* col_rates;    // [nch][2][nx]
+  double* ghosts;       // [nch][2][9][ny]
+  int path;             // 0 by total size, 1 column kernel, 2 row kernel
 };
 
 struct InitArgs {
@@ -131,8 +136,11 @@ constexpr size_t kPressureRowNodes = (size_t)1 << 21;
 hipError_t periodic_step_lds(int block_x, size_t* bytes);
 // lds_reserve: see periodic_step_lds (periodic mode only).
 hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t lds_reserve = 0);
-// One step of every active channel of a pressure-driven batch.
-hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st);
+// Batches with at least this many nodes in all take the row kernel.
+constexpr size_t kPBatchRowNodes = (size_t)1 << 21;
+// One step of every active channel of a pressure-driven batch; lds_reserve
+// as for launch_step (row kernel only).
+hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_reserve = 0);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st);
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);

@@ -54,13 +54,12 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K2: fused pressure-driven step.  Block = (NT / RY) columns x RY row lanes
-// with RY the smallest of 16, 32, 64 covering ny, so that up to ny = 64 each
-// thread owns one node and long narrow channels (2000 x 20: 250 workgroups)
-// fill the chip.  The centre-line density of each column (same step,
-// pre-collision) sets the local Knudsen number Kn(x) = Kn_out rho_out /
-// rho_c(x) (Section 3.2) and through Eqs. (18), (21) the column's s_nu and
-// s_q.  With one node per thread the centre-row threads publish their own
+// K2: fused pressure-driven step.  Block = CX columns x ny rows (64 row
+// lanes for taller channels), so that up to ny = 64 each thread owns one
+// node and long narrow channels (2000 x 20: 250 workgroups) fill the chip.
+// The centre-line density of each column (same step, pre-collision) sets
+// the local Knudsen number Kn(x) = Kn_out rho_out / rho_c(x) (Section 3.2)
+// and through Eqs. (18), (21) the column's s_nu and s_q.  With one node per thread the centre-row threads publish their own
 // density through LDS; otherwise the first row lane gathers the centre rows.
 // Workgroups take the XCD-aware order; interior ones gather with no
 // x-boundary code, the first and last stage the two ghost columns in LDS
@@ -69,28 +68,32 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 constexpr int PX = 16;   // column-sum diagnostics: 16 columns x 16 row lanes
 constexpr int PY = 16;
 
-// One workgroup's columns with the gather of MODE 3 (interior), 2 (ghost
+// One workgroup's CX columns with the gather of MODE 3 (interior), 2 (ghost
 // columns staged in s_ghost by this workgroup) or 1 (ghosts inline).
-// s_rc: [2][CX] centre-row densities.  With staged ghosts every thread
-// issues its own gather loads before the staging, so the two overlap; the
-// few ghost-sourced values are patched in after the barrier.
-template <int RY, int MODE, int NT>
+// s_rc: [2][CX] centre-row densities.  ONE: the workgroup is exactly ny rows
+// tall (ny <= 64), one node per thread; otherwise it has 64 row lanes and
+// each thread walks rows y, y + 64, ...  The two forms are separate kernel
+// instances: the row loop needs about twice the registers, which would
+// halve the waves in flight of the one-node form used by the paper's
+// channels.  With staged ghosts every thread issues its own gather loads
+// before the staging, so the two overlap; the few ghost-sourced values are
+// patched in after the barrier.
+template <int MODE, int CX, bool ONE>
 __device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather<MODE, View>& gat, int blk, int nblk,
-                                                 double (*s_rc)[NT / RY], double* s_ghost) {
-  constexpr int CX = NT / RY;
-  const int tx = threadIdx.x, ty = threadIdx.y;
+                                                 double (*s_rc)[CX], double* s_ghost) {
+  const int tx = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
   const int x = blk * CX + tx;
   const int ny = a.g.ny, yc = ny / 2;
   const bool even = (ny & 1) == 0;
   auto stage = [&]() {
     if (MODE == 2) {
       fill_ghosts(gat.v, a.rho_in, a.rho_out, blk == 0, blk == nblk - 1, s_ghost, s_ghost + 9 * ny, ty * CX + tx,
-                  NT);
+                  CX * ry);
       __syncthreads();
     }
   };
-  if (ny <= RY) {
-    const bool active = x < a.g.nx && ty < ny;
+  if constexpr (ONE) {
+    const bool active = x < a.g.nx;
     double f[9];
     if constexpr (MODE == 2) {
       double A[9], B[4];
@@ -114,54 +117,61 @@ __device__ __forceinline__ void pressure_columns(const StepArgs& a, const Gather
     local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
     collide<false>(f, 0.0, 0.0, Rates{a.s3, snu, sq, a.s8});
     store9(a.dst, a.g, x, ty, f);
-    return;
-  }
-  stage();
-  if (ty < 2 && x < a.g.nx && (ty == 0 || even)) {
-    double f[9];
-    gather_node(gat, x, yc - ty, f);
-    s_rc[ty][tx] = sum9(f);
-  }
-  __syncthreads();
-  if (x >= a.g.nx) return;
-  const double rc = even ? 0.5 * (s_rc[1][tx] + s_rc[0][tx]) : s_rc[0][tx];
-  double snu, sq;
-  local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
-  const Rates s{a.s3, snu, sq, a.s8};
-  for (int y = ty; y < ny; y += RY) {
-    double f[9];
-    gather_node(gat, x, y, f);
-    collide<false>(f, 0.0, 0.0, s);
-    store9(a.dst, a.g, x, y, f);
+  } else {
+    stage();
+    if (ty < 2 && x < a.g.nx && (ty == 0 || even)) {
+      double f[9];
+      gather_node(gat, x, yc - ty, f);
+      s_rc[ty][tx] = sum9(f);
+    }
+    __syncthreads();
+    if (x >= a.g.nx) return;
+    const double rc = even ? 0.5 * (s_rc[1][tx] + s_rc[0][tx]) : s_rc[0][tx];
+    double snu, sq;
+    local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
+    const Rates s{a.s3, snu, sq, a.s8};
+    for (int y = ty; y < ny; y += ry) {
+      double f[9];
+      gather_node(gat, x, y, f);
+      collide<false>(f, 0.0, 0.0, s);
+      store9(a.dst, a.g, x, y, f);
+    }
   }
 }
 
-// Column workgroup blk of nblk covering one channel.
-template <int RY, int NT>
-__device__ __forceinline__ void pressure_block(const StepArgs& a, int blk, int nblk, double (*s_rc)[NT / RY],
+// Column workgroup blk of nblk covering one channel (ONE: ny <= 64, so the
+// ghost columns always fit in LDS).
+template <int CX, bool ONE>
+__device__ __forceinline__ void pressure_block(const StepArgs& a, int blk, int nblk, double (*s_rc)[CX],
                                                double* s_ghost) {
   const View v{a.src, a.g};
   const double omr = 1.0 - a.r;
   if (blk != 0 && blk != nblk - 1) {
     // every x - 1 and x + 1 of this workgroup lies inside the grid
-    pressure_columns<RY, 3, NT>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, nblk, s_rc,
-                                nullptr);
-  } else if (a.ghost_lds) {
+    pressure_columns<3, CX, ONE>(a, Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, nblk, s_rc,
+                                     nullptr);
+  } else if (ONE || a.ghost_lds) {
     const int ny = a.g.ny;
-    pressure_columns<RY, 2, NT>(
+    pressure_columns<2, CX, ONE>(
         a, Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, s_ghost, s_ghost + 9 * ny}, blk, nblk, s_rc,
         s_ghost);
   } else {
-    pressure_columns<RY, 1, NT>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, nblk, s_rc,
-                                nullptr);
+    pressure_columns<1, CX, ONE>(a, Gather<1, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, blk, nblk, s_rc,
+                                     nullptr);
   }
 }
 
-template <int RY, int NT>
-__global__ __launch_bounds__(NT) void k_step_pressure(StepArgs a) {
+// Threads of a column workgroup at most: CX * ny <= 1024 (ONE), CX * 64.
+template <int CX, bool ONE>
+constexpr int column_threads() {
+  return ONE ? 1024 : CX * 64;
+}
+
+template <int CX, bool ONE>
+__global__ __launch_bounds__((column_threads<CX, ONE>())) void k_step_pressure(StepArgs a) {
   extern __shared__ double s_ghost[];   // [2][9][ny] in the first / last workgroup
-  __shared__ double s_rc[2][NT / RY];
-  pressure_block<RY, NT>(a, logical_block(a.xcd_remap), (int)gridDim.x, s_rc, s_ghost);
+  __shared__ double s_rc[2][CX];
+  pressure_block<CX, ONE>(a, logical_block(a.xcd_remap), (int)gridDim.x, s_rc, s_ghost);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,13 +181,8 @@ __global__ __launch_bounds__(NT) void k_step_pressure(StepArgs a) {
 // the same arithmetic as K2 (bitwise the same populations).  Channels that
 // have stopped (converged) are skipped.
 // ---------------------------------------------------------------------------
-template <int RY, int NT>
-__global__ __launch_bounds__(NT) void k_pbatch_step(PBatchArgs p) {
-  extern __shared__ double s_ghost[];
-  __shared__ double s_rc[2][NT / RY];
-  const int b = logical_block(p.xcd_remap);
-  const int c = b / p.nblk;
-  if (!p.state[c].active) return;
+// Step arguments of channel c of a batch.
+__device__ __forceinline__ StepArgs channel_args(const PBatchArgs& p, int c) {
   const PChan ch = p.ch[c];
   StepArgs a{};
   a.src = p.buf[p.par] + (size_t)c * p.stride;
@@ -196,7 +201,21 @@ __global__ __launch_bounds__(NT) void k_pbatch_step(PBatchArgs p) {
   a.c_tau = p.c_tau;
   a.rho_in = ch.rho_in;
   a.rho_out = ch.rho_out;
-  pressure_block<RY, NT>(a, b - c * p.nblk, p.nblk, s_rc, s_ghost);
+  if (p.col_rates) {
+    a.col_rates = p.col_rates + (size_t)c * 2 * p.g.nx;
+    a.ghosts = p.ghosts + (size_t)c * 18 * p.g.ny;
+  }
+  return a;
+}
+
+template <int CX, bool ONE>
+__global__ __launch_bounds__((column_threads<CX, ONE>())) void k_pbatch_step(PBatchArgs p) {
+  extern __shared__ double s_ghost[];
+  __shared__ double s_rc[2][CX];
+  const int b = logical_block(p.xcd_remap);
+  const int c = b / p.nblk;
+  if (!p.state[c].active) return;
+  pressure_block<CX, ONE>(channel_args(p, c), b - c * p.nblk, p.nblk, s_rc, s_ghost);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,12 +227,13 @@ __global__ __launch_bounds__(NT) void k_pbatch_step(PBatchArgs p) {
 // workgroup), reading the rates and ghosts from those arrays.  Bitwise the
 // same result as K2.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pressure_prep(StepArgs a) {
+// Prep work item `bid` of a channel: blocks below ncb compute the rates of
+// 256 columns each, the rest build 256 ghost rows each.
+__device__ __forceinline__ void pressure_prep_block(const StepArgs& a, int bid, int ncb) {
   const int nx = a.g.nx, ny = a.g.ny;
   const View v{a.src, a.g};
-  const int ncb = (nx + 255) / 256;
-  if ((int)blockIdx.x < ncb) {
-    const int x = blockIdx.x * 256 + threadIdx.x;
+  if (bid < ncb) {
+    const int x = bid * 256 + threadIdx.x;
     if (x >= nx) return;
     const Gather<1, View> gat{v, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
     const int yc = ny / 2;
@@ -230,7 +250,7 @@ __global__ __launch_bounds__(256) void k_pressure_prep(StepArgs a) {
     a.col_rates[nx + x] = sq;
   } else {
     // ghost rows: j < ny inlet row j, else outlet row j - ny
-    const int j = ((int)blockIdx.x - ncb) * 256 + threadIdx.x;
+    const int j = (bid - ncb) * 256 + threadIdx.x;
     if (j >= 2 * ny) return;
     const bool inlet = j < ny;
     const int y = inlet ? j : j - ny;
@@ -241,8 +261,8 @@ __global__ __launch_bounds__(256) void k_pressure_prep(StepArgs a) {
   }
 }
 
-__global__ __launch_bounds__(1024) void k_step_pressure_rows(StepArgs a) {
-  const size_t t = (size_t)logical_block(a.xcd_remap) * blockDim.x + threadIdx.x;
+// Row-kernel node update of padded node t (device-layout order).
+__device__ __forceinline__ void pressure_rows_node(const StepArgs& a, size_t t) {
   const int lane = (int)(t & (((size_t)1 << a.g.lshift) - 1));
   const size_t rest = t >> a.g.lshift;
   const int y = (int)(rest / (size_t)a.g.nseg);
@@ -256,6 +276,34 @@ __global__ __launch_bounds__(1024) void k_step_pressure_rows(StepArgs a) {
   gat(x, y, f);
   collide<false>(f, 0.0, 0.0, Rates{a.s3, a.col_rates[x], a.col_rates[a.g.nx + x], a.s8});
   store9(a.dst, a.g, x, y, f);
+}
+
+__global__ __launch_bounds__(256) void k_pressure_prep(StepArgs a) {
+  pressure_prep_block(a, blockIdx.x, (a.g.nx + 255) / 256);
+}
+
+__global__ __launch_bounds__(1024) void k_step_pressure_rows(StepArgs a) {
+  pressure_rows_node(a, (size_t)logical_block(a.xcd_remap) * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// K2d: row-kernel form of K2c for batches of many channels: per step a prep
+// launch over every running channel, then one row-streaming launch over
+// all of them (channel-major, each channel's grid in device-layout order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pbatch_prep(PBatchArgs p) {
+  const int ncb = (p.g.nx + 255) / 256;
+  const int per = ncb + (2 * p.g.ny + 255) / 256;
+  const int c = blockIdx.x / per;
+  if (!p.state[c].active) return;
+  pressure_prep_block(channel_args(p, c), (int)blockIdx.x - c * per, ncb);
+}
+
+__global__ __launch_bounds__(1024) void k_pbatch_rows(PBatchArgs p) {
+  const int b = logical_block(p.xcd_remap);
+  const int c = b / p.nblk;
+  if (!p.state[c].active) return;
+  pressure_rows_node(channel_args(p, c), (size_t)(b - c * p.nblk) * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,28 +476,28 @@ unsigned grid_for(size_t n, unsigned cap = 65536) {
   return (unsigned)b;
 }
 
-// Shape of the column kernels: RY row lanes (the smallest of 16, 32, 64
-// covering ny) and the widest workgroup, NT threads = NT / RY adjacent
-// columns (longer coalesced row pieces per wave), that still leaves about
-// one workgroup per CU over all nch channels.  Measured on one channel:
-// 4000 x 40 10.2 -> 6.9 us per step with 1024 threads; 2000 x 20 stays
-// fastest at 256.
+// Shape of the column kernels: CX adjacent columns x ry rows, ry = ny for
+// ny <= 64 (one node per thread, no idle rows) else 64.  CX is the widest of
+// 64, 32, 16, 8, 4 with CX * ry <= 1024 that still leaves about one
+// workgroup per CU over all nch channels (longer coalesced row pieces per
+// wave), else the narrowest.  Measured on one channel: 4000 x 40 10.2 ->
+// 6.3 us per step against 256-thread workgroups; 2000 x 20 keeps 8 columns.
 struct ColumnShape {
-  int ry, nt, nblk;   // nblk: column workgroups per channel
+  int cx, ry, nblk;   // nblk: column workgroups per channel
+  bool one;           // ny <= 64: one node per thread
 };
 
 ColumnShape column_shape(const Geo& g, int nch, int cus) {
   ColumnShape s;
-  s.ry = g.ny <= 16 ? 16 : (g.ny <= 32 ? 32 : 64);
+  s.one = g.ny <= 64;
+  s.ry = s.one ? g.ny : 64;
   const long enough = cus > 0 ? cus - cus / 10 : 230;
-  s.nt = 256;
-  for (const int cand : {1024, 512})
-    if ((long)nch * ((g.nx + cand / s.ry - 1) / (cand / s.ry)) >= enough) {
-      s.nt = cand;
-      break;
-    }
-  const int cx = s.nt / s.ry;
-  s.nblk = (g.nx + cx - 1) / cx;
+  for (const int cand : {64, 32, 16, 8, 4}) {
+    if (cand * s.ry > (s.one ? 1024 : 512)) continue;
+    s.cx = cand;   // the narrowest one if none leaves enough workgroups
+    if ((long)nch * ((g.nx + cand - 1) / cand) >= enough) break;
+  }
+  s.nblk = (g.nx + s.cx - 1) / s.cx;
   return s;
 }
 
@@ -457,22 +505,19 @@ size_t ghost_lds_bytes(const Geo& g) {
   return g.ny <= kGhostLdsMaxNy ? 2 * 9 * (size_t)g.ny * sizeof(double) : 0;
 }
 
-// Launch LAUNCH(RY, NT) for the template instance that shape s names.
-#define CLB_COLUMN_DISPATCH(s, LAUNCH)          \
-  do {                                          \
-    if ((s).nt == 1024) {                       \
-      if ((s).ry == 16) LAUNCH(16, 1024);       \
-      else if ((s).ry == 32) LAUNCH(32, 1024);  \
-      else LAUNCH(64, 1024);                    \
-    } else if ((s).nt == 512) {                 \
-      if ((s).ry == 16) LAUNCH(16, 512);        \
-      else if ((s).ry == 32) LAUNCH(32, 512);   \
-      else LAUNCH(64, 512);                     \
-    } else {                                    \
-      if ((s).ry == 16) LAUNCH(16, 256);        \
-      else if ((s).ry == 32) LAUNCH(32, 256);   \
-      else LAUNCH(64, 256);                     \
-    }                                           \
+// Launch LAUNCH(CX, ONE) for the template instance that shape s names.
+#define CLB_COLUMN_DISPATCH(s, LAUNCH)         \
+  do {                                         \
+    if (!(s).one) {                            \
+      if ((s).cx == 8) LAUNCH(8, false);       \
+      else LAUNCH(4, false);                   \
+    } else {                                   \
+      if ((s).cx == 64) LAUNCH(64, true);      \
+      else if ((s).cx == 32) LAUNCH(32, true); \
+      else if ((s).cx == 16) LAUNCH(16, true); \
+      else if ((s).cx == 8) LAUNCH(8, true);   \
+      else LAUNCH(4, true);                    \
+    }                                          \
   } while (0)
 
 }  // namespace
@@ -499,7 +544,9 @@ hipError_t periodic_step_lds(int block_x, size_t* bytes) {
       hipFuncSetAttribute((const void*)k_step_periodic<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)want) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_step_pressure_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)want) != hipSuccess) {
+                          (int)want) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_pbatch_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) !=
+          hipSuccess) {
     (void)hipGetLastError();
     return hipSuccess;
   }
@@ -536,22 +583,31 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
     b.ghost_lds = a.g.ny <= kGhostLdsMaxNy ? 1 : 0;
     const ColumnShape s = column_shape(a.g, 1, a.cus);
     const dim3 pgrid((unsigned)s.nblk);
-#define CLB_PRESSURE_LAUNCH(RYV, NTV) \
-  k_step_pressure<RYV, NTV><<<pgrid, dim3(NTV / RYV, RYV), ghost_lds_bytes(a.g), st>>>(b)
+#define CLB_PRESSURE_LAUNCH(CXV, ONEV) \
+  k_step_pressure<CXV, ONEV><<<pgrid, dim3(CXV, s.ry), ghost_lds_bytes(a.g), st>>>(b)
     CLB_COLUMN_DISPATCH(s, CLB_PRESSURE_LAUNCH);
 #undef CLB_PRESSURE_LAUNCH
   }
   return hipGetLastError();
 }
 
-hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st) {
+hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_reserve) {
+  if (a.col_rates && a.ghosts &&
+      (a.path == 2 || (a.path == 0 && (size_t)a.nch * a.g.nx * a.g.ny >= kPBatchRowNodes))) {
+    PBatchArgs b = a;
+    const int per = (a.g.nx + 255) / 256 + (2 * a.g.ny + 255) / 256;
+    k_pbatch_prep<<<(unsigned)((size_t)per * a.nch), 256, 0, st>>>(b);
+    b.nblk = (int)((a.g.padded_nodes() + 1023) / 1024);
+    k_pbatch_rows<<<(unsigned)((size_t)b.nblk * a.nch), 1024, lds_reserve, st>>>(b);
+    return hipGetLastError();
+  }
   const ColumnShape s = column_shape(a.g, a.nch, a.cus);
   PBatchArgs b = a;
   b.ghost_lds = a.g.ny <= kGhostLdsMaxNy ? 1 : 0;
   b.nblk = s.nblk;
   const dim3 grid((unsigned)((size_t)s.nblk * a.nch));
-#define CLB_PBATCH_LAUNCH(RYV, NTV) \
-  k_pbatch_step<RYV, NTV><<<grid, dim3(NTV / RYV, RYV), ghost_lds_bytes(a.g), st>>>(b)
+#define CLB_PBATCH_LAUNCH(CXV, ONEV) \
+  k_pbatch_step<CXV, ONEV><<<grid, dim3(CXV, s.ry), ghost_lds_bytes(a.g), st>>>(b)
   CLB_COLUMN_DISPATCH(s, CLB_PBATCH_LAUNCH);
 #undef CLB_PBATCH_LAUNCH
   return hipGetLastError();

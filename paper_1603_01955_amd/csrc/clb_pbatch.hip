@@ -93,6 +93,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct PBatchLayout {
   size_t buf;     // bytes of one channel buffer
   size_t col;     // bytes of one per-column array
+  size_t rates;   // bytes of the row kernel's per-column rates, all channels
+  size_t ghosts;  // bytes of the row kernel's ghost columns, all channels
   size_t total;
 };
 
@@ -100,10 +102,12 @@ PBatchLayout pbatch_layout(int32_t nch, const clb_params& p) {
   PBatchLayout L{};
   L.buf = align256(make_geo(p.nx, p.ny).size() * sizeof(double));
   L.col = align256((size_t)p.nx * sizeof(double));
+  L.rates = align256((size_t)nch * 2 * p.nx * sizeof(double));
+  L.ghosts = align256((size_t)nch * 18 * p.ny * sizeof(double));
   // two buffers per channel, channel table, run states, mass flows, three
-  // per-column diagnostics arrays
+  // per-column diagnostics arrays, row-kernel scratch
   L.total = 2 * (size_t)nch * L.buf + align256(nch * sizeof(PChan)) + align256(nch * sizeof(PChanState)) +
-            align256(nch * sizeof(double)) + 3 * L.col;
+            align256(nch * sizeof(double)) + 3 * L.col + L.rates + L.ghosts;
   return L;
 }
 
@@ -135,6 +139,7 @@ struct clb_pbatch {
   int64_t t;                               // steps taken by the channels still running
   hipStream_t stream;                      // caller's stream: all work runs here
   hipStream_t capture;                     // private stream, used only to record graphs
+  size_t step_lds;                         // LDS reserved per row-kernel workgroup (occupancy cap)
   hipGraph_t graph[2];                     // check_every steps + check, per starting parity
   hipGraphExec_t exec[2];
   int32_t g_every;
@@ -160,7 +165,7 @@ clb_status enqueue_chunk(clb_pbatch* b, hipStream_t st, int par, int64_t n, int 
   clb::PBatchArgs a = b->args;
   for (int64_t k = 0; k < n; ++k) {
     a.par = (int)((par + k) & 1);
-    PBATCH_HIP(clb::launch_pbatch_step(a, st));
+    PBATCH_HIP(clb::launch_pbatch_step(a, st, b->step_lds));
   }
   clb::k_pbatch_check<<<b->nch, clb::kMassThreads, 0, st>>>(b->args, b->d_state, (int)n, check, tol);
   PBATCH_HIP(hipGetLastError());
@@ -243,9 +248,11 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   if (bytes < need) return clb::perr(CLB_ENOMEM, "workspace: smaller than clb_pbatch_workspace_size");
   if ((st = clb::check_device_ptr(d_workspace, need, "d_workspace")) != CLB_OK) return st;
   const clb::Geo g = clb::make_geo(params[0].nx, params[0].ny);
-  // launch-shape limit: at least 4 columns per workgroup, below 2^31 workgroups
-  if ((size_t)nch * (size_t)((g.nx + 3) / 4) >= ((size_t)1 << 31))
-    return clb::perr(CLB_EINVAL, "nch*nx: too many workgroups for one launch");
+  // launch-shape limits: below 2^31 workgroups in the column kernel (at least
+  // 4 columns per workgroup) and in the row kernel (1024 nodes each)
+  if ((size_t)nch * (size_t)((g.nx + 3) / 4) >= ((size_t)1 << 31) ||
+      (size_t)nch * ((g.padded_nodes() + 1023) / 1024) >= ((size_t)1 << 31))
+    return clb::perr(CLB_EINVAL, "nch*nx*ny: too many workgroups for one launch");
 
   clb_pbatch* b = new (std::nothrow) clb_pbatch();
   if (!b) return clb::perr(CLB_ENOMEM, "host context allocation failed");
@@ -290,6 +297,10 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   b->d_m = reinterpret_cast<double*>(q);
   q += clb::align256(nch * sizeof(double));
   for (int k = 0; k < 3; ++k) b->col[k] = reinterpret_cast<double*>(q + k * L.col);
+  q += 3 * L.col;
+  a.col_rates = reinterpret_cast<double*>(q);
+  a.ghosts = reinterpret_cast<double*>(q + L.rates);
+  a.path = 0;
   b->h_state.assign(nch, clb::PChanState{0, 1, 0, 0.0});
   b->h_m.assign(nch, 0.0);
   b->t = 0;
@@ -304,6 +315,8 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   };
   hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
   if (e != hipSuccess) return fail_init(e, "hipStreamCreateWithFlags");
+  e = clb::periodic_step_lds(1024, &b->step_lds);
+  if (e != hipSuccess) return fail_init(e, "device attributes");
   e = hipMemcpyAsync(d_ch, b->chan.data(), nch * sizeof(clb::PChan), hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return fail_init(e, "upload channel table");
   for (int c = 0; c < nch && e == hipSuccess; ++c) {
@@ -384,6 +397,17 @@ clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every,
       if (h_steps) h_steps[c] = b->h_state[c].steps;
       if (h_converged) h_converged[c] = b->h_state[c].active ? 0 : 1;
     }
+  }
+  return CLB_OK;
+}
+
+clb_status clb_pbatch_set_path(clb_pbatch* b, int32_t path) {
+  if (!b) return clb::perr(CLB_EINVAL, "batch: NULL");
+  if (path < 0 || path > 2) return clb::perr(CLB_EINVAL, "path: must be 0, 1 or 2");
+  if (path != b->args.path) {
+    PBATCH_HIP(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    b->args.path = path;
   }
   return CLB_OK;
 }

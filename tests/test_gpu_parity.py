@@ -148,12 +148,16 @@ def test_launch_shapes_bitwise_identical():
     (dict(nx=2, ny=3, xbc="pressure", kn=0.05, p_ratio=1.4), 50, "linear"),
     (dict(nx=130, ny=5, xbc="pressure", kn=0.388, p_ratio=1.8, sigma=0.93), 40, "random"),
     (dict(nx=64, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, cbbsr_shift=0), 60, "linear"),
-    (dict(nx=149, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0), 60, "linear"),      # 64-row tiles, nx = 1 (mod 4)
+    (dict(nx=149, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0), 60, "linear"),      # 4 columns x 40 rows, nx = 1 (mod 4)
     (dict(nx=50, ny=70, xbc="pressure", kn=0.2, p_ratio=1.5, cbbsr_shift=0), 40, "random"),  # rows looped
     (dict(nx=1030, ny=20, xbc="pressure", kn=0.194, p_ratio=2.0), 30, "linear"),   # 129 workgroups, remap tail
-    (dict(nx=2500, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0), 6, "linear"),      # 512-thread workgroups
-    (dict(nx=8001, ny=12, xbc="pressure", kn=0.3, p_ratio=1.5), 6, "random"),      # 512 threads, 16 rows
-    (dict(nx=7401, ny=24, xbc="pressure", kn=0.2, p_ratio=1.8, cbbsr_shift=0), 4, "random"),  # 1024 threads
+    (dict(nx=2500, ny=40, xbc="pressure", kn=0.1, p_ratio=2.0), 6, "linear"),      # 16 columns x 40 rows
+    (dict(nx=8001, ny=12, xbc="pressure", kn=0.3, p_ratio=1.5), 6, "random"),      # 32 columns x 12 rows
+    (dict(nx=7401, ny=24, xbc="pressure", kn=0.2, p_ratio=1.8, cbbsr_shift=0), 4, "random"),  # 32 x 24 rows
+    (dict(nx=300, ny=1, xbc="pressure", kn=0.3, p_ratio=1.2), 30, "random"),       # one-row workgroups
+    (dict(nx=4100, ny=33, xbc="pressure", kn=0.15, p_ratio=2.0), 5, "random"),     # 16 x 33 rows, ragged tail
+    (dict(nx=3003, ny=63, xbc="pressure", kn=0.1, p_ratio=1.6), 4, "linear"),      # 16 x 63 rows
+    (dict(nx=1500, ny=130, xbc="pressure", kn=0.1, p_ratio=1.6), 3, "random"),     # 8 columns x 64 lanes, 3 passes
 ])
 def test_pressure_mode(kw, steps, start):
     prm = _oracle_params(kw)

@@ -61,17 +61,20 @@ def _ref(nx, ny, spec, shift=1):
     return prm, P0
 
 
-@pytest.mark.parametrize("nx,ny,nch,steps,shift", [
-    (149, 12, 4, 30, 1),    # 256-thread workgroups, 16 row lanes
-    (1030, 40, 5, 8, 1),    # 1024-thread workgroups, 64 row lanes
-    (500, 20, 8, 6, 1),     # 512-thread workgroups, 32 row lanes
-    (50, 70, 2, 10, 0),     # ny > 64: several rows per thread; literal Eq. (20) source
-    (2, 3, 3, 5, 1),        # one workgroup per channel holds both ghost columns
+@pytest.mark.parametrize("nx,ny,nch,steps,shift,path", [
+    (149, 12, 4, 30, 1, 1),    # column kernel: 256-thread workgroups, 16 row lanes
+    (1030, 40, 5, 8, 1, 1),    # 1024-thread workgroups, 64 row lanes
+    (500, 20, 8, 6, 1, 1),     # 512-thread workgroups, 32 row lanes
+    (50, 70, 2, 10, 0, 1),     # ny > 64: several rows per thread; literal Eq. (20) source
+    (2, 3, 3, 5, 1, 1),        # one workgroup per channel holds both ghost columns
+    (149, 12, 4, 30, 1, 2),    # row kernel (prep + row streaming)
+    (1030, 40, 3, 8, 0, 2),    # row kernel, two row segments per row
 ])
-def test_matches_reference(nx, ny, nch, steps, shift):
+def test_matches_reference(nx, ny, nch, steps, shift, path):
     PressureBatch, _, clb = _mods()
     specs = _specs(nch)
     pb = PressureBatch([_gpu_params(clb, nx, ny, s, shift) for s in specs])
+    pb.set_path(path)
     pb.step(steps)
     m, m_ns = pb.massflow()
     for c, spec in enumerate(specs):
@@ -90,6 +93,23 @@ def test_matches_reference(nx, ny, nch, steps, shift):
         want_ns = A.noslip_massflow(nx, ny, prm.kn, prm.p_ratio, rho_out=prm.rho_out)
         assert abs(m_ns[c] / want_ns - 1.0) <= 1e-14, c
     pb.close()
+
+
+@pytest.mark.parametrize("nx,ny,nch", [(149, 12, 4), (1030, 40, 5), (50, 70, 2), (2, 3, 3), (2000, 20, 3)])
+def test_row_and_column_kernels_agree_bitwise(nx, ny, nch):
+    PressureBatch, _, clb = _mods()
+    params = [_gpu_params(clb, nx, ny, s) for s in _specs(nch)]
+    out = []
+    for path in (1, 2):
+        pb = PressureBatch(params)
+        pb.set_path(path)
+        pb.step(7)
+        steps, _ = pb.run(6, check_every=3, tol=0.0)
+        assert steps.tolist() == [13] * nch
+        out.append([pb.populations(c) for c in range(nch)])
+        pb.close()
+    for c in range(nch):
+        assert torch.equal(out[0][c], out[1][c]), c
 
 
 def test_run_stops_each_channel_where_its_mass_flow_settles():
