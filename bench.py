@@ -30,11 +30,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched Kn-sweep comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
-    ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "adjoint"), default="all",
-                    help="run one part alone (step: the periodic step only; sweep / pressure / adjoint: "
+    ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "msweep", "adjoint"), default="all",
+                    help="run one part alone (step: the periodic step only; sweep / pressure / msweep / adjoint: "
                          "that measurement only, printed as its own JSON line) -- for profiling runs")
     ap.add_argument("--no-loop-baseline", action="store_true",
-                    help="sweep: skip the loop-of-solvers baselines (profiling the batched kernel)")
+                    help="sweep / msweep: skip the loop-of-solvers baselines (profiling the batched kernel)")
+    ap.add_argument("--no-msweep", action="store_true", help="skip the pressure-driven mass-flow sweep")
+    ap.add_argument("--msweep-max-steps", type=int, default=3000000,
+                    help="msweep: step cap per channel (lower it for traced runs)")
     ap.add_argument("--block-x", type=int, default=1024)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -210,6 +213,84 @@ def pressure_step(nx=4000, ny=40, steps=20000):
             "mlups": round(nx * ny / us, 1), "algorithmic_gbs": round(BYTES_PER_NODE * nx * ny / us / 1e3, 1)}
 
 
+def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2000, baselines=True):
+    """Mass-flow study of Section 3.2: 16 long channels (2000 x 20, L/H = 100,
+    p_in/p_out = 1.8, sigma = 0.93, Kn_out log-spaced 0.01-1, linear-density
+    start) advanced together by the pressure batch, each to steady state
+    (column-mean mass flow settled to tol over check_every steps).  Reports
+    S = m / m_ns per channel, the batched step time against a loop of
+    single-channel solvers, and the run to steady state against the same loop
+    with the same checks."""
+    import numpy as np
+    import torch
+    from clb_inputs import WORKLOADS, mass_flow_sweep_kn
+    from paper_1603_01955_amd import PressureBatch, Solver, clb
+
+    w = WORKLOADS["mass_flow_sweep_16x2000x20"]
+    kns = mass_flow_sweep_kn(w["channels"], w["kn_lo"], w["kn_hi"])
+    params = [clb.make_params(w["nx"], w["ny"], xbc="pressure", kn=k, p_ratio=w["p_ratio"], sigma=w["sigma"])
+              for k in kns]
+    nodes = w["channels"] * w["nx"] * w["ny"]
+
+    def per_step_us(obj):
+        obj.step(200)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(obj.stream)
+        obj.step(step_probe)
+        e1.record(obj.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / step_probe
+
+    pb = PressureBatch(params)
+    us_batch = per_step_us(pb)
+    pb.close()
+    pb = PressureBatch(params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_b, conv = pb.run(max_steps, check_every, tol)        # synchronises
+    t_batch = time.perf_counter() - t0
+    m, m_ns = pb.massflow()
+    pb.close()
+    out = {"workload": "mass_flow_sweep_16x2000x20", "channels": len(params), "p_ratio": w["p_ratio"],
+           "sigma": w["sigma"], "kn_out": [round(k, 5) for k in kns],
+           "S": [round(float(v), 6) for v in m / m_ns], "all_converged": bool(conv.all()),
+           "steps": [int(v) for v in steps_b], "check_every": check_every, "tol": tol,
+           "batched_to_steady_s": round(t_batch, 3),
+           "batched_step_us": round(us_batch, 3), "batched_mlups": round(nodes / us_batch, 1),
+           "batched_algorithmic_gbs": round(BYTES_PER_NODE * nodes / us_batch / 1e3, 1)}
+    if not baselines:
+        return out
+    s = Solver(params=params[0])
+    s.set_graph_steps(step_probe // 10)
+    us_single = per_step_us(s)
+    s.close()
+    out["loop_step_us"] = round(us_single * len(params), 3)
+    out["step_speedup_vs_graph_loop"] = round(us_single * len(params) / us_batch, 2)
+    torch.cuda.synchronize()
+    steps_l = []
+    t0 = time.perf_counter()
+    for p in params:
+        s = Solver(params=p)
+        s.set_graph_steps(check_every)
+        prev, n = float("nan"), 0
+        while n < max_steps:
+            s.step(check_every)
+            n += check_every
+            cur = s.massflow()[1]                              # synchronises
+            if abs(cur - prev) <= tol * abs(cur):
+                break
+            prev = cur
+        steps_l.append(n)
+        s.close()
+    t_loop = time.perf_counter() - t0
+    out["graph_loop_to_steady_s"] = round(t_loop, 3)
+    out["loop_steps_match"] = bool((np.array(steps_l) == steps_b).all())
+    out["speedup_vs_graph_loop"] = round(t_loop / t_batch, 2)
+    return out
+
+
 def cpu_baseline():
     """The CPU reference, as it stands, on a bounded sample of the workload:
     CPU_SAMPLE_STEPS steps of a 32768 x CPU_SAMPLE_ROWS slab of the same
@@ -245,6 +326,10 @@ def main():
         return
     if args.part == "pressure":
         print(json.dumps({"pressure_step": pressure_step()}), flush=True)
+        return
+    if args.part == "msweep":
+        print(json.dumps({"mass_flow_sweep": mass_flow_sweep(max_steps=args.msweep_max_steps,
+                                                             baselines=not args.no_loop_baseline)}), flush=True)
         return
     if args.part == "adjoint":
         print(json.dumps({"adjoint": adjoint_calibration()}), flush=True)
@@ -302,6 +387,9 @@ def main():
     if not args.no_sweep:
         rec["kn_sweep"] = kn_sweep(baselines=not args.no_loop_baseline)
     rec["pressure_step"] = pressure_step()
+    if not args.no_msweep:
+        rec["mass_flow_sweep"] = mass_flow_sweep(max_steps=args.msweep_max_steps,
+                                                 baselines=not args.no_loop_baseline)
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_calibration()
     if not args.no_cpu_baseline:

@@ -84,7 +84,8 @@ struct PBatchArgs {
   double* buf[2];       // buffer k of channel c at buf[k] + c * stride
   size_t stride;        // doubles per channel buffer (Geo::size, padded)
   Geo g;
-  int nch;
+  int nch;              // step launches: channels in `live`; otherwise all channels
+  const int32_t* live;  // [nch] indices of the channels a step launch covers
   int shift;            // Eq. (20) specular source from x -/+ 1
   int xcd_remap;
   int par;              // step: read buf[par], write buf[par ^ 1]

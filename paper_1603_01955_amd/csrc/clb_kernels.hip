@@ -177,9 +177,10 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_step_pressure(S
 // ---------------------------------------------------------------------------
 // K2c: one step of a batch of pressure-driven channels of the same grid
 // (the mass-flow sweep of Section 3.2), in one launch: workgroup b serves
-// column block b % nblk of channel b / nblk with that channel's parameters,
-// the same arithmetic as K2 (bitwise the same populations).  Channels that
-// have stopped (converged) are skipped.
+// column block b % nblk of channel live[b / nblk] with that channel's
+// parameters, the same arithmetic as K2 (bitwise the same populations).
+// The launch covers the channels still running (the host keeps the list);
+// a channel found stopped is skipped.
 // ---------------------------------------------------------------------------
 // Step arguments of channel c of a batch.
 __device__ __forceinline__ StepArgs channel_args(const PBatchArgs& p, int c) {
@@ -213,9 +214,10 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_pbatch_step(PBa
   extern __shared__ double s_ghost[];
   __shared__ double s_rc[2][CX];
   const int b = logical_block(p.xcd_remap);
-  const int c = b / p.nblk;
+  const int k = b / p.nblk;
+  const int c = p.live[k];
   if (!p.state[c].active) return;
-  pressure_block<CX, ONE>(channel_args(p, c), b - c * p.nblk, p.nblk, s_rc, s_ghost);
+  pressure_block<CX, ONE>(channel_args(p, c), b - k * p.nblk, p.nblk, s_rc, s_ghost);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,16 +296,18 @@ __global__ __launch_bounds__(1024) void k_step_pressure_rows(StepArgs a) {
 __global__ __launch_bounds__(256) void k_pbatch_prep(PBatchArgs p) {
   const int ncb = (p.g.nx + 255) / 256;
   const int per = ncb + (2 * p.g.ny + 255) / 256;
-  const int c = blockIdx.x / per;
+  const int k = blockIdx.x / per;
+  const int c = p.live[k];
   if (!p.state[c].active) return;
-  pressure_prep_block(channel_args(p, c), (int)blockIdx.x - c * per, ncb);
+  pressure_prep_block(channel_args(p, c), (int)blockIdx.x - k * per, ncb);
 }
 
 __global__ __launch_bounds__(1024) void k_pbatch_rows(PBatchArgs p) {
   const int b = logical_block(p.xcd_remap);
-  const int c = b / p.nblk;
+  const int k = b / p.nblk;
+  const int c = p.live[k];
   if (!p.state[c].active) return;
-  pressure_rows_node(channel_args(p, c), (size_t)(b - c * p.nblk) * blockDim.x + threadIdx.x);
+  pressure_rows_node(channel_args(p, c), (size_t)(b - k * p.nblk) * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

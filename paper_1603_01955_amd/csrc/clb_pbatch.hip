@@ -105,9 +105,9 @@ PBatchLayout pbatch_layout(int32_t nch, const clb_params& p) {
   L.rates = align256((size_t)nch * 2 * p.nx * sizeof(double));
   L.ghosts = align256((size_t)nch * 18 * p.ny * sizeof(double));
   // two buffers per channel, channel table, run states, mass flows, three
-  // per-column diagnostics arrays, row-kernel scratch
+  // per-column diagnostics arrays, row-kernel scratch, running-channel list
   L.total = 2 * (size_t)nch * L.buf + align256(nch * sizeof(PChan)) + align256(nch * sizeof(PChanState)) +
-            align256(nch * sizeof(double)) + 3 * L.col + L.rates + L.ghosts;
+            align256(nch * sizeof(double)) + 3 * L.col + L.rates + L.ghosts + align256(nch * sizeof(int32_t));
   return L;
 }
 
@@ -136,6 +136,9 @@ struct clb_pbatch {
   double* col[3];                          // per-column diagnostics scratch
   std::vector<clb::PChanState> h_state;    // mirror of d_state, current after every call
   std::vector<double> h_m;
+  int32_t* d_live;                         // indices of the running channels (step launches)
+  std::vector<int32_t> h_live;             // host copy, read by the last upload
+  int32_t n_live;
   int64_t t;                               // steps taken by the channels still running
   hipStream_t stream;                      // caller's stream: all work runs here
   hipStream_t capture;                     // private stream, used only to record graphs
@@ -144,6 +147,7 @@ struct clb_pbatch {
   hipGraphExec_t exec[2];
   int32_t g_every;
   double g_tol;
+  int32_t g_live;                          // running channels the graphs were recorded for
 };
 
 namespace {
@@ -163,7 +167,8 @@ void drop_graphs(clb_pbatch* b) {
 // (and with check the convergence test) on stream st.
 clb_status enqueue_chunk(clb_pbatch* b, hipStream_t st, int par, int64_t n, int check, double tol) {
   clb::PBatchArgs a = b->args;
-  for (int64_t k = 0; k < n; ++k) {
+  a.nch = b->n_live;
+  for (int64_t k = 0; k < n && b->n_live > 0; ++k) {
     a.par = (int)((par + k) & 1);
     PBATCH_HIP(clb::launch_pbatch_step(a, st, b->step_lds));
   }
@@ -187,10 +192,24 @@ clb_status record_chunk(clb_pbatch* b, int par, int32_t every, double tol) {
   return CLB_OK;
 }
 
+// Refresh the host mirror of the run states and, when channels have stopped,
+// the list of running channels that step launches cover (upload finished
+// before returning, so the host copy may change afterwards).
 clb_status read_state(clb_pbatch* b) {
   PBATCH_HIP(hipMemcpyAsync(b->h_state.data(), b->d_state, b->nch * sizeof(clb::PChanState),
                             hipMemcpyDeviceToHost, b->stream));
   PBATCH_HIP(hipStreamSynchronize(b->stream));
+  int32_t n = 0;
+  for (int c = 0; c < b->nch; ++c)
+    if (b->h_state[c].active) b->h_live[n++] = c;
+  if (n != b->n_live) {
+    b->n_live = n;
+    if (n > 0) {
+      PBATCH_HIP(hipMemcpyAsync(b->d_live, b->h_live.data(), n * sizeof(int32_t), hipMemcpyHostToDevice,
+                                b->stream));
+      PBATCH_HIP(hipStreamSynchronize(b->stream));
+    }
+  }
   return CLB_OK;
 }
 
@@ -300,7 +319,13 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   q += 3 * L.col;
   a.col_rates = reinterpret_cast<double*>(q);
   a.ghosts = reinterpret_cast<double*>(q + L.rates);
+  q += L.rates + L.ghosts;
   a.path = 0;
+  b->d_live = reinterpret_cast<int32_t*>(q);
+  a.live = b->d_live;
+  b->h_live.resize(nch);
+  for (int c = 0; c < nch; ++c) b->h_live[c] = c;
+  b->n_live = nch;
   b->h_state.assign(nch, clb::PChanState{0, 1, 0, 0.0});
   b->h_m.assign(nch, 0.0);
   b->t = 0;
@@ -319,6 +344,8 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   if (e != hipSuccess) return fail_init(e, "device attributes");
   e = hipMemcpyAsync(d_ch, b->chan.data(), nch * sizeof(clb::PChan), hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return fail_init(e, "upload channel table");
+  e = hipMemcpyAsync(b->d_live, b->h_live.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return fail_init(e, "upload channel list");
   for (int c = 0; c < nch && e == hipSuccess; ++c) {
     const clb_params& p = params[c];
     clb::InitArgs ia{};
@@ -338,7 +365,7 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   clb::k_pbatch_reset<<<(nch + 255) / 256, 256, 0, b->stream>>>(b->d_state, nch);
   e = hipGetLastError();
   if (e != hipSuccess) return fail_init(e, "state reset kernel");
-  // The upload reads b->chan; finish it before returning.
+  // The uploads read b->chan and b->h_live; finish them before returning.
   e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return fail_init(e, "hipStreamSynchronize");
   *out = b;
@@ -374,10 +401,11 @@ clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every,
       b->g_tol = tol;
     }
     int64_t left = max_steps;
-    while (left > 0) {
-      int any = 0;
-      for (const auto& s : b->h_state) any |= s.active;
-      if (!any) break;
+    while (left > 0 && b->n_live > 0) {
+      if (b->g_live != b->n_live) {   // the graphs cover a fixed set of running channels
+        drop_graphs(b);
+        b->g_live = b->n_live;
+      }
       const int par = (int)(b->t & 1);
       const int64_t n = left < check_every ? left : check_every;
       if (n == check_every) {
