@@ -84,7 +84,11 @@ typedef struct clb_params {
   double tq_den;         /* denominator of Eq. 21 (16 as printed; 24 = exact-slip variant)     */
   int32_t cbbsr_shift;   /* Eq. 20 specular source: 1 = neighbour x-1 / x+1 (default),
                             0 = the same node                                                   */
-  int32_t reserved;      /* must be 0                                                          */
+  int32_t forcing;       /* body-force source: 0 = Eq. 9 as printed (default); 1 = Eq. 9 plus the
+                            third-order moments (1 - s_q/2) rho F / 3 of a second-order (Guo-type)
+                            force term in k_xxy (F_y) and k_xyy (F_x), with which Eq. 21's
+                            denominator 16 gives the slip law of Eq. 19 exactly.  No effect
+                            without a force (pressure mode).                                    */
 } clb_params;
 
 /* Derived constants (host-only).  In pressure mode s_nu, s_q and tau_tilde

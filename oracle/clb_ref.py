@@ -64,6 +64,7 @@ class Params:
     uy0: float = 0.0
     tq_den: float = 16.0           # Eq. (21) denominator (16 as printed)
     cbbsr_shift: int = 1
+    forcing: int = 0               # 0: source of Eq. (9); 1: plus third-order moments (see collide)
 
 
 # ---------------------------------------------------------------------------
@@ -255,7 +256,12 @@ def _apply(mats, vecs):
     return np.matmul(mats, vecs.T[:, :, None])[:, :, 0].T
 
 
-def collide(pre, gx, gy, s3, s_nu, s_q, s8):
+def collide(pre, gx, gy, s3, s_nu, s_q, s8, forcing=0):
+    """forcing=1 adds (1 - s_q/2) rho F/3 to the post-collision raw moments
+    k_xxy (F_y) and k_xyy (F_x): the third-order moments of the second-order
+    (Guo-type) discrete force term with its usual (1 - s/2) factor, which the
+    source of Eq. (9) leaves out.  With them the printed Eq. (21) is the exact
+    match to the slip law of Eq. (19) in a force-driven channel."""
     shape = pre.shape
     f = pre.reshape(9, -1)
     M = T @ f
@@ -282,6 +288,10 @@ def collide(pre, gx, gy, s3, s_nu, s_q, s8):
     for k in range(3, 9):
         post[k] = kap[k] - rates[k] * (kap[k] - kap_eq[k])
     M_post = _apply(central_shift(-ux, -uy), post)
+    if forcing:
+        third = (1.0 - 0.5 * rates[6]) * rho / 3.0
+        M_post[6] = M_post[6] + third * gy
+        M_post[7] = M_post[7] + third * gx
     return (T_INV @ M_post).reshape(shape)
 
 
@@ -380,7 +390,7 @@ def step(P, prm):
     _, r = resolved(prm)
     pre = stream_bc(P, prm, r)
     s_nu, s_q = step_rates(pre, prm)
-    return collide(pre, prm.gx, prm.gy, prm.s3, s_nu, s_q, prm.s8)
+    return collide(pre, prm.gx, prm.gy, prm.s3, s_nu, s_q, prm.s8, prm.forcing)
 
 
 def run(P, prm, nsteps, callback=None):
@@ -397,7 +407,7 @@ def step_nodes(P, prm, ys, xs):
     _, r = resolved(prm)
     pre = gather_nodes(P, prm, ys, xs, r)
     s_nu, s_q = step_rates(pre, prm)
-    return collide(pre, prm.gx, prm.gy, prm.s3, s_nu, s_q, prm.s8)
+    return collide(pre, prm.gx, prm.gy, prm.s3, s_nu, s_q, prm.s8, prm.forcing)
 
 
 # ---------------------------------------------------------------------------

@@ -39,7 +39,7 @@ class clb_params(ctypes.Structure):
         ("rho0", ctypes.c_double), ("ux0", ctypes.c_double), ("uy0", ctypes.c_double),
         ("init_amp", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("tq_den", ctypes.c_double),
-        ("cbbsr_shift", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("cbbsr_shift", ctypes.c_int32), ("forcing", ctypes.c_int32),
     ]
 
 
@@ -96,7 +96,7 @@ def check(status):
 
 def make_params(nx, ny, xbc="periodic", kn=0.1, a=2.0, sigma=1.0, A1=None, A2=0.55, r=None,
                 s3=1.1, s8=1.2, gx=0.0, gy=0.0, p_ratio=2.0, rho_out=1.0, rho0=1.0, ux0=0.0,
-                uy0=0.0, init=None, init_amp=0.0, seed=0, tq_den=16.0, cbbsr_shift=1):
+                uy0=0.0, init=None, init_amp=0.0, seed=0, tq_den=16.0, cbbsr_shift=1, forcing=0):
     p = clb_params()
     lib().clb_params_default(ctypes.byref(p))
     p.nx, p.ny = int(nx), int(ny)
@@ -117,6 +117,7 @@ def make_params(nx, ny, xbc="periodic", kn=0.1, a=2.0, sigma=1.0, A1=None, A2=0.
     p.init_amp, p.seed = float(init_amp), int(seed)
     p.tq_den = float(tq_den)
     p.cbbsr_shift = int(cbbsr_shift)
+    p.forcing = int(forcing)
     return p
 
 

@@ -96,7 +96,7 @@ clb_status validate(const clb_params* p, clb_derived* d) {
   if (!(finite(p->init_amp) && p->init_amp >= 0)) return fail(CLB_EINVAL, "init_amp: must be finite and >= 0");
   if (!(finite(p->tq_den) && p->tq_den > 0)) return fail(CLB_EINVAL, "tq_den: must be finite and > 0");
   if (p->cbbsr_shift != 0 && p->cbbsr_shift != 1) return fail(CLB_EINVAL, "cbbsr_shift: must be 0 or 1");
-  if (p->reserved != 0) return fail(CLB_EINVAL, "reserved: must be 0");
+  if (p->forcing != 0 && p->forcing != 1) return fail(CLB_EINVAL, "forcing: must be 0 or 1");
   // Launch-shape limit of the periodic kernel (64-thread blocks at worst).
   if (clb::make_geo(p->nx, p->ny).padded_nodes() / 64 >= ((size_t)1 << 31))
     return fail(CLB_EINVAL, "nx*ny: grid too large for one launch");
@@ -183,6 +183,7 @@ clb::StepArgs step_args(const clb_ctx* c) {
   a.r = c->d.r;
   a.gx = c->p.gx;
   a.gy = c->p.gy;
+  a.forcing = c->p.forcing;
   a.s3 = c->p.s3;
   a.snu = c->d.s_nu;
   a.sq = c->d.s_q;

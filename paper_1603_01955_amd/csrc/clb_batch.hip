@@ -27,7 +27,8 @@ namespace clb {
 namespace {
 
 struct ChanDesc {
-  int32_t nx, ny, shift, force;
+  int32_t nx, ny, shift;
+  int32_t force;        // 0: no body force; 1: source of Eq. (9); 2: plus its third-order moments
   int64_t off;          // offset (doubles) of the channel's [9][ny][nx] populations
   double r, gx, gy, s3, snu, sq, s8;
 };
@@ -70,7 +71,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-template <bool FORCE>
+template <bool FORCE, bool THIRD>
 __device__ void channel_step(const ChanDesc& d, const double* A, double* B, int n) {
   const Gather<0, LdsView> gat{{A, d.nx, d.ny, n}, d.r, 1.0 - d.r, d.shift, 0.0, 0.0};
   const Rates s{d.s3, d.snu, d.sq, d.s8};
@@ -78,7 +79,7 @@ __device__ void channel_step(const ChanDesc& d, const double* A, double* B, int 
     const int y = j / d.nx, x = j - y * d.nx;
     double f[9];
     gat(x, y, f);
-    collide<FORCE>(f, d.gx, d.gy, s);
+    collide<FORCE, THIRD>(f, d.gx, d.gy, s);
 #pragma unroll
     for (int i = 0; i < 9; ++i) B[i * n + j] = f[i];
   }
@@ -120,7 +121,7 @@ __device__ __forceinline__ NodeSources node_sources(const ChanDesc& d, int j) {
   return q;
 }
 
-template <bool FORCE>
+template <bool FORCE, bool THIRD>
 __device__ __forceinline__ void node_step(const ChanDesc& d, const NodeSources& q, const double* A, double* B,
                                           int n, int j) {
 #pragma clang fp contract(off)
@@ -138,7 +139,7 @@ __device__ __forceinline__ void node_step(const ChanDesc& d, const NodeSources& 
     f[7] = r * f[7] + omr * s[2];
     f[8] = r * f[8] + omr * s[3];
   }
-  collide<FORCE>(f, d.gx, d.gy, Rates{d.s3, d.snu, d.sq, d.s8});
+  collide<FORCE, THIRD>(f, d.gx, d.gy, Rates{d.s3, d.snu, d.sq, d.s8});
 #pragma unroll
   for (int i = 0; i < 9; ++i) B[i * n + j] = f[i];
 }
@@ -182,15 +183,19 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
   while (!st.converged && taken < a.max_steps) {
     if (one) {
       if (mine) {
-        if (d.force)
-          node_step<true>(d, q, A, B, n, threadIdx.x);
+        if (d.force == 2)
+          node_step<true, true>(d, q, A, B, n, threadIdx.x);
+        else if (d.force)
+          node_step<true, false>(d, q, A, B, n, threadIdx.x);
         else
-          node_step<false>(d, q, A, B, n, threadIdx.x);
+          node_step<false, false>(d, q, A, B, n, threadIdx.x);
       }
+    } else if (d.force == 2) {
+      channel_step<true, true>(d, A, B, n);
     } else if (d.force) {
-      channel_step<true>(d, A, B, n);
+      channel_step<true, false>(d, A, B, n);
     } else {
-      channel_step<false>(d, A, B, n);
+      channel_step<false, false>(d, A, B, n);
     }
     __syncthreads();
     double* t = A;
@@ -396,7 +401,7 @@ clb_status clb_batch_init(int32_t nch, const clb_params* params, void* d_workspa
     cd.nx = p.nx;
     cd.ny = p.ny;
     cd.shift = p.cbbsr_shift;
-    cd.force = (p.gx != 0.0 || p.gy != 0.0) ? 1 : 0;
+    cd.force = (p.gx != 0.0 || p.gy != 0.0) ? (p.forcing ? 2 : 1) : 0;
     cd.off = off;
     cd.r = d.r;
     cd.gx = p.gx;

@@ -23,8 +23,12 @@ struct Rates {
 //   collision kernels g3..g8 in ascending order (Eq. 7, g0 = g1 = g2 = 0),
 //   forcing S = T^-1 S_hat (Eqs. 9, 10) with T^-1 in closed form, and the
 //   update f + K g + S written out per direction (Eqs. 4, 6).
+// THIRD adds (1 - s_q/2) rho F/3 to the source's raw moments k_xxy (F_y) and
+// k_xyy (F_x): the third-order moments of a second-order (Guo-type) force
+// term, which Eq. (9) leaves out; with them Eq. (21)'s printed denominator
+// reproduces the slip law of Eq. (19) in a force-driven channel.
 // ---------------------------------------------------------------------------
-template <bool FORCE>
+template <bool FORCE, bool THIRD = false>
 __device__ __forceinline__ void collide(double f[9], double gx, double gy, const Rates& s) {
   // Products and sums round on their own except where written as fma(): the
   // same FP64 result in every kernel that inlines this, whatever the
@@ -100,8 +104,13 @@ __device__ __forceinline__ void collide(double f[9], double gx, double gy, const
     // Eq. (9) source moments in the basis of Eq. (10) ...
     const double Sx = rho * gx, Sy = rho * gy;
     const double Sxy = rho * fma(ux, gy, uy * gx);
-    const double Sxxy = fma(Sy, ux2, 2.0 * Sx * uxy);
-    const double Sxyy = fma(Sx, uy2, 2.0 * Sy * uxy);
+    double Sxxy = fma(Sy, ux2, 2.0 * Sx * uxy);
+    double Sxyy = fma(Sx, uy2, 2.0 * Sy * uxy);
+    if (THIRD) {
+      const double c = (1.0 - 0.5 * s.sq) * (1.0 / 3.0);
+      Sxxy = fma(c, Sy, Sxxy);
+      Sxyy = fma(c, Sx, Sxyy);
+    }
     const double Sxxyy = 2.0 * fma(Sx * ux, uy2, Sy * uy * ux2);
     const double Sxx = 2.0 * Sx * ux;   // (S3 + S4)/2
     const double Syy = 2.0 * Sy * uy;   // (S3 - S4)/2

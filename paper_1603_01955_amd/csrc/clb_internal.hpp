@@ -43,6 +43,7 @@ struct StepArgs {
   int ghost_lds;        // pressure mode: ghost columns staged in LDS (set by the launcher)
   double r;             // bounce-back fraction, Eq. (20)
   double gx, gy;        // body acceleration (periodic)
+  int forcing;          // 1: source with the third-order force moments (see collide)
   double s3, snu, sq, s8;
   // pressure mode: per-column rates from the local Knudsen number
   double kn;            // Kn_out

@@ -37,7 +37,7 @@ __device__ __forceinline__ void store9(double* __restrict__ Q, const Geo& g, int
 // K1: fused periodic step.  One thread per node; threads enumerate the
 // padded nodes in device-layout order (y, segment, lane).
 // ---------------------------------------------------------------------------
-template <bool FORCE>
+template <bool FORCE, bool THIRD>
 __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
   const size_t t = (size_t)logical_block(a.xcd_remap) * blockDim.x + threadIdx.x;
   const int lane = (int)(t & (((size_t)1 << a.g.lshift) - 1));
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
   double f[9];
   gat(x, y, f);
   const Rates s{a.s3, a.snu, a.sq, a.s8};
-  collide<FORCE>(f, a.gx, a.gy, s);
+  collide<FORCE, THIRD>(f, a.gx, a.gy, s);
   store9(a.dst, a.g, x, y, f);
 }
 
@@ -543,9 +543,11 @@ hipError_t periodic_step_lds(int block_x, size_t* bytes) {
   const int per_cu = kStepThreadsPerCU / block_x > 1 ? kStepThreadsPerCU / block_x : 1;
   const size_t want = (size_t)lds_cu / (size_t)(per_cu + 1) + 256;   // per_cu + 1 workgroups no longer fit
   if (want * (size_t)per_cu > (size_t)lds_cu) return hipSuccess;
-  if (hipFuncSetAttribute((const void*)k_step_periodic<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  if (hipFuncSetAttribute((const void*)k_step_periodic<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)want) != hipSuccess ||
-      hipFuncSetAttribute((const void*)k_step_periodic<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      hipFuncSetAttribute((const void*)k_step_periodic<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)want) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_step_periodic<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)want) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_step_pressure_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)want) != hipSuccess ||
@@ -572,10 +574,12 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
   if (a.mode == 0) {
     const size_t threads = a.g.padded_nodes();
     const dim3 grid((unsigned)((threads + block_x - 1) / block_x));
-    if (a.gx != 0.0 || a.gy != 0.0)
-      k_step_periodic<true><<<grid, block_x, lds_reserve, st>>>(a);
+    if ((a.gx != 0.0 || a.gy != 0.0) && a.forcing)
+      k_step_periodic<true, true><<<grid, block_x, lds_reserve, st>>>(a);
+    else if (a.gx != 0.0 || a.gy != 0.0)
+      k_step_periodic<true, false><<<grid, block_x, lds_reserve, st>>>(a);
     else
-      k_step_periodic<false><<<grid, block_x, lds_reserve, st>>>(a);
+      k_step_periodic<false, false><<<grid, block_x, lds_reserve, st>>>(a);
   } else if (a.col_rates && a.ghosts &&
              (a.pressure_path == 2 || (a.pressure_path == 0 && (size_t)a.g.nx * a.g.ny >= kPressureRowNodes))) {
     k_pressure_prep<<<(a.g.nx + 255) / 256 + (2 * a.g.ny + 255) / 256, 256, 0, st>>>(a);

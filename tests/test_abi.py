@@ -79,7 +79,7 @@ def test_workspace_size_arithmetic(lib):
     ("nx", 0), ("ny", -1), ("xbc", 7), ("init", 9), ("kn", 0.0), ("kn", -1.0), ("kn", math.inf),
     ("a", -0.1), ("sigma", 0.0), ("sigma", 2.5), ("A2", -1.0), ("r", 1.5), ("s3", 2.0),
     ("s8", 0.0), ("gx", math.nan), ("p_ratio", 0.0), ("rho_out", -1.0), ("rho0", 0.0),
-    ("init_amp", -1e-3), ("tq_den", 0.0), ("cbbsr_shift", 2), ("reserved", 1)])
+    ("init_amp", -1e-3), ("tq_den", 0.0), ("cbbsr_shift", 2), ("forcing", 2)])
 def test_invalid_parameters_rejected(lib, field, value):
     p = clb.make_params(8, 8)
     setattr(p, field, value)

@@ -29,11 +29,13 @@ def _mods():
 
 CHANNELS = [
     dict(nx=4, ny=16, kn=0.3, gx=1e-6),
+    dict(nx=6, ny=24, kn=0.05, gx=1e-6, forcing=1),     # third-order force moments; 144 nodes > 64 threads
     dict(nx=4, ny=128, kn=0.01, gx=1e-6),
     dict(nx=7, ny=9, kn=2.0, gx=1e-4, gy=3e-5, cbbsr_shift=0),
     dict(nx=1, ny=1, kn=0.5, gx=1e-5),
     dict(nx=32, ny=32, kn=10.0, gx=1e-6, sigma=0.8, tq_den=24.0),
     dict(nx=3, ny=5, kn=0.1, init="perturbed", init_amp=1e-3, seed=9),
+    dict(nx=5, ny=12, kn=0.7, gx=2e-5, gy=1e-5, forcing=1),          # third-order force moments
 ]
 
 
@@ -112,6 +114,23 @@ def test_kn_sweep_matches_closed_form_and_knudsen_minimum():
     ref_curve = np.array([A.discrete_Q(128, k, 2.0, 0.55, r) for k in grid])
     kmin = grid[int(np.argmin(ref_curve))]
     assert 0.6 < kmin < 1.3
+
+
+def test_kn_sweep_with_third_order_forcing_matches_continuum_slip():
+    """The same sweep shape with the source's third-order moments: every
+    channel's steady Q is the continuum second-order slip solution of
+    Eq. (19) (discrete excess of Eq. (9)'s source removed)."""
+    Batch, _, clb = _mods()
+    heights, kns = kn_sweep_channels(16, seed=11, heights=(16, 32, 64))
+    params = [clb.make_params(4, ny, kn=kn, gx=1e-6, forcing=1) for ny, kn in zip(heights, kns)]
+    b = Batch(params)
+    steps, conv = b.run(400000, check_every=1000, tol=1e-12)
+    assert conv.all(), steps[~conv]
+    Q = b.flow_rate()
+    A1 = C.slip_A1(1.0)
+    Qref = np.array([A.continuum_sum_u(ny, kn, 2.0, A1, 0.55, 1e-6) * np.sqrt(6.0) / (3.0 * 1e-6 * ny * ny)
+                     for ny, kn in zip(heights, kns)])
+    assert np.max(np.abs(Q / Qref - 1)) <= 1e-6
 
 
 def test_batch_rejects_bad_channels():

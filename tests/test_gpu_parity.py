@@ -49,8 +49,30 @@ def _gpu_run(kw, steps, P0=None, launch=None):
 
 def _oracle_params(kw):
     keys = ("nx", "ny", "xbc", "kn", "a", "sigma", "A1", "A2", "r", "s3", "s8", "gx", "gy",
-            "p_ratio", "rho_out", "rho0", "ux0", "uy0", "tq_den", "cbbsr_shift")
+            "p_ratio", "rho_out", "rho0", "ux0", "uy0", "tq_den", "cbbsr_shift", "forcing")
     return C.Params(**{k: v for k, v in kw.items() if k in keys})
+
+
+@pytest.mark.parametrize("ny,kn", [(32, 0.1), (16, 1.0)])
+def test_third_order_forcing_gives_continuum_slip(ny, kn):
+    """Force-driven channel with the source's third-order moments and the
+    printed Eq. (21): the steady flow rate is the continuum second-order slip
+    solution of Eq. (19) (the excess of Eq. (9)'s source is gone)."""
+    from paper_1603_01955_amd import Solver
+    s = Solver(nx=4, ny=ny, kn=kn, gx=1e-6, forcing=1)
+    s.set_graph_steps(1000)
+    prev = None
+    for _ in range(200):
+        s.step(1000)
+        q = s.flow_rate()
+        if prev is not None and abs(q - prev) <= 1e-13 * abs(q):
+            break
+        prev = q
+    A1 = C.slip_A1(1.0)
+    su = A.continuum_sum_u(ny, kn, 2.0, A1, 0.55, 1e-6)
+    q_ref = su * np.sqrt(6.0) / (3.0 * 1e-6 * ny * ny)
+    assert abs(q / q_ref - 1.0) <= 1e-8
+    s.close()
 
 
 def test_channel_4x32_full_run():
@@ -122,6 +144,9 @@ def test_channel_no_slip_parabola():
     (dict(nx=513, ny=9, kn=10.0, sigma=0.7, A2=0.3, tq_den=24.0), 30),
     (dict(nx=65, ny=4, kn=0.05, r=0.0, gx=1e-3), 30),          # pure specular walls
     (dict(nx=65, ny=4, kn=0.05, r=1.0, gx=1e-3), 30),          # pure bounce-back
+    (dict(nx=77, ny=13, kn=0.5, gx=1e-3, gy=2e-4, forcing=1), 40),   # third-order force moments
+    (dict(nx=1, ny=6, kn=0.3, gx=1e-4, forcing=1), 25),
+    (dict(nx=1100, ny=5, kn=4.0, gx=-1e-4, gy=3e-5, sigma=0.8, forcing=1, cbbsr_shift=0), 20),
 ])
 def test_random_state_periodic(kw, steps):
     P0 = uniform_populations(kw["nx"], kw["ny"], seed=101)

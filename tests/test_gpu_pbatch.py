@@ -95,6 +95,24 @@ def test_matches_reference(nx, ny, nch, steps, shift, path):
     pb.close()
 
 
+def test_bench_workload_matches_reference():
+    """The benchmarked mass-flow sweep itself (16 channels 2000 x 20, ratio
+    1.8, sigma 0.93, Kn_out 0.01-1, the launch shape bench.py times): every
+    channel against the CPU reference after 4 steps, element by element."""
+    PressureBatch, _, clb = _mods()
+    nx, ny = 2000, 20
+    kns = mass_flow_sweep_kn(16)
+    specs = [dict(kn=k, p_ratio=MASS_FLOW_P_RATIO, sigma=MASS_FLOW_SIGMA) for k in kns]
+    pb = PressureBatch([_gpu_params(clb, nx, ny, s) for s in specs])
+    pb.step(4)
+    for c, spec in enumerate(specs):
+        prm, P0 = _ref(nx, ny, spec)
+        Pref = C.run(P0, prm, 4)
+        P = pb.populations(c).cpu().numpy()
+        assert np.max(np.abs(P - Pref)) <= 1e-10 * np.max(np.abs(Pref)), c
+    pb.close()
+
+
 @pytest.mark.parametrize("nx,ny,nch", [(149, 12, 4), (1030, 40, 5), (50, 70, 2), (2, 3, 3), (2000, 20, 3)])
 def test_row_and_column_kernels_agree_bitwise(nx, ny, nch):
     PressureBatch, _, clb = _mods()

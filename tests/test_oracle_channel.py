@@ -98,6 +98,36 @@ def test_denominator_24_matches_continuum_slip():
     assert abs(ux[:, 0].sum() / cont - 1) <= 1e-6
 
 
+@pytest.mark.parametrize("ny,kn", [(16, 0.1), (16, 1.0), (8, 0.3)])
+def test_third_order_forcing_gives_continuum_slip_with_printed_denominator(ny, kn):
+    """With the source's third-order moments of a second-order (Guo-type)
+    force term, (1 - s_q/2) rho F/3 in k_xyy, the printed Eq. (21) (16)
+    reproduces the continuum second-order slip profile of Eq. (19): the
+    force-driven excess of Eq. (9)'s source (+1.6% at H = 32) vanishes."""
+    prm = C.Params(nx=1, ny=ny, kn=kn, gx=1e-6, forcing=1)
+    P, _ = _steady(prm)
+    A1, _ = C.resolved(prm)
+    _, ux, _ = C.moments(P, prm)
+    cont = A.continuum_sum_u(ny, kn, 2.0, A1, 0.55, 1e-6)
+    assert abs(ux[:, 0].sum() / cont - 1) <= 1e-8
+
+
+def test_third_order_forcing_changes_only_third_moments():
+    """The variant keeps mass and momentum of every node and differs from the
+    Eq. (9) collision only in the raw moments k_xxy, k_xyy, by
+    (1 - s_q/2) rho (F_y, F_x) / 3."""
+    rng_ = np.random.default_rng(5)
+    f = rng_.uniform(0.05, 0.15, size=(9, 40))
+    gx, gy, sq = 3e-3, -2e-3, 0.7
+    a = C.collide(f, gx, gy, 1.1, 0.4, sq, 1.2)
+    b = C.collide(f, gx, gy, 1.1, 0.4, sq, 1.2, forcing=1)
+    d = C.T @ (b - a)
+    rho = f.sum(axis=0)
+    assert np.max(np.abs(d[[0, 1, 2, 3, 4, 5, 8]])) <= 1e-16
+    assert np.allclose(d[6], (1 - sq / 2) * rho * gy / 3, rtol=1e-12, atol=0)
+    assert np.allclose(d[7], (1 - sq / 2) * rho * gx / 3, rtol=1e-12, atol=0)
+
+
 def test_no_slip_magic_combination():
     """P13: r = 1 with (tau_s - 1/2)(tau_q - 1/2) = 1/8 (B2 = 0, denominator
     24) gives the exact no-slip Poiseuille parabola."""
