@@ -80,7 +80,7 @@ def traffic_from_profile():
     return float(rec["bytes_per_launch"])
 
 
-def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True):
+def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True, forcing=0):
     """Batched Kn sweep (64 periodic channels, heights from {16..128}, Kn
     log-spaced 0.01-10, g = 1e-6, each to steady state) in one persistent
     launch, against a loop of single-channel solvers with the same check
@@ -91,7 +91,7 @@ def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True):
     from paper_1603_01955_amd import Batch, Solver, clb
 
     heights, kns = kn_sweep_channels(64, seed=7)
-    params = [clb.make_params(4, ny, kn=kn, gx=1e-6) for ny, kn in zip(heights, kns)]
+    params = [clb.make_params(4, ny, kn=kn, gx=1e-6, forcing=forcing) for ny, kn in zip(heights, kns)]
     b = Batch(params)
     t0 = time.perf_counter()
     threads, longest = b.tune(probe_steps=200)
@@ -211,6 +211,33 @@ def pressure_step(nx=4000, ny=40, steps=20000):
     s.close()
     return {"workload": "pressure_%dx%d" % (nx, ny), "steps": steps, "us_per_step": round(us, 3),
             "mlups": round(nx * ny / us, 1), "algorithmic_gbs": round(BYTES_PER_NODE * nx * ny / us / 1e3, 1)}
+
+
+def forcing_variant(steps=200, warmup=10):
+    """The source with third-order force moments (clb_params.forcing = 1):
+    the periodic step's throughput on the benchmark grid, and the batched Kn
+    sweep's flow-rate minimum, which moves from 1/(sqrt(18 B2) - a) = 0.87 to
+    the continuum 1/(sqrt(12 B2) - a) = 1.76 (no loop baselines)."""
+    import torch
+    from paper_1603_01955_amd import Solver
+    s = Solver(forcing=1, **WORKLOAD)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nodes = s.nx * s.ny
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    sw = kn_sweep(baselines=False, forcing=1)
+    return {"forcing": 1, "step_ms": round(ms, 4), "step_mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
+            "kn_sweep_all_converged": sw["all_converged"], "kn_sweep_batched_s": sw["batched_s"],
+            "kn_at_min_Q": sw["kn_at_min_Q"]}
 
 
 def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2000, baselines=True):
@@ -387,6 +414,7 @@ def main():
     if not args.no_sweep:
         rec["kn_sweep"] = kn_sweep(baselines=not args.no_loop_baseline)
     rec["pressure_step"] = pressure_step()
+    rec["forcing_variant"] = forcing_variant()
     if not args.no_msweep:
         rec["mass_flow_sweep"] = mass_flow_sweep(max_steps=args.msweep_max_steps,
                                                  baselines=not args.no_loop_baseline)
