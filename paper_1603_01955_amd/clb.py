@@ -67,6 +67,7 @@ _SIGNATURES = {
     "clb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "clb_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "clb_set_steps_per_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_set_pressure_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_set_graph_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -167,6 +168,9 @@ class Solver:
 
     def set_launch(self, block_x=1024, xcd_remap=1):
         check(lib().clb_set_launch(self._ctx, int(block_x), int(xcd_remap)))
+
+    def set_steps_per_launch(self, steps=2):
+        check(lib().clb_set_steps_per_launch(self._ctx, int(steps)))
 
     def set_pressure_path(self, path=0):
         """Pressure-mode kernel: 0 by grid size, 1 column kernel, 2 row kernel."""

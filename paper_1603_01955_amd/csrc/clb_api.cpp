@@ -163,8 +163,10 @@ struct clb_ctx {
   double* col_rates;     // pressure mode, large grids: per-column s_nu, s_q
   double* ghosts;        // pressure mode, large grids: ghost columns
   int xcd_remap;
-  // optional hipGraph of graph_steps step launches, one per starting buffer
+  int steps_per_launch;  // periodic mode: 2 = two steps per launch (first kept in LDS), 1 = one
+  // optional hipGraph of graph_steps steps, one per starting buffer
   int graph_steps;
+  int graph_flip;        // buffer parity change of one graph replay (launches mod 2)
   hipStream_t capture;  // private stream used only to record the graphs
   hipGraph_t graph[2];
   hipGraphExec_t gexec[2];
@@ -312,8 +314,10 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->pressure_path = 0;
   c->cus = clb::device_cus();
   c->step_lds = 0;
+  c->steps_per_launch = 2;
   {
     hipError_t e = clb::periodic_step_lds(c->block_x, &c->step_lds);
+    if (e == hipSuccess) e = clb::step2_setup();
     if (e != hipSuccess) {
       delete c;
       return hip_fail(e, "clb_init: device attributes");
@@ -351,21 +355,36 @@ void drop_graphs(clb_ctx* c) {
   }
 }
 
-// Record graph_steps step launches starting from buffer parity c->cur on the
+// Enqueue n steps on stream st starting from buffer parity *cur (updated):
+// in periodic mode two steps per launch when enabled, else one.
+hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) {
+  const bool two = c->p.xbc == CLB_X_PERIODIC && c->steps_per_launch == 2;
+  hipError_t e = hipSuccess;
+  while (n > 0 && e == hipSuccess) {
+    clb::StepArgs a = step_args(c);
+    a.src = c->buf[*cur];
+    a.dst = c->buf[*cur ^ 1];
+    if (two && n >= 2) {
+      e = clb::launch_step2(a, st);
+      n -= 2;
+    } else {
+      e = clb::launch_step(a, c->block_x, st, c->step_lds);
+      n -= 1;
+    }
+    *cur ^= 1;
+  }
+  return e;
+}
+
+// Record graph_steps steps starting from buffer parity c->cur on the
 // private capture stream (recording only: nothing runs there).
 clb_status record_graph(clb_ctx* c) {
   const int p = c->cur;
   if (!c->capture) CLB_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
   CLB_HIP(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-  hipError_t e = hipSuccess;
   int cur = p;
-  for (int k = 0; k < c->graph_steps && e == hipSuccess; ++k) {
-    clb::StepArgs a = step_args(c);
-    a.src = c->buf[cur];
-    a.dst = c->buf[cur ^ 1];
-    e = clb::launch_step(a, c->block_x, c->capture, c->step_lds);
-    cur ^= 1;
-  }
+  const hipError_t e = enqueue_steps(c, c->graph_steps, c->capture, &cur);
+  c->graph_flip = cur ^ p;
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->capture, &g);
   if (e != hipSuccess) {
@@ -387,16 +406,12 @@ clb_status clb_step(clb_ctx* c, int64_t nsteps) {
   while (c->graph_steps > 0 && nsteps >= c->graph_steps) {
     if (!c->gexec[c->cur] && (st = record_graph(c)) != CLB_OK) return st;
     CLB_HIP(hipGraphLaunch(c->gexec[c->cur], c->stream));
-    c->cur ^= (c->graph_steps & 1);
+    c->cur ^= c->graph_flip;
     c->steps += c->graph_steps;
     nsteps -= c->graph_steps;
   }
-  for (int64_t k = 0; k < nsteps; ++k) {
-    clb::StepArgs a = step_args(c);
-    CLB_HIP(clb::launch_step(a, c->block_x, c->stream, c->step_lds));
-    c->cur ^= 1;
-    c->steps += 1;
-  }
+  CLB_HIP(enqueue_steps(c, nsteps, c->stream, &c->cur));
+  c->steps += nsteps;
   return CLB_OK;
 }
 
@@ -522,6 +537,18 @@ clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap) {
   CLB_HIP(clb::periodic_step_lds(block_x, &c->step_lds));
   c->block_x = block_x;
   c->xcd_remap = xcd_remap;
+  return CLB_OK;
+}
+
+clb_status clb_set_steps_per_launch(clb_ctx* c, int32_t steps) {
+  clb_status st = check_ctx(c);
+  if (st != CLB_OK) return st;
+  if (steps != 1 && steps != 2) return fail(CLB_EINVAL, "steps: must be 1 or 2");
+  if (steps != c->steps_per_launch) {
+    CLB_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+  }
+  c->steps_per_launch = steps;
   return CLB_OK;
 }
 

@@ -54,6 +54,64 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// K1b: two periodic steps in one launch (temporal blocking).  A workgroup of
+// 66 x H threads owns a tile of 64 columns x (H - 2) rows.  The first step
+// is computed for the tile and a one-node halo around it (the nodes its
+// second step pulls from; rows beyond a wall are skipped) and kept in LDS;
+// the second step gathers from LDS and writes the tile.  Per two steps a
+// tile node costs (66 H) / (64 (H - 2)) x 72 B of reads and 72 B of writes
+// instead of 2 x 144 B.  The gather and collision are K1's code, so two
+// steps here equal two K1 steps bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kTileX = 64;           // tile columns (one halo column each side)
+constexpr int kTileW = kTileX + 2;   // LDS row width
+
+// First-step populations of a tile in LDS, [9][h][kTileW], addressed with
+// global (unwrapped) coordinates.
+struct TileView {
+  const double* P;
+  int x0, y0;       // global coordinates of LDS column 0 and row 0
+  int h;
+  int nx_, ny_;
+  __device__ __forceinline__ double at(int i, int x, int y) const {
+    return P[(i * h + (y - y0)) * kTileW + (x - x0)];
+  }
+  __device__ __forceinline__ int nx() const { return nx_; }
+  __device__ __forceinline__ int ny() const { return ny_; }
+};
+
+template <bool FORCE, bool THIRD, int H>
+__global__ __launch_bounds__(kTileW * H) void k_step2_periodic(StepArgs a) {
+  extern __shared__ double s1[];   // [9][H][kTileW]
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int ntx = (nx + kTileX - 1) / kTileX;
+  const int b = logical_block(a.xcd_remap);
+  const int by = b / ntx, bx = b - by * ntx;
+  const int x0 = bx * kTileX - 1, y0 = by * (H - 2) - 1;   // global coordinates of LDS (0, 0)
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = x0 + lx, y = y0 + ly;
+  const Rates s{a.s3, a.snu, a.sq, a.s8};
+  if (y >= 0 && y < ny) {
+    int xw = x % nx;                 // x >= -1
+    if (xw < 0) xw += nx;
+    const Gather<0, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+    double f[9];
+    gat(xw, y, f);
+    collide<FORCE, THIRD>(f, a.gx, a.gy, s);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s1[(i * H + ly) * kTileW + lx] = f[i];
+  }
+  __syncthreads();
+  if (lx >= 1 && lx <= kTileX && ly >= 1 && ly <= H - 2 && x < nx && y < ny) {
+    const Gather<3, TileView> gat{{s1, x0, y0, H, nx, ny}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+    double f[9];
+    gat(x, y, f);
+    collide<FORCE, THIRD>(f, a.gx, a.gy, s);
+    store9(a.dst, a.g, x, y, f);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K2: fused pressure-driven step.  Block = CX columns x ny rows (64 row
 // lanes for taller channels), so that up to ny = 64 each thread owns one
 // node and long narrow channels (2000 x 20: 250 workgroups) fill the chip.
@@ -618,6 +676,33 @@ hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_re
   k_pbatch_step<CXV, ONEV><<<grid, dim3(CXV, s.ry), ghost_lds_bytes(a.g), st>>>(b)
   CLB_COLUMN_DISPATCH(s, CLB_PBATCH_LAUNCH);
 #undef CLB_PBATCH_LAUNCH
+  return hipGetLastError();
+}
+
+// Rows per tile of K1b (H - 2 output rows, 66 x H threads).
+constexpr int kStep2H = 15;
+
+hipError_t step2_setup() {
+  const int bytes = 9 * kStep2H * kTileW * (int)sizeof(double);
+  for (const void* k : {(const void*)k_step2_periodic<true, true, kStep2H>,
+                        (const void*)k_step2_periodic<true, false, kStep2H>,
+                        (const void*)k_step2_periodic<false, false, kStep2H>}) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_step2(const StepArgs& a, hipStream_t st) {
+  const size_t tiles = (size_t)((a.g.nx + kTileX - 1) / kTileX) * (size_t)((a.g.ny + kStep2H - 3) / (kStep2H - 2));
+  const dim3 grid((unsigned)tiles), block(kTileW, kStep2H);
+  const size_t lds = 9 * (size_t)kStep2H * kTileW * sizeof(double);
+  if ((a.gx != 0.0 || a.gy != 0.0) && a.forcing)
+    k_step2_periodic<true, true, kStep2H><<<grid, block, lds, st>>>(a);
+  else if (a.gx != 0.0 || a.gy != 0.0)
+    k_step2_periodic<true, false, kStep2H><<<grid, block, lds, st>>>(a);
+  else
+    k_step2_periodic<false, false, kStep2H><<<grid, block, lds, st>>>(a);
   return hipGetLastError();
 }
 

@@ -106,6 +106,7 @@ def test_null_arguments(lib):
     assert lib.clb_derive(ctypes.byref(p), None) == clb.CLB_EINVAL
     assert lib.clb_workspace_size(ctypes.byref(p), None) == clb.CLB_EINVAL
     assert lib.clb_step(None, 1) == clb.CLB_EINVAL
+    assert lib.clb_set_steps_per_launch(None, 2) == clb.CLB_EINVAL
     assert lib.clb_destroy(None) == clb.CLB_EINVAL
     out = ctypes.c_void_p()
     assert lib.clb_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == clb.CLB_EINVAL

@@ -335,6 +335,30 @@ def test_graph_replay_identical(graph_steps):
     assert np.array_equal(s.populations().cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("kw,steps", [
+    (dict(nx=77, ny=13, kn=0.5, gx=1e-3, gy=2e-4), 9),            # ragged tiles, odd step count
+    (dict(nx=1, ny=6, kn=0.3, gx=1e-4), 8),                        # every tile column wraps to x = 0
+    (dict(nx=6, ny=1, kn=0.3), 5),                                 # both walls on one row
+    (dict(nx=130, ny=27, kn=0.1, gx=1e-5, forcing=1, cbbsr_shift=0), 12),
+    (dict(nx=1030, ny=40, kn=2.0, gx=1e-6, sigma=0.8), 7),
+    (dict(nx=64, ny=13, kn=0.2, gx=1e-4, r=0.0), 4),               # one tile exactly
+])
+def test_two_steps_per_launch_bitwise(kw, steps):
+    """Two steps per launch (first step in LDS) give the populations of one
+    step per launch bit for bit, with graphs and an odd remainder."""
+    P0 = torch.from_numpy(uniform_populations(kw["nx"], kw["ny"], seed=77))
+    out = []
+    for spl, graph in ((1, 0), (2, 0), (2, 3)):
+        s = _solver(**kw)
+        s.set_steps_per_launch(spl)
+        s.set_graph_steps(graph)
+        s.set_populations(P0)
+        s.step(steps)
+        out.append(s.populations())
+        s.close()
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+
+
 @pytest.mark.parametrize("path", [1, 2])
 def test_graph_replay_pressure(path):
     """Pressure mode through recorded hipGraphs (the row kernel records two
