@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-msweep", action="store_true", help="skip the pressure-driven mass-flow sweep")
     ap.add_argument("--msweep-max-steps", type=int, default=3000000,
                     help="msweep: step cap per channel (lower it for traced runs)")
+    ap.add_argument("--steps-per-launch", type=int, default=2,
+                    help="periodic step: steps per launch (1-4; the earlier ones kept in LDS)")
     ap.add_argument("--block-x", type=int, default=1024)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -368,6 +370,7 @@ def main():
     torch.cuda.set_device(dev)
     s = Solver(device=dev, **WORKLOAD)
     s.set_launch(args.block_x, args.xcd_remap)
+    s.set_steps_per_launch(args.steps_per_launch)
     nodes = s.nx * s.ny
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -398,12 +401,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "periodic_32768x2048", "nx": s.nx, "ny": s.ny, "kn": WORKLOAD["kn"],
                    "g": WORKLOAD["gx"], "start": "seeded perturbed equilibrium, amp 1e-4, seed 12345",
-                   "buffers": "A-B", "block_x": args.block_x, "xcd_remap": args.xcd_remap},
+                   "buffers": "A-B", "block_x": args.block_x, "xcd_remap": args.xcd_remap,
+                   "steps_per_launch": args.steps_per_launch},
         "hbm_gbs": round(achieved, 1),
         "finite": ok,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic if args.steps_per_launch == 2 else None,
+                     "steps_per_launch": args.steps_per_launch,
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * args.steps_per_launch},
     }
     s.close()
     del s

@@ -163,7 +163,7 @@ struct clb_ctx {
   double* col_rates;     // pressure mode, large grids: per-column s_nu, s_q
   double* ghosts;        // pressure mode, large grids: ghost columns
   int xcd_remap;
-  int steps_per_launch;  // periodic mode: 2 = two steps per launch (first kept in LDS), 1 = one
+  int steps_per_launch;  // periodic mode: steps per launch, 1-4 (those before the last kept in LDS)
   // optional hipGraph of graph_steps steps, one per starting buffer
   int graph_steps;
   int graph_flip;        // buffer parity change of one graph replay (launches mod 2)
@@ -317,7 +317,7 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->steps_per_launch = 2;
   {
     hipError_t e = clb::periodic_step_lds(c->block_x, &c->step_lds);
-    if (e == hipSuccess) e = clb::step2_setup();
+    if (e == hipSuccess) e = clb::stepk_setup();
     if (e != hipSuccess) {
       delete c;
       return hip_fail(e, "clb_init: device attributes");
@@ -356,17 +356,19 @@ void drop_graphs(clb_ctx* c) {
 }
 
 // Enqueue n steps on stream st starting from buffer parity *cur (updated):
-// in periodic mode two steps per launch when enabled, else one.
+// in periodic mode steps_per_launch steps per launch while that many remain,
+// then the remainder in one launch; pressure mode one step per launch.
 hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) {
-  const bool two = c->p.xbc == CLB_X_PERIODIC && c->steps_per_launch == 2;
+  const int k = c->p.xbc == CLB_X_PERIODIC ? c->steps_per_launch : 1;
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {
     clb::StepArgs a = step_args(c);
     a.src = c->buf[*cur];
     a.dst = c->buf[*cur ^ 1];
-    if (two && n >= 2) {
-      e = clb::launch_step2(a, st);
-      n -= 2;
+    const int m = n < k ? (int)n : k;
+    if (m >= 2) {
+      e = clb::launch_stepk(a, m, st);
+      n -= m;
     } else {
       e = clb::launch_step(a, c->block_x, st, c->step_lds);
       n -= 1;
@@ -543,7 +545,7 @@ clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap) {
 clb_status clb_set_steps_per_launch(clb_ctx* c, int32_t steps) {
   clb_status st = check_ctx(c);
   if (st != CLB_OK) return st;
-  if (steps != 1 && steps != 2) return fail(CLB_EINVAL, "steps: must be 1 or 2");
+  if (steps < 1 || steps > 4) return fail(CLB_EINVAL, "steps: must be 1, 2, 3 or 4");
   if (steps != c->steps_per_launch) {
     CLB_HIP(hipStreamSynchronize(c->stream));
     drop_graphs(c);

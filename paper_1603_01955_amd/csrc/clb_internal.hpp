@@ -143,10 +143,10 @@ constexpr size_t kPBatchRowNodes = (size_t)1 << 21;
 // One step of every active channel of a pressure-driven batch; lds_reserve
 // as for launch_step (row kernel only).
 hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_reserve = 0);
-// Two periodic steps in one launch (a.src -> a.dst, the first step kept in
-// LDS); step2_setup allows its LDS size once per process and device.
-hipError_t step2_setup();
-hipError_t launch_step2(const StepArgs& a, hipStream_t st);
+// k = 2, 3 or 4 periodic steps in one launch (a.src -> a.dst, the steps
+// before the last kept in LDS); stepk_setup allows their LDS sizes.
+hipError_t stepk_setup();
+hipError_t launch_stepk(const StepArgs& a, int k, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st);
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);

@@ -54,58 +54,83 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K1b: two periodic steps in one launch (temporal blocking).  A workgroup of
-// 66 x H threads owns a tile of 64 columns x (H - 2) rows.  The first step
-// is computed for the tile and a one-node halo around it (the nodes its
-// second step pulls from; rows beyond a wall are skipped) and kept in LDS;
-// the second step gathers from LDS and writes the tile.  Per two steps a
-// tile node costs (66 H) / (64 (H - 2)) x 72 B of reads and 72 B of writes
-// instead of 2 x 144 B.  The gather and collision are K1's code, so two
-// steps here equal two K1 steps bit for bit.
+// K1b: K periodic steps in one launch (temporal blocking).  A workgroup of
+// (64 + 2(K - 1)) x H threads owns a tile of 64 columns x (H - 2(K - 1))
+// rows.  The first step is computed for the tile and a (K - 1)-node halo
+// around it (rows beyond a wall are skipped) and kept in LDS; each further
+// step gathers from LDS for a region one node smaller on every side and
+// overwrites LDS in place (barriers between reading and writing); the last
+// writes the tile to HBM.  Per K steps a tile node costs
+// (64 + 2(K - 1)) H / (64 (H - 2(K - 1))) x 72 B of reads and 72 B of writes
+// instead of K x 144 B.  The gather and collision are K1's code, so K steps
+// here equal K one-step launches bit for bit.
 // ---------------------------------------------------------------------------
-constexpr int kTileX = 64;           // tile columns (one halo column each side)
-constexpr int kTileW = kTileX + 2;   // LDS row width
+constexpr int kTileX = 64;   // tile columns
 
-// First-step populations of a tile in LDS, [9][h][kTileW], addressed with
-// global (unwrapped) coordinates.
+// Populations of a tile region in LDS, [9][h][w], addressed with global
+// (unwrapped) coordinates.
 struct TileView {
   const double* P;
   int x0, y0;       // global coordinates of LDS column 0 and row 0
-  int h;
+  int w, h;
   int nx_, ny_;
   __device__ __forceinline__ double at(int i, int x, int y) const {
-    return P[(i * h + (y - y0)) * kTileW + (x - x0)];
+    return P[(i * h + (y - y0)) * w + (x - x0)];
   }
   __device__ __forceinline__ int nx() const { return nx_; }
   __device__ __forceinline__ int ny() const { return ny_; }
 };
 
-template <bool FORCE, bool THIRD, int H>
-__global__ __launch_bounds__(kTileW * H) void k_step2_periodic(StepArgs a) {
-  extern __shared__ double s1[];   // [9][H][kTileW]
+template <int K>
+constexpr int tile_w() {
+  return kTileX + 2 * (K - 1);
+}
+
+template <bool FORCE, bool THIRD, int K, int H>
+__global__ __launch_bounds__(tile_w<K>() * H, K == 2 ? 8 : 4) void k_stepk_periodic(StepArgs a) {
+  constexpr int W = tile_w<K>();
+  extern __shared__ double s1[];   // [9][H][W]
   const int nx = a.g.nx, ny = a.g.ny;
   const int ntx = (nx + kTileX - 1) / kTileX;
   const int b = logical_block(a.xcd_remap);
   const int by = b / ntx, bx = b - by * ntx;
-  const int x0 = bx * kTileX - 1, y0 = by * (H - 2) - 1;   // global coordinates of LDS (0, 0)
+  const int x0 = bx * kTileX - (K - 1), y0 = by * (H - 2 * (K - 1)) - (K - 1);   // LDS (0, 0)
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = x0 + lx, y = y0 + ly;
+  const bool row = y >= 0 && y < ny;
   const Rates s{a.s3, a.snu, a.sq, a.s8};
-  if (y >= 0 && y < ny) {
-    int xw = x % nx;                 // x >= -1
+  if (row) {
+    int xw = x % nx;                 // x >= -(K - 1)
     if (xw < 0) xw += nx;
     const Gather<0, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
     double f[9];
     gat(xw, y, f);
     collide<FORCE, THIRD>(f, a.gx, a.gy, s);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) s1[(i * H + ly) * kTileW + lx] = f[i];
+    for (int i = 0; i < 9; ++i) s1[(i * H + ly) * W + lx] = f[i];
   }
-  __syncthreads();
-  if (lx >= 1 && lx <= kTileX && ly >= 1 && ly <= H - 2 && x < nx && y < ny) {
-    const Gather<3, TileView> gat{{s1, x0, y0, H, nx, ny}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+  const Gather<3, TileView> lds{{s1, x0, y0, W, H, nx, ny}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+  // intermediate steps: gather and collide, barrier, overwrite in place
+#pragma unroll
+  for (int k = 1; k < K - 1; ++k) {
+    const bool inside = row && lx >= k && lx < W - k && ly >= k && ly < H - k;
+    __syncthreads();
     double f[9];
-    gat(x, y, f);
+    if (inside) {
+      lds(x, y, f);
+      collide<FORCE, THIRD>(f, a.gx, a.gy, s);
+    }
+    __syncthreads();
+    if (inside) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s1[(i * H + ly) * W + lx] = f[i];
+    }
+  }
+  // last step: the tile itself, written to HBM
+  __syncthreads();
+  if (row && lx >= K - 1 && lx < W - (K - 1) && ly >= K - 1 && ly < H - (K - 1) && x < nx) {
+    double f[9];
+    lds(x, y, f);
     collide<FORCE, THIRD>(f, a.gx, a.gy, s);
     store9(a.dst, a.g, x, y, f);
   }
@@ -679,31 +704,58 @@ hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_re
   return hipGetLastError();
 }
 
-// Rows per tile of K1b (H - 2 output rows, 66 x H threads).
-constexpr int kStep2H = 15;
+// Rows per tile of K1b for K = 2, 3, 4 steps per launch (at most 1024
+// threads: 66 x 15, 68 x 15, 70 x 14).
+template <int K>
+constexpr int stepk_h() {
+  return K == 2 ? 15 : (K == 3 ? 15 : 14);
+}
 
-hipError_t step2_setup() {
-  const int bytes = 9 * kStep2H * kTileW * (int)sizeof(double);
-  for (const void* k : {(const void*)k_step2_periodic<true, true, kStep2H>,
-                        (const void*)k_step2_periodic<true, false, kStep2H>,
-                        (const void*)k_step2_periodic<false, false, kStep2H>}) {
+template <int K>
+size_t stepk_lds() {
+  return 9 * (size_t)stepk_h<K>() * tile_w<K>() * sizeof(double);
+}
+
+template <int K>
+hipError_t stepk_allow() {
+  constexpr int H = stepk_h<K>();
+  const int bytes = (int)stepk_lds<K>();
+  for (const void* k : {(const void*)k_stepk_periodic<true, true, K, H>,
+                        (const void*)k_stepk_periodic<true, false, K, H>,
+                        (const void*)k_stepk_periodic<false, false, K, H>}) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_step2(const StepArgs& a, hipStream_t st) {
-  const size_t tiles = (size_t)((a.g.nx + kTileX - 1) / kTileX) * (size_t)((a.g.ny + kStep2H - 3) / (kStep2H - 2));
-  const dim3 grid((unsigned)tiles), block(kTileW, kStep2H);
-  const size_t lds = 9 * (size_t)kStep2H * kTileW * sizeof(double);
+template <int K>
+hipError_t launch_stepk_t(const StepArgs& a, hipStream_t st) {
+  constexpr int H = stepk_h<K>();
+  const size_t tiles =
+      (size_t)((a.g.nx + kTileX - 1) / kTileX) * (size_t)((a.g.ny + H - 2 * K + 1) / (H - 2 * (K - 1)));
+  const dim3 grid((unsigned)tiles), block(tile_w<K>(), H);
+  const size_t lds = stepk_lds<K>();
   if ((a.gx != 0.0 || a.gy != 0.0) && a.forcing)
-    k_step2_periodic<true, true, kStep2H><<<grid, block, lds, st>>>(a);
+    k_stepk_periodic<true, true, K, H><<<grid, block, lds, st>>>(a);
   else if (a.gx != 0.0 || a.gy != 0.0)
-    k_step2_periodic<true, false, kStep2H><<<grid, block, lds, st>>>(a);
+    k_stepk_periodic<true, false, K, H><<<grid, block, lds, st>>>(a);
   else
-    k_step2_periodic<false, false, kStep2H><<<grid, block, lds, st>>>(a);
+    k_stepk_periodic<false, false, K, H><<<grid, block, lds, st>>>(a);
   return hipGetLastError();
+}
+
+hipError_t stepk_setup() {
+  hipError_t e = stepk_allow<2>();
+  if (e == hipSuccess) e = stepk_allow<3>();
+  if (e == hipSuccess) e = stepk_allow<4>();
+  return e;
+}
+
+hipError_t launch_stepk(const StepArgs& a, int k, hipStream_t st) {
+  if (k == 4) return launch_stepk_t<4>(a, st);
+  if (k == 3) return launch_stepk_t<3>(a, st);
+  return launch_stepk_t<2>(a, st);
 }
 
 hipError_t launch_init(const InitArgs& a, hipStream_t st) {

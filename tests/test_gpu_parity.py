@@ -343,12 +343,13 @@ def test_graph_replay_identical(graph_steps):
     (dict(nx=1030, ny=40, kn=2.0, gx=1e-6, sigma=0.8), 7),
     (dict(nx=64, ny=13, kn=0.2, gx=1e-4, r=0.0), 4),               # one tile exactly
 ])
-def test_two_steps_per_launch_bitwise(kw, steps):
-    """Two steps per launch (first step in LDS) give the populations of one
-    step per launch bit for bit, with graphs and an odd remainder."""
+def test_several_steps_per_launch_bitwise(kw, steps):
+    """Two, three or four steps per launch (the earlier ones in LDS) give the
+    populations of one step per launch bit for bit, with graphs and a
+    shorter remainder."""
     P0 = torch.from_numpy(uniform_populations(kw["nx"], kw["ny"], seed=77))
     out = []
-    for spl, graph in ((1, 0), (2, 0), (2, 3)):
+    for spl, graph in ((1, 0), (2, 0), (2, 3), (3, 0), (4, 0), (4, 5)):
         s = _solver(**kw)
         s.set_steps_per_launch(spl)
         s.set_graph_steps(graph)
@@ -356,7 +357,8 @@ def test_two_steps_per_launch_bitwise(kw, steps):
         s.step(steps)
         out.append(s.populations())
         s.close()
-    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+    for k in range(1, len(out)):
+        assert torch.equal(out[0], out[k]), k
 
 
 @pytest.mark.parametrize("path", [1, 2])
