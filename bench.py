@@ -409,7 +409,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic if args.steps_per_launch == 2 else None,
                      "steps_per_launch": args.steps_per_launch,
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * args.steps_per_launch},
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * args.steps_per_launch,
+                     # measured HBM bytes per launch over the launch time: the bandwidth actually drawn
+                     "traffic_gbs": (round(traffic / (ms * args.steps_per_launch * 1e-3) / 1e9, 1)
+                                     if traffic and args.steps_per_launch == 2 else None)},
     }
     s.close()
     del s
