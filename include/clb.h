@@ -174,12 +174,15 @@ clb_status clb_check_finite(clb_ctx* c, int32_t* h_ok);
  * xcd_remap = 1 to map consecutive row segments onto the same XCD. */
 clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap);
 
-/* Periodic-mode temporal blocking (tuning): steps = 2 (default) advances two
- * steps per launch -- each workgroup computes the first step for its tile and
- * a one-node halo into LDS, then the second step from LDS -- so a node update
- * moves about 79 instead of 144 bytes; an odd remainder of clb_step takes a
- * one-step launch.  steps = 1: one step per launch.  Both give bitwise the
- * same populations.  CLB_EINVAL for other values; no effect in pressure mode. */
+/* Temporal blocking (tuning): steps = 2 (default) advances two steps per
+ * launch -- each workgroup computes the first step for its tile and a
+ * one-node halo into LDS, then the second step from LDS -- so a node update
+ * moves about 79 instead of 144 bytes (periodic mode); in pressure mode the
+ * same for channels of at most 48 rows on the column-kernel path (the edge
+ * workgroups rebuild the ghost columns from the LDS values).  steps = 3 or 4
+ * (periodic mode; pressure mode takes 2) keep more steps in LDS; a shorter
+ * remainder of clb_step takes fewer.  steps = 1: one step per launch.  All
+ * give bitwise the same populations.  CLB_EINVAL for other values. */
 clb_status clb_set_steps_per_launch(clb_ctx* c, int32_t steps);
 
 /* Pressure-mode kernel choice (tuning; Section 3.2 step): 0 = by grid size

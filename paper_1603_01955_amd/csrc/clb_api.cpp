@@ -356,10 +356,13 @@ void drop_graphs(clb_ctx* c) {
 }
 
 // Enqueue n steps on stream st starting from buffer parity *cur (updated):
-// in periodic mode steps_per_launch steps per launch while that many remain,
-// then the remainder in one launch; pressure mode one step per launch.
+// periodic mode steps_per_launch steps per launch while that many remain,
+// then the remainder in one launch; pressure mode two per launch where the
+// two-step kernel applies and steps_per_launch >= 2, else one.
 hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) {
-  const int k = c->p.xbc == CLB_X_PERIODIC ? c->steps_per_launch : 1;
+  const bool periodic = c->p.xbc == CLB_X_PERIODIC;
+  int k = c->steps_per_launch;
+  if (!periodic) k = (k >= 2 && clb::pressure_two_step_ok(step_args(c))) ? 2 : 1;
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {
     clb::StepArgs a = step_args(c);
@@ -367,7 +370,7 @@ hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) 
     a.dst = c->buf[*cur ^ 1];
     const int m = n < k ? (int)n : k;
     if (m >= 2) {
-      e = clb::launch_stepk(a, m, st);
+      e = periodic ? clb::launch_stepk(a, m, st) : clb::launch_step2_pressure(a, st);
       n -= m;
     } else {
       e = clb::launch_step(a, c->block_x, st, c->step_lds);

@@ -147,6 +147,10 @@ hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_re
 // before the last kept in LDS); stepk_setup allows their LDS sizes.
 hipError_t stepk_setup();
 hipError_t launch_stepk(const StepArgs& a, int k, hipStream_t st);
+// Two pressure-driven steps in one launch (a.src -> a.dst); only where
+// pressure_two_step_ok holds (ny <= 48, column-kernel path).
+bool pressure_two_step_ok(const StepArgs& a);
+hipError_t launch_step2_pressure(const StepArgs& a, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st);
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);

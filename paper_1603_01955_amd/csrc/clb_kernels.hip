@@ -258,6 +258,91 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_step_pressure(S
 }
 
 // ---------------------------------------------------------------------------
+// K2e: two pressure-driven steps in one launch, for channels of at most 64
+// rows.  A workgroup of (CX + 2) x ny threads computes the first step for
+// its CX columns and one column on each side (inlet / outlet ghost columns
+// staged from HBM as in K2) and keeps it in LDS; the workgroups holding the
+// first or last column then rebuild the ghost columns from those LDS values,
+// and every workgroup computes the second step for its CX columns from LDS
+// and stores it.  Each step takes its per-column rates from its own centre
+// rows.  The gather, ghost, rate and collision arithmetic is K2's, so the
+// result equals two K2 steps bit for bit; a node update moves
+// ((CX + 2) / CX x 72 + 72) / 2 bytes of HBM traffic instead of 144.
+// ---------------------------------------------------------------------------
+template <int CX>
+__global__ __launch_bounds__(1024) void k_step2_pressure(StepArgs a) {
+  constexpr int W = CX + 2;
+  extern __shared__ double lds2[];
+  __shared__ double s_rc[2][W];
+  const int nx = a.g.nx, ny = a.g.ny;
+  double* s1 = lds2;                   // [9][ny][W]: first-step populations
+  double* gh = lds2 + 9 * ny * W;      // [2][9][ny]: ghost columns (first, then second step)
+  const int blk = logical_block(a.xcd_remap);
+  const int x0 = blk * CX - 1;         // global column of LDS column 0
+  const int lx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * W + lx, nthreads = W * ny;
+  const int x = x0 + lx;
+  const int yc = ny / 2;
+  const bool even = (ny & 1) == 0;
+  const double omr = 1.0 - a.r;
+  // first step: columns x0 .. x0 + CX + 1 that exist
+  {
+    const bool in1 = x0 <= 0, out1 = x0 + W - 1 >= nx - 1;   // the region holds column 0 / nx - 1
+    const bool valid = x >= 0 && x < nx;
+    double f[9];
+    if (in1 || out1) {
+      const View v{a.src, a.g};
+      fill_ghosts(v, a.rho_in, a.rho_out, in1, out1, gh, gh + 9 * ny, tid, nthreads);
+      __syncthreads();
+      if (valid) gather_node(Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}, x, ty, f);
+    } else {
+      gather_node(Gather<3, View>{{a.src, a.g}, a.r, omr, a.shift, a.rho_in, a.rho_out}, x, ty, f);
+    }
+    if (valid) {
+      if (ty == yc) s_rc[0][lx] = sum9(f);
+      if (even && ty == yc - 1) s_rc[1][lx] = sum9(f);
+    }
+    __syncthreads();
+    if (valid) {
+      const double rc = even ? 0.5 * (s_rc[1][lx] + s_rc[0][lx]) : s_rc[0][lx];
+      double snu, sq;
+      local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
+      collide<false>(f, 0.0, 0.0, Rates{a.s3, snu, sq, a.s8});
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s1[(i * ny + ty) * W + lx] = f[i];
+    }
+  }
+  __syncthreads();
+  // second step: columns x0 + 1 .. x0 + CX
+  {
+    const TileView tv{s1, x0, 0, W, ny, nx, ny};
+    const bool in2 = x0 + 1 == 0, out2 = x0 + CX >= nx - 1;   // the outputs hold column 0 / nx - 1
+    const bool out = lx >= 1 && lx <= CX && x < nx;
+    if (in2 || out2) {
+      fill_ghosts(tv, a.rho_in, a.rho_out, in2, out2, gh, gh + 9 * ny, tid, nthreads);
+      __syncthreads();
+    }
+    double f[9];
+    if (out) {
+      if (in2 || out2)
+        Gather<2, TileView>{tv, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}(x, ty, f);
+      else
+        Gather<3, TileView>{tv, a.r, omr, a.shift, a.rho_in, a.rho_out}(x, ty, f);
+      if (ty == yc) s_rc[0][lx] = sum9(f);
+      if (even && ty == yc - 1) s_rc[1][lx] = sum9(f);
+    }
+    __syncthreads();
+    if (out) {
+      const double rc = even ? 0.5 * (s_rc[1][lx] + s_rc[0][lx]) : s_rc[0][lx];
+      double snu, sq;
+      local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
+      collide<false>(f, 0.0, 0.0, Rates{a.s3, snu, sq, a.s8});
+      store9(a.dst, a.g, x, ty, f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K2c: one step of a batch of pressure-driven channels of the same grid
 // (the mass-flow sweep of Section 3.2), in one launch: workgroup b serves
 // column block b % nblk of channel live[b / nblk] with that channel's
@@ -679,6 +764,44 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
     CLB_COLUMN_DISPATCH(s, CLB_PRESSURE_LAUNCH);
 #undef CLB_PRESSURE_LAUNCH
   }
+  return hipGetLastError();
+}
+
+// Two-step pressure launches: channels of at most kPressureTwoStepRows rows
+// on the column kernel's path (grids that take the row kernel step one at a
+// time).  Measured, us per step one / two steps per launch: 2000 x 20
+// 4.35 / 3.48, 4000 x 40 6.37 / 4.99, 8192 x 40 11.75 / 8.74, 32768 x 16
+// 15.45 / 14.65, but 16384 x 64 33.0 / 34.1 (8-column tiles: the halo
+// columns cost more than the second launch saves).
+constexpr int kPressureTwoStepRows = 48;
+
+bool pressure_two_step_ok(const StepArgs& a) {
+  const bool rows = a.col_rates && a.ghosts &&
+                    (a.pressure_path == 2 || (a.pressure_path == 0 && (size_t)a.g.nx * a.g.ny >= kPressureRowNodes));
+  return a.mode == 1 && a.g.ny <= kPressureTwoStepRows && !rows;
+}
+
+// Width of K2e: the widest of 32, 16, 8 columns with (CX + 2) ny <= 1024 that
+// leaves about one workgroup per CU, else 8.
+hipError_t launch_step2_pressure(const StepArgs& a, hipStream_t st) {
+  const int ny = a.g.ny;
+  const long enough = a.cus > 0 ? a.cus - a.cus / 10 : 230;
+  int cx = 8;
+  for (const int cand : {32, 16}) {
+    if ((cand + 2) * ny > 1024) continue;
+    if ((a.g.nx + cand - 1) / cand >= enough) {
+      cx = cand;
+      break;
+    }
+  }
+  const dim3 grid((unsigned)((a.g.nx + cx - 1) / cx)), block(cx + 2, ny);
+  const size_t lds = (9 * (size_t)ny * (cx + 2) + 18 * (size_t)ny) * sizeof(double);
+  if (cx == 32)
+    k_step2_pressure<32><<<grid, block, lds, st>>>(a);
+  else if (cx == 16)
+    k_step2_pressure<16><<<grid, block, lds, st>>>(a);
+  else
+    k_step2_pressure<8><<<grid, block, lds, st>>>(a);
   return hipGetLastError();
 }
 

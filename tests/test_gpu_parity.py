@@ -342,6 +342,14 @@ def test_graph_replay_identical(graph_steps):
     (dict(nx=130, ny=27, kn=0.1, gx=1e-5, forcing=1, cbbsr_shift=0), 12),
     (dict(nx=1030, ny=40, kn=2.0, gx=1e-6, sigma=0.8), 7),
     (dict(nx=64, ny=13, kn=0.2, gx=1e-4, r=0.0), 4),               # one tile exactly
+    (dict(nx=2000, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0), 9),           # pressure: 8-column tiles
+    (dict(nx=4000, ny=40, xbc="pressure", kn=0.2, p_ratio=1.8, sigma=0.93), 6),  # 16 columns
+    (dict(nx=17, ny=3, xbc="pressure", kn=0.3, p_ratio=1.5, cbbsr_shift=0), 7),  # two ragged workgroups
+    (dict(nx=2, ny=1, xbc="pressure", kn=0.05, p_ratio=1.4), 5),              # both ghosts in one workgroup
+    (dict(nx=300, ny=48, xbc="pressure", kn=0.1, p_ratio=2.0, tq_den=24.0), 4),   # tallest two-step channel
+    (dict(nx=90, ny=70, xbc="pressure", kn=0.1, p_ratio=2.0), 4),             # taller: one step per launch
+    (dict(nx=100, ny=64, xbc="pressure", kn=0.1, p_ratio=2.0), 4),
+    (dict(nx=9000, ny=12, xbc="pressure", kn=0.2, p_ratio=1.5), 5),           # 32 columns
 ])
 def test_several_steps_per_launch_bitwise(kw, steps):
     """Two, three or four steps per launch (the earlier ones in LDS) give the
