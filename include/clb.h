@@ -294,6 +294,12 @@ clb_status clb_pbatch_step(clb_pbatch* b, int64_t nsteps);
 clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every, double tol,
                           int64_t* h_steps, int32_t* h_converged);
 
+/* Steps per launch (tuning): 2 (default) advances the running channels two
+ * steps per launch (first step kept in LDS, as clb_set_steps_per_launch in
+ * pressure mode) where the grid allows it (ny <= 48, column kernel), 1 one
+ * step per launch.  Bitwise the same populations.  CLB_EINVAL otherwise. */
+clb_status clb_pbatch_set_steps_per_launch(clb_pbatch* b, int32_t steps);
+
 /* Kernel choice (tuning): 0 = by total size (default; the row form from
  * 2^21 nodes over all channels), 1 = column kernel (each workgroup owns whole
  * columns of one channel), 2 = row kernel (a prep launch computes every

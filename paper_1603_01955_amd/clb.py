@@ -346,6 +346,7 @@ _PBATCH_SIGNATURES = {
     "clb_pbatch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "clb_pbatch_set_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "clb_pbatch_set_steps_per_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_pbatch_massflow": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "clb_pbatch_column_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
@@ -399,6 +400,9 @@ class PressureBatch:
     def set_path(self, path=0):
         """0: by total size, 1: column kernel, 2: row kernel."""
         check(lib().clb_pbatch_set_path(self._h, int(path)))
+
+    def set_steps_per_launch(self, steps=2):
+        check(lib().clb_pbatch_set_steps_per_launch(self._h, int(steps)))
 
     def massflow(self):
         """(m, m_ns): column-mean mass flow of each channel and the continuum

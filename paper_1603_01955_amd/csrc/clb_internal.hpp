@@ -72,13 +72,15 @@ struct PChan {
 };
 
 // Run state of one channel of such a batch.  Every channel starts at step 0
-// and the channels still running share one step count, so a channel's
-// current populations are in buffer (steps & 1).
+// in buffer 0; the channels still running share one step count and one
+// current buffer, which the check kernel records in cur.
 struct PChanState {
   int64_t steps;        // steps taken
   int32_t active;       // 0 once converged: no further steps
   int32_t have_prev;    // prev holds the mass flow of the previous check
   double prev;          // column-mean mass flow at the previous check
+  int32_t cur;          // buffer holding the current populations
+  int32_t pad;
 };
 
 struct PBatchArgs {
@@ -143,6 +145,10 @@ constexpr size_t kPBatchRowNodes = (size_t)1 << 21;
 // One step of every active channel of a pressure-driven batch; lds_reserve
 // as for launch_step (row kernel only).
 hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_reserve = 0);
+// Two steps of every active channel in one launch, where pbatch_two_step_ok
+// holds (ny <= 48, column-kernel path for the running channels).
+bool pbatch_two_step_ok(const PBatchArgs& a);
+hipError_t launch_pbatch_step2(const PBatchArgs& a, hipStream_t st);
 // k = 2, 3 or 4 periodic steps in one launch (a.src -> a.dst, the steps
 // before the last kept in LDS); stepk_setup allows their LDS sizes.
 hipError_t stepk_setup();

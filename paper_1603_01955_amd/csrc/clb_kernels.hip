@@ -270,14 +270,11 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_step_pressure(S
 // ((CX + 2) / CX x 72 + 72) / 2 bytes of HBM traffic instead of 144.
 // ---------------------------------------------------------------------------
 template <int CX>
-__global__ __launch_bounds__(1024) void k_step2_pressure(StepArgs a) {
+__device__ __forceinline__ void pressure2_block(const StepArgs& a, int blk, double* lds2, double (*s_rc)[CX + 2]) {
   constexpr int W = CX + 2;
-  extern __shared__ double lds2[];
-  __shared__ double s_rc[2][W];
   const int nx = a.g.nx, ny = a.g.ny;
   double* s1 = lds2;                   // [9][ny][W]: first-step populations
   double* gh = lds2 + 9 * ny * W;      // [2][9][ny]: ghost columns (first, then second step)
-  const int blk = logical_block(a.xcd_remap);
   const int x0 = blk * CX - 1;         // global column of LDS column 0
   const int lx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * W + lx, nthreads = W * ny;
@@ -342,6 +339,13 @@ __global__ __launch_bounds__(1024) void k_step2_pressure(StepArgs a) {
   }
 }
 
+template <int CX>
+__global__ __launch_bounds__(1024) void k_step2_pressure(StepArgs a) {
+  extern __shared__ double lds2[];   // [9][ny][CX + 2] + [2][9][ny]
+  __shared__ double s_rc[2][CX + 2];
+  pressure2_block<CX>(a, logical_block(a.xcd_remap), lds2, s_rc);
+}
+
 // ---------------------------------------------------------------------------
 // K2c: one step of a batch of pressure-driven channels of the same grid
 // (the mass-flow sweep of Section 3.2), in one launch: workgroup b serves
@@ -386,6 +390,18 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_pbatch_step(PBa
   const int c = p.live[k];
   if (!p.state[c].active) return;
   pressure_block<CX, ONE>(channel_args(p, c), b - k * p.nblk, p.nblk, s_rc, s_ghost);
+}
+
+// Two steps of every running channel in one launch (K2e per channel).
+template <int CX>
+__global__ __launch_bounds__(1024) void k_pbatch_step2(PBatchArgs p) {
+  extern __shared__ double lds2[];
+  __shared__ double s_rc[2][CX + 2];
+  const int b = logical_block(p.xcd_remap);
+  const int k = b / p.nblk;
+  const int c = p.live[k];
+  if (!p.state[c].active) return;
+  pressure2_block<CX>(channel_args(p, c), b - k * p.nblk, lds2, s_rc);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,18 +798,19 @@ bool pressure_two_step_ok(const StepArgs& a) {
 }
 
 // Width of K2e: the widest of 32, 16, 8 columns with (CX + 2) ny <= 1024 that
-// leaves about one workgroup per CU, else 8.
+// leaves about one workgroup per CU over nch channels, else 8.
+int step2_pressure_cx(const Geo& g, int nch, int cus) {
+  const long enough = cus > 0 ? cus - cus / 10 : 230;
+  for (const int cand : {32, 16}) {
+    if ((cand + 2) * g.ny > 1024) continue;
+    if ((long)nch * ((g.nx + cand - 1) / cand) >= enough) return cand;
+  }
+  return 8;
+}
+
 hipError_t launch_step2_pressure(const StepArgs& a, hipStream_t st) {
   const int ny = a.g.ny;
-  const long enough = a.cus > 0 ? a.cus - a.cus / 10 : 230;
-  int cx = 8;
-  for (const int cand : {32, 16}) {
-    if ((cand + 2) * ny > 1024) continue;
-    if ((a.g.nx + cand - 1) / cand >= enough) {
-      cx = cand;
-      break;
-    }
-  }
+  const int cx = step2_pressure_cx(a.g, 1, a.cus);
   const dim3 grid((unsigned)((a.g.nx + cx - 1) / cx)), block(cx + 2, ny);
   const size_t lds = (9 * (size_t)ny * (cx + 2) + 18 * (size_t)ny) * sizeof(double);
   if (cx == 32)
@@ -802,6 +819,28 @@ hipError_t launch_step2_pressure(const StepArgs& a, hipStream_t st) {
     k_step2_pressure<16><<<grid, block, lds, st>>>(a);
   else
     k_step2_pressure<8><<<grid, block, lds, st>>>(a);
+  return hipGetLastError();
+}
+
+bool pbatch_two_step_ok(const PBatchArgs& a) {
+  const bool rows = a.col_rates && a.ghosts &&
+                    (a.path == 2 || (a.path == 0 && (size_t)a.nch * a.g.nx * a.g.ny >= kPBatchRowNodes));
+  return a.g.ny <= kPressureTwoStepRows && !rows;
+}
+
+hipError_t launch_pbatch_step2(const PBatchArgs& a, hipStream_t st) {
+  const int ny = a.g.ny;
+  const int cx = step2_pressure_cx(a.g, a.nch, a.cus);
+  PBatchArgs b = a;
+  b.nblk = (a.g.nx + cx - 1) / cx;
+  const dim3 grid((unsigned)((size_t)b.nblk * a.nch)), block(cx + 2, ny);
+  const size_t lds = (9 * (size_t)ny * (cx + 2) + 18 * (size_t)ny) * sizeof(double);
+  if (cx == 32)
+    k_pbatch_step2<32><<<grid, block, lds, st>>>(b);
+  else if (cx == 16)
+    k_pbatch_step2<16><<<grid, block, lds, st>>>(b);
+  else
+    k_pbatch_step2<8><<<grid, block, lds, st>>>(b);
   return hipGetLastError();
 }
 

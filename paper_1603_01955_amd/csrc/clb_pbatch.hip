@@ -55,19 +55,21 @@ __device__ double channel_massflow(const PBatchArgs& p, const PChan& ch, const d
   return s_red[0] / (double)p.g.nx;
 }
 
-// After `add` steps of the running channels: count them, and with `check`
-// compare each running channel's mass flow with its previous check; the
-// channel stops once |m - m_prev| <= tol |m|.  One workgroup per channel.
-__global__ __launch_bounds__(kMassThreads) void k_pbatch_check(PBatchArgs p, PChanState* st, int add, int check,
-                                                                double tol) {
+// After `add` steps of the running channels, whose state is now in buffer
+// `cur`: count them, record the buffer, and with `check` compare each running
+// channel's mass flow with its previous check; the channel stops once
+// |m - m_prev| <= tol |m|.  One workgroup per channel.
+__global__ __launch_bounds__(kMassThreads) void k_pbatch_check(PBatchArgs p, PChanState* st, int add, int cur,
+                                                                int check, double tol) {
   __shared__ double s_red[kMassThreads];
   const int c = blockIdx.x;
   PChanState s = st[c];
   __syncthreads();   // every thread has read st[c] before thread 0 rewrites it
   if (!s.active) return;
   s.steps += add;
+  s.cur = cur;
   if (check) {
-    const double m = channel_massflow(p, p.ch[c], p.buf[s.steps & 1] + (size_t)c * p.stride, s_red);
+    const double m = channel_massflow(p, p.ch[c], p.buf[s.cur] + (size_t)c * p.stride, s_red);
     if (s.have_prev && fabs(m - s.prev) <= tol * fabs(m)) s.active = 0;
     s.prev = m;
     s.have_prev = 1;
@@ -79,13 +81,13 @@ __global__ __launch_bounds__(kMassThreads) void k_pbatch_check(PBatchArgs p, PCh
 __global__ __launch_bounds__(kMassThreads) void k_pbatch_mass(PBatchArgs p, const PChanState* st, double* m) {
   __shared__ double s_red[kMassThreads];
   const int c = blockIdx.x;
-  const double v = channel_massflow(p, p.ch[c], p.buf[st[c].steps & 1] + (size_t)c * p.stride, s_red);
+  const double v = channel_massflow(p, p.ch[c], p.buf[st[c].cur] + (size_t)c * p.stride, s_red);
   if (threadIdx.x == 0) m[c] = v;
 }
 
 __global__ void k_pbatch_reset(PChanState* st, int nch) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < nch) st[c] = PChanState{0, 1, 0, 0.0};
+  if (c < nch) st[c] = PChanState{0, 1, 0, 0.0, 0, 0};
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -140,11 +142,14 @@ struct clb_pbatch {
   std::vector<int32_t> h_live;             // host copy, read by the last upload
   int32_t n_live;
   int64_t t;                               // steps taken by the channels still running
+  int32_t par;                             // buffer holding their current state
+  int32_t steps_per_launch;                // 2: two-step launches where they apply, 1: one step
   hipStream_t stream;                      // caller's stream: all work runs here
   hipStream_t capture;                     // private stream, used only to record graphs
   size_t step_lds;                         // LDS reserved per row-kernel workgroup (occupancy cap)
-  hipGraph_t graph[2];                     // check_every steps + check, per starting parity
+  hipGraph_t graph[2];                     // check_every steps + check, per starting buffer
   hipGraphExec_t exec[2];
+  int32_t g_end[2];                        // buffer after a replay, per starting buffer
   int32_t g_every;
   double g_tol;
   int32_t g_live;                          // running channels the graphs were recorded for
@@ -163,23 +168,34 @@ void drop_graphs(clb_pbatch* b) {
   }
 }
 
-// n step launches of the running channels from parity par, then the count
-// (and with check the convergence test) on stream st.
-clb_status enqueue_chunk(clb_pbatch* b, hipStream_t st, int par, int64_t n, int check, double tol) {
+// n steps of the running channels from buffer *par (updated) -- two per
+// launch where the two-step kernel applies -- then the count (and with check
+// the convergence test) on stream st.
+clb_status enqueue_chunk(clb_pbatch* b, hipStream_t st, int* par, int64_t n, int check, double tol) {
   clb::PBatchArgs a = b->args;
   a.nch = b->n_live;
-  for (int64_t k = 0; k < n && b->n_live > 0; ++k) {
-    a.par = (int)((par + k) & 1);
-    PBATCH_HIP(clb::launch_pbatch_step(a, st, b->step_lds));
+  const bool two = b->steps_per_launch >= 2 && b->n_live > 0 && clb::pbatch_two_step_ok(a);
+  for (int64_t left = n; left > 0 && b->n_live > 0;) {
+    a.par = *par;
+    if (two && left >= 2) {
+      PBATCH_HIP(clb::launch_pbatch_step2(a, st));
+      left -= 2;
+    } else {
+      PBATCH_HIP(clb::launch_pbatch_step(a, st, b->step_lds));
+      left -= 1;
+    }
+    *par ^= 1;
   }
-  clb::k_pbatch_check<<<b->nch, clb::kMassThreads, 0, st>>>(b->args, b->d_state, (int)n, check, tol);
+  clb::k_pbatch_check<<<b->nch, clb::kMassThreads, 0, st>>>(b->args, b->d_state, (int)n, *par, check, tol);
   PBATCH_HIP(hipGetLastError());
   return CLB_OK;
 }
 
 clb_status record_chunk(clb_pbatch* b, int par, int32_t every, double tol) {
   PBATCH_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-  clb_status st = enqueue_chunk(b, b->capture, par, every, 1, tol);
+  int end = par;
+  clb_status st = enqueue_chunk(b, b->capture, &end, every, 1, tol);
+  b->g_end[par] = end;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(b->capture, &g);
   if (st != CLB_OK) {
@@ -217,7 +233,7 @@ clb_status read_state(clb_pbatch* b) {
 clb::DiagArgs diag_of(const clb_pbatch* b, int ch) {
   const clb::PChan& c = b->chan[ch];
   clb::DiagArgs d{};
-  d.src = b->args.buf[b->h_state[ch].steps & 1] + (size_t)ch * b->args.stride;
+  d.src = b->args.buf[b->h_state[ch].cur] + (size_t)ch * b->args.stride;
   d.g = b->args.g;
   d.mode = CLB_X_PRESSURE;
   d.shift = b->args.shift;
@@ -326,9 +342,11 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   b->h_live.resize(nch);
   for (int c = 0; c < nch; ++c) b->h_live[c] = c;
   b->n_live = nch;
-  b->h_state.assign(nch, clb::PChanState{0, 1, 0, 0.0});
+  b->h_state.assign(nch, clb::PChanState{0, 1, 0, 0.0, 0, 0});
   b->h_m.assign(nch, 0.0);
   b->t = 0;
+  b->par = 0;
+  b->steps_per_launch = 2;
   b->stream = static_cast<hipStream_t>(hip_stream);
 
   auto fail_init = [b](hipError_t e, const char* where) {
@@ -376,11 +394,14 @@ clb_status clb_pbatch_step(clb_pbatch* b, int64_t nsteps) {
   if (!b) return clb::perr(CLB_EINVAL, "batch: NULL");
   if (nsteps < 0) return clb::perr(CLB_EINVAL, "nsteps: must be >= 0");
   if (nsteps == 0) return CLB_OK;
-  clb_status st = enqueue_chunk(b, b->stream, (int)(b->t & 1), nsteps, 0, 0.0);
+  clb_status st = enqueue_chunk(b, b->stream, &b->par, nsteps, 0, 0.0);
   if (st != CLB_OK) return st;
   b->t += nsteps;
   for (auto& s : b->h_state)
-    if (s.active) s.steps += nsteps;
+    if (s.active) {
+      s.steps += nsteps;
+      s.cur = b->par;
+    }
   return CLB_OK;
 }
 
@@ -406,12 +427,13 @@ clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every,
         drop_graphs(b);
         b->g_live = b->n_live;
       }
-      const int par = (int)(b->t & 1);
+      const int par = b->par;
       const int64_t n = left < check_every ? left : check_every;
       if (n == check_every) {
         if (!b->exec[par] && (st = record_chunk(b, par, check_every, tol)) != CLB_OK) return st;
         PBATCH_HIP(hipGraphLaunch(b->exec[par], b->stream));
-      } else if ((st = enqueue_chunk(b, b->stream, par, n, 0, 0.0)) != CLB_OK) {
+        b->par = b->g_end[par];
+      } else if ((st = enqueue_chunk(b, b->stream, &b->par, n, 0, 0.0)) != CLB_OK) {
         return st;
       }
       b->t += n;
@@ -425,6 +447,17 @@ clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every,
       if (h_steps) h_steps[c] = b->h_state[c].steps;
       if (h_converged) h_converged[c] = b->h_state[c].active ? 0 : 1;
     }
+  }
+  return CLB_OK;
+}
+
+clb_status clb_pbatch_set_steps_per_launch(clb_pbatch* b, int32_t steps) {
+  if (!b) return clb::perr(CLB_EINVAL, "batch: NULL");
+  if (steps != 1 && steps != 2) return clb::perr(CLB_EINVAL, "steps: must be 1 or 2");
+  if (steps != b->steps_per_launch) {
+    PBATCH_HIP(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    b->steps_per_launch = steps;
   }
   return CLB_OK;
 }

@@ -115,19 +115,24 @@ def test_bench_workload_matches_reference():
 
 @pytest.mark.parametrize("nx,ny,nch", [(149, 12, 4), (1030, 40, 5), (50, 70, 2), (2, 3, 3), (2000, 20, 3)])
 def test_row_and_column_kernels_agree_bitwise(nx, ny, nch):
+    """Row and column kernels, one or two steps per launch (odd chunks, so
+    both launch kinds and both buffers occur): the same populations."""
     PressureBatch, _, clb = _mods()
     params = [_gpu_params(clb, nx, ny, s) for s in _specs(nch)]
     out = []
     for path in (1, 2):
-        pb = PressureBatch(params)
-        pb.set_path(path)
-        pb.step(7)
-        steps, _ = pb.run(6, check_every=3, tol=0.0)
-        assert steps.tolist() == [13] * nch
-        out.append([pb.populations(c) for c in range(nch)])
-        pb.close()
-    for c in range(nch):
-        assert torch.equal(out[0][c], out[1][c]), c
+        for spl in (1, 2):
+            pb = PressureBatch(params)
+            pb.set_path(path)
+            pb.set_steps_per_launch(spl)
+            pb.step(7)
+            steps, _ = pb.run(6, check_every=3, tol=0.0)
+            assert steps.tolist() == [13] * nch
+            out.append([pb.populations(c) for c in range(nch)])
+            pb.close()
+    for k in range(1, len(out)):
+        for c in range(nch):
+            assert torch.equal(out[0][c], out[k][c]), (k, c)
 
 
 def test_run_stops_each_channel_where_its_mass_flow_settles():
