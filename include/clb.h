@@ -177,7 +177,8 @@ clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap);
 /* Temporal blocking (tuning): steps = 2 (default) advances two steps per
  * launch -- each workgroup computes the first step for its tile and a
  * one-node halo into LDS, then the second step from LDS -- so a node update
- * moves about 79 instead of 144 bytes (periodic mode); in pressure mode the
+ * moves about 79 instead of 144 bytes (periodic mode, nx >= 64; narrower
+ * grids step one at a time); in pressure mode the
  * same for channels of at most 48 rows on the column-kernel path (the edge
  * workgroups rebuild the ghost columns from the LDS values).  steps = 3 or 4
  * (periodic mode; pressure mode takes 2) keep more steps in LDS; a shorter

@@ -356,12 +356,13 @@ void drop_graphs(clb_ctx* c) {
 }
 
 // Enqueue n steps on stream st starting from buffer parity *cur (updated):
-// periodic mode steps_per_launch steps per launch while that many remain,
-// then the remainder in one launch; pressure mode two per launch where the
-// two-step kernel applies and steps_per_launch >= 2, else one.
+// periodic mode (nx >= 64) steps_per_launch steps per launch while that many
+// remain, then the remainder in one launch; pressure mode two per launch
+// where the two-step kernel applies and steps_per_launch >= 2; else one.
 hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) {
   const bool periodic = c->p.xbc == CLB_X_PERIODIC;
   int k = c->steps_per_launch;
+  if (periodic && !clb::periodic_multi_step_ok(step_args(c))) k = 1;
   if (!periodic) k = (k >= 2 && clb::pressure_two_step_ok(step_args(c))) ? 2 : 1;
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {

@@ -162,8 +162,16 @@ __device__ double channel_sum_ux(const ChanDesc& d, const double* A, int n, doub
 // Persistent batched run: workgroup b advances channel order[b] until it has
 // converged or taken max_steps steps in this launch.  Every exit decision is
 // uniform across the workgroup (it depends only on LDS-reduced values and
-// counters), so all waves leave the loop together.
-__global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
+// counters), so all waves leave the loop together.  ONE: every channel has
+// at most one node per thread (the launch checks it); the instance then
+// carries only the fixed-offset node update, which needs far fewer
+// registers than the several-nodes-per-thread loop (no spills in the
+// per-step loop).  MAXT: the largest workgroup the instance serves; with at
+// most 512 threads the compiler may use up to 256 VGPRs (the batch runs one
+// channel per workgroup and few workgroups per CU, so occupancy is not the
+// limit, while spills sit in the per-step loop).
+template <bool ONE, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_batch(BatchArgs a) {
   extern __shared__ double lds[];
   const int c = a.order[blockIdx.x];
   const ChanDesc d = a.ch[c];
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
   ChanState st = a.cs[c];
   __syncthreads();
   int64_t taken = 0;
-  const bool one = n <= (int)blockDim.x;   // one node per thread: sources fixed for the run
+  const bool one = ONE || n <= (int)blockDim.x;   // one node per thread: sources fixed for the run
   const bool mine = (int)threadIdx.x < n;
   NodeSources q{};
   if (one && mine) q = node_sources(d, threadIdx.x);
@@ -190,12 +198,13 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs a) {
         else
           node_step<false, false>(d, q, A, B, n, threadIdx.x);
       }
-    } else if (d.force == 2) {
-      channel_step<true, true>(d, A, B, n);
-    } else if (d.force) {
-      channel_step<true, false>(d, A, B, n);
-    } else {
-      channel_step<false, false>(d, A, B, n);
+    } else if (!ONE) {
+      if (d.force == 2)
+        channel_step<true, true>(d, A, B, n);
+      else if (d.force)
+        channel_step<true, false>(d, A, B, n);
+      else
+        channel_step<false, false>(d, A, B, n);
     }
     __syncthreads();
     double* t = A;
@@ -341,7 +350,19 @@ clb_status upload_order(clb_batch* b) {
 clb_status launch_batch(clb_batch* b, hipStream_t st, double* state, clb::ChanState* cs, int64_t max_steps,
                         int32_t check_every, double tol) {
   clb::BatchArgs a{b->d_desc, b->d_order, state, cs, max_steps, check_every, tol};
-  clb::k_batch<<<b->nch, b->threads, lds_bytes(b, b->threads), st>>>(a);
+  const size_t lds = lds_bytes(b, b->threads);
+  const bool one = b->n_max <= b->threads;
+  if (b->threads <= 512) {
+    if (one)
+      clb::k_batch<true, 512><<<b->nch, b->threads, lds, st>>>(a);
+    else
+      clb::k_batch<false, 512><<<b->nch, b->threads, lds, st>>>(a);
+  } else {
+    if (one)
+      clb::k_batch<true, 1024><<<b->nch, b->threads, lds, st>>>(a);
+    else
+      clb::k_batch<false, 1024><<<b->nch, b->threads, lds, st>>>(a);
+  }
   BATCH_HIP(hipGetLastError());
   return CLB_OK;
 }
@@ -468,8 +489,13 @@ clb_status clb_batch_init(int32_t nch, const clb_params* params, void* d_workspa
   };
   hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
   if (e != hipSuccess) return fail_init(e, "hipStreamCreateWithFlags");
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&clb::k_batch),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(b, 1024));
+  for (const void* k : {reinterpret_cast<const void*>(&clb::k_batch<true, 512>),
+                        reinterpret_cast<const void*>(&clb::k_batch<false, 512>),
+                        reinterpret_cast<const void*>(&clb::k_batch<true, 1024>),
+                        reinterpret_cast<const void*>(&clb::k_batch<false, 1024>)}) {
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(b, 1024));
+    if (e != hipSuccess) break;
+  }
   if (e != hipSuccess) (void)hipGetLastError();   // not needed on every runtime
   e = hipMemcpyAsync(b->d_desc, b->desc.data(), nch * sizeof(clb::ChanDesc), hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return fail_init(e, "upload channel table");

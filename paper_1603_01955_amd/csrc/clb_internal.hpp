@@ -153,6 +153,7 @@ hipError_t launch_pbatch_step2(const PBatchArgs& a, hipStream_t st);
 // before the last kept in LDS); stepk_setup allows their LDS sizes.
 hipError_t stepk_setup();
 hipError_t launch_stepk(const StepArgs& a, int k, hipStream_t st);
+bool periodic_multi_step_ok(const StepArgs& a);   // nx >= 64
 // Two pressure-driven steps in one launch (a.src -> a.dst); only where
 // pressure_two_step_ok holds (ny <= 48, column-kernel path).
 bool pressure_two_step_ok(const StepArgs& a);

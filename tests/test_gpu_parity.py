@@ -337,8 +337,10 @@ def test_graph_replay_identical(graph_steps):
 
 @pytest.mark.parametrize("kw,steps", [
     (dict(nx=77, ny=13, kn=0.5, gx=1e-3, gy=2e-4), 9),            # ragged tiles, odd step count
-    (dict(nx=1, ny=6, kn=0.3, gx=1e-4), 8),                        # every tile column wraps to x = 0
+    (dict(nx=1, ny=6, kn=0.3, gx=1e-4), 8),                        # narrower than a tile: one step per launch
     (dict(nx=6, ny=1, kn=0.3), 5),                                 # both walls on one row
+    (dict(nx=64, ny=1, kn=0.3, gx=1e-4), 5),                       # one tile wide, one row
+    (dict(nx=100, ny=3, kn=0.3, gx=1e-4, cbbsr_shift=0), 7),       # second tile wraps to x = 0
     (dict(nx=130, ny=27, kn=0.1, gx=1e-5, forcing=1, cbbsr_shift=0), 12),
     (dict(nx=1030, ny=40, kn=2.0, gx=1e-6, sigma=0.8), 7),
     (dict(nx=64, ny=13, kn=0.2, gx=1e-4, r=0.0), 4),               # one tile exactly
