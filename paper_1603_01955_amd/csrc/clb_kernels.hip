@@ -4,9 +4,12 @@
 // node (x, y) reads P_i from (x - e_ix, y - e_iy), except where that source
 // lies behind a wall (Eq. 20, half-way walls below row 0 and above row
 // ny - 1) or outside the inlet/outlet (periodic wrap, Section 3.1, or
-// pressure ghost columns, Section 3.2).  The step is one fused kernel:
+// pressure ghost columns, Section 3.2).  A step is one fused kernel:
 // gather -> cascaded collision (Eqs. 4, 6-9, 13) -> store to the other
-// buffer, so each node update moves 72 B in and 72 B out of HBM.
+// buffer, so each node update moves 72 B in and 72 B out of HBM.  The
+// multi-step kernels (K1b periodic, K2e pressure) keep the steps before the
+// last in LDS, computed over a halo of the workgroup's tile, and move about
+// half of that per node update.
 #include "clb_device.hpp"
 #include "clb_gather.hpp"
 #include "clb_internal.hpp"
@@ -86,6 +89,9 @@ constexpr int tile_w() {
   return kTileX + 2 * (K - 1);
 }
 
+// Occupancy target: two steps fit 8 waves per SIMD (64 VGPRs, no spill), so
+// two workgroups share a CU; three or four steps would spill at that target
+// and keep their natural 90-102 VGPRs (4 waves per SIMD).
 template <bool FORCE, bool THIRD, int K, int H>
 __global__ __launch_bounds__(tile_w<K>() * H, K == 2 ? 8 : 4) void k_stepk_periodic(StepArgs a) {
   constexpr int W = tile_w<K>();
@@ -259,7 +265,8 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_step_pressure(S
 
 // ---------------------------------------------------------------------------
 // K2e: two pressure-driven steps in one launch, for channels of at most 64
-// rows.  A workgroup of (CX + 2) x ny threads computes the first step for
+// rows (taken up to 48 rows, see pressure_two_step_ok).  A workgroup of
+// (CX + 2) x ny threads computes the first step for
 // its CX columns and one column on each side (inlet / outlet ghost columns
 // staged from HBM as in K2) and keeps it in LDS; the workgroups holding the
 // first or last column then rebuild the ghost columns from those LDS values,
