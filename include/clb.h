@@ -326,8 +326,16 @@ clb_status clb_pbatch_column_sums(clb_pbatch* b, int32_t ch, double* d_m, double
  * (device array [nx]). */
 clb_status clb_pbatch_pressure_deviation(clb_pbatch* b, int32_t ch, double* d_dp);
 
-/* Copy channel ch's post-collision populations out ([9][ny][nx], device). */
+/* Copy channel ch's post-collision populations out / in ([9][ny][nx],
+ * device).  Setting them leaves the channel's step count and run state
+ * as they are. */
 clb_status clb_pbatch_get_populations(clb_pbatch* b, int32_t ch, double* d_out);
+clb_status clb_pbatch_set_populations(clb_pbatch* b, int32_t ch, const double* d_in);
+
+/* Failure detection: h_ok[nch] = 1 where every population of the channel is
+ * finite, else 0; the call returns CLB_EUNSTABLE if any channel is not.
+ * Synchronises. */
+clb_status clb_pbatch_check_finite(clb_pbatch* b, int32_t* h_ok);
 
 /* Release the host context (synchronises the stream first). */
 clb_status clb_pbatch_destroy(clb_pbatch* b);

@@ -352,6 +352,8 @@ _PBATCH_SIGNATURES = {
                                               ctypes.c_void_p]),
     "clb_pbatch_pressure_deviation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "clb_pbatch_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "clb_pbatch_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "clb_pbatch_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb_pbatch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 _SIGNATURES.update(_PBATCH_SIGNATURES)
@@ -429,6 +431,23 @@ class PressureBatch:
         out = torch.empty(9, self.ny, self.nx, dtype=torch.float64, device=self.device)
         check(lib().clb_pbatch_get_populations(self._h, int(ch), _ptr(out)))
         return out
+
+    def set_populations(self, ch, P):
+        P = P.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(P.shape) != (9, self.ny, self.nx):
+            raise ValueError("populations must have shape (9, ny, nx)")
+        check(lib().clb_pbatch_set_populations(self._h, int(ch), _ptr(P)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def check_finite(self):
+        """Per-channel flags (numpy bool array): True where every population
+        is finite.  Does not raise for non-finite channels."""
+        import numpy as np
+        ok = np.zeros(self.nch, dtype=np.int32)
+        st = lib().clb_pbatch_check_finite(self._h, ok.ctypes.data_as(ctypes.c_void_p))
+        if st not in (CLB_OK, CLB_EUNSTABLE):
+            check(st)
+        return ok.astype(bool)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -92,6 +92,8 @@ __global__ void k_pbatch_reset(PChanState* st, int nch) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+constexpr int kPartials = 1024;   // reduction partials of the finiteness check
+
 struct PBatchLayout {
   size_t buf;     // bytes of one channel buffer
   size_t col;     // bytes of one per-column array
@@ -109,7 +111,8 @@ PBatchLayout pbatch_layout(int32_t nch, const clb_params& p) {
   // two buffers per channel, channel table, run states, mass flows, three
   // per-column diagnostics arrays, row-kernel scratch, running-channel list
   L.total = 2 * (size_t)nch * L.buf + align256(nch * sizeof(PChan)) + align256(nch * sizeof(PChanState)) +
-            align256(nch * sizeof(double)) + 3 * L.col + L.rates + L.ghosts + align256(nch * sizeof(int32_t));
+            align256(nch * sizeof(double)) + 3 * L.col + L.rates + L.ghosts + align256(nch * sizeof(int32_t)) +
+            align256(kPartials * sizeof(double)) + align256(nch * sizeof(double));
   return L;
 }
 
@@ -139,6 +142,8 @@ struct clb_pbatch {
   std::vector<clb::PChanState> h_state;    // mirror of d_state, current after every call
   std::vector<double> h_m;
   int32_t* d_live;                         // indices of the running channels (step launches)
+  double* d_partial;                       // finiteness check: reduction partials and per-channel counts
+  double* d_bad;
   std::vector<int32_t> h_live;             // host copy, read by the last upload
   int32_t n_live;
   int64_t t;                               // steps taken by the channels still running
@@ -338,6 +343,9 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   q += L.rates + L.ghosts;
   a.path = 0;
   b->d_live = reinterpret_cast<int32_t*>(q);
+  q += clb::align256(nch * sizeof(int32_t));
+  b->d_partial = reinterpret_cast<double*>(q);
+  b->d_bad = reinterpret_cast<double*>(q + clb::align256(clb::kPartials * sizeof(double)));
   a.live = b->d_live;
   b->h_live.resize(nch);
   for (int c = 0; c < nch; ++c) b->h_live[c] = c;
@@ -535,6 +543,38 @@ clb_status clb_pbatch_get_populations(clb_pbatch* b, int32_t ch, double* d_out) 
   const size_t bytes = 9 * (size_t)b->args.g.nx * b->args.g.ny * sizeof(double);
   if ((st = clb::check_device_ptr(d_out, bytes, "d_out")) != CLB_OK) return st;
   PBATCH_HIP(clb::launch_export(diag_of(b, ch).src, b->args.g, d_out, b->stream));
+  return CLB_OK;
+}
+
+clb_status clb_pbatch_set_populations(clb_pbatch* b, int32_t ch, const double* d_in) {
+  clb_status st = check_ch(b, ch);
+  if (st != CLB_OK) return st;
+  const size_t bytes = 9 * (size_t)b->args.g.nx * b->args.g.ny * sizeof(double);
+  if ((st = clb::check_device_ptr(d_in, bytes, "d_in")) != CLB_OK) return st;
+  PBATCH_HIP(clb::launch_import(d_in, b->args.g, const_cast<double*>(diag_of(b, ch).src), b->stream));
+  return CLB_OK;
+}
+
+clb_status clb_pbatch_check_finite(clb_pbatch* b, int32_t* h_ok) {
+  if (!b) return clb::perr(CLB_EINVAL, "batch: NULL");
+  if (!h_ok) return clb::perr(CLB_EINVAL, "h_ok: NULL");
+  const clb::Geo& g = b->args.g;
+  size_t nb = ((size_t)g.nx * g.ny + 255) / 256;
+  if (nb > (size_t)clb::kPartials) nb = clb::kPartials;
+  for (int c = 0; c < b->nch; ++c)
+    PBATCH_HIP(clb::launch_nonfinite(diag_of(b, c).src, g, b->d_partial, (int)nb, b->d_bad + c, b->stream));
+  PBATCH_HIP(hipMemcpyAsync(b->h_m.data(), b->d_bad, b->nch * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  PBATCH_HIP(hipStreamSynchronize(b->stream));
+  int bad = 0;
+  for (int c = 0; c < b->nch; ++c) {
+    h_ok[c] = b->h_m[c] == 0.0 ? 1 : 0;
+    bad += !h_ok[c];
+  }
+  if (bad) {
+    char m[128];
+    snprintf(m, sizeof(m), "populations: %d channel(s) with non-finite values", bad);
+    return clb::perr(CLB_EUNSTABLE, m);
+  }
   return CLB_OK;
 }
 

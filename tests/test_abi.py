@@ -172,6 +172,8 @@ def test_pressure_batch_validation(lib):
     assert lib.clb_pbatch_step(None, ctypes.c_int64(1)) == clb.CLB_EINVAL
     assert lib.clb_pbatch_set_steps_per_launch(None, ctypes.c_int32(2)) == clb.CLB_EINVAL
     assert lib.clb_pbatch_set_path(None, ctypes.c_int32(1)) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_check_finite(None, None) == clb.CLB_EINVAL
+    assert lib.clb_pbatch_set_populations(None, ctypes.c_int32(0), None) == clb.CLB_EINVAL
     assert lib.clb_pbatch_run(None, ctypes.c_int64(10), ctypes.c_int32(0), ctypes.c_double(0.0), None,
                               None) == clb.CLB_EINVAL
     assert lib.clb_pbatch_massflow(None, None, None) == clb.CLB_EINVAL

@@ -188,6 +188,31 @@ def test_step_and_odd_chunks_keep_buffers_straight():
     pb.close()
 
 
+def test_set_populations_and_failure_detection():
+    """A channel given the reference's state continues like the reference; a
+    channel given a non-finite value is reported by check_finite and stays
+    confined to itself (channels are independent)."""
+    PressureBatch, _, clb = _mods()
+    nx, ny = 60, 8
+    specs = _specs(3)
+    pb = PressureBatch([_gpu_params(clb, nx, ny, s) for s in specs])
+    pb.step(3)
+    assert pb.check_finite().all()
+    prm, P0 = _ref(nx, ny, specs[0])
+    Pmid = C.run(P0, prm, 5)
+    pb.set_populations(0, torch.from_numpy(Pmid))
+    bad = pb.populations(1).clone()
+    bad[4, 3, 7] = float("nan")
+    pb.set_populations(1, bad)
+    assert pb.check_finite().tolist() == [True, False, True]
+    pb.step(4)
+    assert pb.check_finite().tolist() == [True, False, True]
+    P = pb.populations(0).cpu().numpy()
+    Pref = C.run(Pmid, prm, 4)
+    assert np.max(np.abs(P - Pref)) <= 1e-10 * np.max(np.abs(Pref))
+    pb.close()
+
+
 def test_zero_steps_and_converged_channels_do_not_move():
     PressureBatch, _, clb = _mods()
     params = [_gpu_params(clb, 40, 4, s) for s in _specs(2)]
