@@ -254,6 +254,10 @@ clb_status clb_batch_set_populations(clb_batch* b, int32_t ch, const double* d_i
 /* Forget step counts and convergence history (the populations are kept). */
 clb_status clb_batch_reset(clb_batch* b);
 
+/* Failure detection: h_ok[nch] = 1 where every population of the channel is
+ * finite, else 0; CLB_EUNSTABLE if any channel is not.  Synchronises. */
+clb_status clb_batch_check_finite(clb_batch* b, int32_t* h_ok);
+
 /* Release the host context (synchronises the stream first). */
 clb_status clb_batch_destroy(clb_batch* b);
 

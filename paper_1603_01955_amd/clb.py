@@ -254,6 +254,7 @@ _BATCH_SIGNATURES = {
     "clb_batch_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "clb_batch_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "clb_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "clb_batch_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 _SIGNATURES.update(_BATCH_SIGNATURES)
@@ -324,6 +325,16 @@ class Batch:
 
     def reset(self):
         check(lib().clb_batch_reset(self._h))
+
+    def check_finite(self):
+        """Per-channel flags (numpy bool array): True where every population
+        is finite.  Does not raise for non-finite channels."""
+        import numpy as np
+        ok = np.zeros(self.nch, dtype=np.int32)
+        st = lib().clb_batch_check_finite(self._h, ok.ctypes.data_as(ctypes.c_void_p))
+        if st not in (CLB_OK, CLB_EUNSTABLE):
+            check(st)
+        return ok.astype(bool)
 
     def close(self):
         if getattr(self, "_h", None):

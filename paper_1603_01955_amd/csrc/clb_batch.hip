@@ -270,6 +270,19 @@ __global__ __launch_bounds__(256) void k_batch_sum_ux(const ChanDesc* ch, const 
   out[blockIdx.x] = channel_sum_ux(d, state + d.off, n, red);
 }
 
+// Non-finite values among each channel's populations, counted by one
+// workgroup of 256 threads per channel (fixed order).
+__global__ __launch_bounds__(256) void k_batch_nonfinite(const ChanDesc* ch, const double* state, double* out) {
+  __shared__ double red[256];
+  const ChanDesc d = ch[blockIdx.x];
+  const int n9 = 9 * d.nx * d.ny;
+  const double* p = state + d.off;
+  double cnt = 0.0;
+  for (int k = threadIdx.x; k < n9; k += 256) cnt += (p[k] - p[k] == 0.0) ? 0.0 : 1.0;   // NaN, inf
+  const double s = block_sum(cnt, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct BatchLayout {
@@ -636,6 +649,22 @@ clb_status clb_batch_flow_rate(clb_batch* b, double* h_Q) {
     // Section 3.1: Q = (int u_x dy) / (F_x H^2 sqrt(RT/2) / p), per column
     h_Q[c] = (b->host_sums[c] / p.nx) * std::sqrt(6.0) / (3.0 * p.gx * H * H);
   }
+  return CLB_OK;
+}
+
+clb_status clb_batch_check_finite(clb_batch* b, int32_t* h_ok) {
+  if (!b) return clb::err(CLB_EINVAL, "batch: NULL");
+  if (!h_ok) return clb::err(CLB_EINVAL, "h_ok: NULL");
+  clb::k_batch_nonfinite<<<b->nch, 256, 0, b->stream>>>(b->d_desc, b->state, b->sums);
+  BATCH_HIP(hipGetLastError());
+  BATCH_HIP(hipMemcpyAsync(b->host_sums.data(), b->sums, b->nch * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BATCH_HIP(hipStreamSynchronize(b->stream));
+  int bad = 0;
+  for (int c = 0; c < b->nch; ++c) {
+    h_ok[c] = b->host_sums[c] == 0.0 ? 1 : 0;
+    bad += !h_ok[c];
+  }
+  if (bad) return clb::err(CLB_EUNSTABLE, "populations: non-finite values in at least one channel");
   return CLB_OK;
 }
 

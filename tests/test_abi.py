@@ -140,6 +140,7 @@ def test_batch_validation(lib):
     assert out.value is None
     assert lib.clb_batch_run(None, ctypes.c_int64(10), ctypes.c_int32(0), ctypes.c_double(0.0), None,
                              None) == clb.CLB_EINVAL
+    assert lib.clb_batch_check_finite(None, None) == clb.CLB_EINVAL
     assert lib.clb_batch_destroy(None) == clb.CLB_EINVAL
 
 

@@ -133,6 +133,23 @@ def test_kn_sweep_with_third_order_forcing_matches_continuum_slip():
     assert np.max(np.abs(Q / Qref - 1)) <= 1e-6
 
 
+def test_batch_failure_detection():
+    """A planted non-finite value is reported for its channel only, also
+    after further steps (channels are independent)."""
+    Batch, _, clb = _mods()
+    params = [clb.make_params(**kw) for kw in CHANNELS[:3]]
+    b = Batch(params)
+    b.run(10)
+    assert b.check_finite().all()
+    bad = b.populations(1).clone()
+    bad[2, 5, 3] = float("inf")
+    b.set_populations(1, bad)
+    assert b.check_finite().tolist() == [True, False, True]
+    b.run(10)
+    assert b.check_finite().tolist() == [True, False, True]
+    b.close()
+
+
 def test_batch_rejects_bad_channels():
     Batch, _, clb = _mods()
     with pytest.raises(clb.ClbError):
