@@ -306,6 +306,23 @@ def test_full_size_periodic_sampled():
     s.close()
 
 
+def test_full_size_two_steps_per_launch_equal_one_step():
+    """The benchmarked launch configuration itself: 32768 x 2048, two steps
+    per launch (the default, as bench.py times it) against one step per
+    launch -- whose single steps the test above pins to the reference at
+    this size -- after 21 steps (ten two-step launches and a one-step
+    remainder): every population equal bit for bit."""
+    kw = dict(nx=32768, ny=2048, kn=1.0, gx=1e-7, init="perturbed", init_amp=1e-4, seed=12345)
+    two = _solver(**kw)
+    two.step(21)
+    one = _solver(**kw)
+    one.set_steps_per_launch(1)
+    one.step(21)
+    assert torch.equal(two.populations(), one.populations())
+    two.close()
+    one.close()
+
+
 def test_deterministic_and_resumable():
     kw = dict(nx=333, ny=12, kn=0.8, gx=1e-4, init="perturbed", init_amp=1e-3, seed=7)
     a, _ = _gpu_run(kw, 50)
