@@ -361,6 +361,7 @@ def test_graph_replay_identical(graph_steps):
     (dict(nx=130, ny=27, kn=0.1, gx=1e-5, forcing=1, cbbsr_shift=0), 12),
     (dict(nx=1030, ny=40, kn=2.0, gx=1e-6, sigma=0.8), 7),
     (dict(nx=64, ny=13, kn=0.2, gx=1e-4, r=0.0), 4),               # one tile exactly
+    (dict(nx=4096, ny=300, kn=0.4, gx=1e-5, gy=-3e-6), 5),         # runs of several passes, ragged last run
     (dict(nx=2000, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0), 9),           # pressure: 8-column tiles
     (dict(nx=4000, ny=40, xbc="pressure", kn=0.2, p_ratio=1.8, sigma=0.93), 6),  # 16 columns
     (dict(nx=17, ny=3, xbc="pressure", kn=0.3, p_ratio=1.5, cbbsr_shift=0), 7),  # two ragged workgroups
