@@ -28,6 +28,12 @@ FLAGS = [
 ]
 
 
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+# roctx ranges around the entry points (rocprofv3 --marker-trace)
+LINK = ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+
+
 def hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -52,7 +58,7 @@ def source_hash(names=STEP_SOURCES):
 def build(verbose=False, extra_flags=()):
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-x", "hip"] + FLAGS + list(extra_flags) + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs
+    cmd = [hipcc(), "-x", "hip"] + FLAGS + list(extra_flags) + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs + LINK
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -35,6 +35,7 @@
 #include "clb_device.hpp"
 #include "clb_gather.hpp"
 #include "clb_internal.hpp"
+#include "clb_trace.hpp"
 
 namespace clb {
 namespace {
@@ -845,6 +846,7 @@ clb_status clb_adjoint_init(const clb_params* p, int32_t T, int32_t K, void* d_w
 }
 
 clb_status clb_adjoint_forward(clb_adjoint* a, const double* d_dp_target, double m_target, double* h_loss) {
+  const clb::TraceRange trace("clb_adjoint_forward");
   if (!a) return clb::set_error(CLB_EINVAL, "adjoint: NULL");
   clb_status st = clb::check_device_ptr(d_dp_target, (size_t)a->p.nx * sizeof(double), "d_dp_target");
   if (st != CLB_OK) return st;
@@ -888,6 +890,7 @@ clb_status clb_adjoint_forward(clb_adjoint* a, const double* d_dp_target, double
 }
 
 clb_status clb_adjoint_backward(clb_adjoint* a, double* h_grad) {
+  const clb::TraceRange trace("clb_adjoint_backward");
   if (!a) return clb::set_error(CLB_EINVAL, "adjoint: NULL");
   if (!h_grad) return clb::set_error(CLB_EINVAL, "h_grad: NULL");
   if (!a->forward_done) return clb::set_error(CLB_ESTATE, "clb_adjoint_backward: run clb_adjoint_forward first");

@@ -14,6 +14,7 @@
 
 #include "clb.h"
 #include "clb_internal.hpp"
+#include "clb_trace.hpp"
 
 namespace {
 
@@ -278,6 +279,7 @@ clb_status clb_workspace_size(const clb_params* p, size_t* bytes) {
 }
 
 clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* hip_stream, clb_ctx** out) {
+  const clb::TraceRange trace("clb_init");
   if (!out) return fail(CLB_EINVAL, "out: NULL");
   *out = nullptr;
   clb_derived d;
@@ -406,6 +408,7 @@ clb_status record_graph(clb_ctx* c) {
 }  // namespace
 
 clb_status clb_step(clb_ctx* c, int64_t nsteps) {
+  const clb::TraceRange trace("clb_step");
   clb_status st = check_ctx(c);
   if (st != CLB_OK) return st;
   if (nsteps < 0) return fail(CLB_EINVAL, "nsteps: must be >= 0");

@@ -22,6 +22,7 @@
 #include "clb_device.hpp"
 #include "clb_gather.hpp"
 #include "clb_internal.hpp"
+#include "clb_trace.hpp"
 
 namespace clb {
 namespace {
@@ -406,6 +407,7 @@ clb_status clb_batch_workspace_size(int32_t nch, const clb_params* params, size_
 
 clb_status clb_batch_init(int32_t nch, const clb_params* params, void* d_workspace, size_t bytes,
                           void* hip_stream, clb_batch** out) {
+  const clb::TraceRange trace("clb_batch_init");
   if (!out) return clb::err(CLB_EINVAL, "out: NULL");
   *out = nullptr;
   size_t need = 0;
@@ -595,6 +597,7 @@ clb_status clb_batch_tune(clb_batch* b, int32_t probe_steps, int32_t* h_threads,
 
 clb_status clb_batch_run(clb_batch* b, int64_t max_steps, int32_t check_every, double tol, int64_t* h_steps,
                          int32_t* h_converged) {
+  const clb::TraceRange trace("clb_batch_run");
   if (!b) return clb::err(CLB_EINVAL, "batch: NULL");
   if (max_steps < 0) return clb::err(CLB_EINVAL, "max_steps: must be >= 0");
   if (check_every < 0) return clb::err(CLB_EINVAL, "check_every: must be >= 0");

@@ -23,6 +23,7 @@
 #include "clb_device.hpp"
 #include "clb_gather.hpp"
 #include "clb_internal.hpp"
+#include "clb_trace.hpp"
 
 namespace clb {
 namespace {
@@ -279,6 +280,7 @@ clb_status clb_pbatch_workspace_size(int32_t nch, const clb_params* params, size
 
 clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_workspace, size_t bytes, void* hip_stream,
                            clb_pbatch** out) {
+  const clb::TraceRange trace("clb_pbatch_init");
   if (!out) return clb::perr(CLB_EINVAL, "out: NULL");
   *out = nullptr;
   size_t need = 0;
@@ -399,6 +401,7 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
 }
 
 clb_status clb_pbatch_step(clb_pbatch* b, int64_t nsteps) {
+  const clb::TraceRange trace("clb_pbatch_step");
   if (!b) return clb::perr(CLB_EINVAL, "batch: NULL");
   if (nsteps < 0) return clb::perr(CLB_EINVAL, "nsteps: must be >= 0");
   if (nsteps == 0) return CLB_OK;
@@ -415,6 +418,7 @@ clb_status clb_pbatch_step(clb_pbatch* b, int64_t nsteps) {
 
 clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every, double tol, int64_t* h_steps,
                           int32_t* h_converged) {
+  const clb::TraceRange trace("clb_pbatch_run");
   if (!b) return clb::perr(CLB_EINVAL, "batch: NULL");
   if (max_steps < 0) return clb::perr(CLB_EINVAL, "max_steps: must be >= 0");
   if (check_every < 0 || check_every > 100000) return clb::perr(CLB_EINVAL, "check_every: must lie in [0, 100000]");

@@ -53,7 +53,7 @@ def test_host_code_under_asan_ubsan(tmp_path):
     _run(cmds, str(tmp_path))
 
     lib = str(tmp_path / "libclb_san.so")
-    _run([[hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + SAN + objs + ["-o", lib]], str(tmp_path))
+    _run([[hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + SAN + objs + ["-o", lib] + B.LINK], str(tmp_path))
 
     exe = str(tmp_path / "host_checks")
     _run([[CLANG, "-std=c++17", "-g", "-O1", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
