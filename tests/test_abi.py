@@ -75,6 +75,19 @@ def test_workspace_size_arithmetic(lib):
         assert n < 2 * 72 * padded * ny + 6 * 8 * nx + 144 * ny + 64 * 1024
 
 
+def test_largest_grid(lib):
+    """The size limit sits where one launch can no longer enumerate the padded
+    nodes in 64-thread blocks (2^37 padded nodes): one row less is accepted
+    and its workspace size does not overflow."""
+    n = ctypes.c_size_t()
+    p = clb.make_params(1 << 20, (1 << 17) - 1)
+    assert lib.clb_workspace_size(ctypes.byref(p), ctypes.byref(n)) == clb.CLB_OK
+    assert n.value >= 2 * 72 * (1 << 20) * ((1 << 17) - 1)
+    p = clb.make_params(1 << 20, 1 << 17)
+    assert lib.clb_workspace_size(ctypes.byref(p), ctypes.byref(n)) == clb.CLB_EINVAL
+    assert "too large" in lib.clb_last_error().decode()
+
+
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("ny", -1), ("xbc", 7), ("init", 9), ("kn", 0.0), ("kn", -1.0), ("kn", math.inf),
     ("a", -0.1), ("sigma", 0.0), ("sigma", 2.5), ("A2", -1.0), ("r", 1.5), ("s3", 2.0),
