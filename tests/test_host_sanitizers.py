@@ -3,7 +3,7 @@
 Builds a copy of the C ABI library with the host side instrumented
 (``-Xarch_host`` before each ``-fsanitize=``; device code is compiled as
 usual and never runs here) and links ``host_checks.cpp`` against it.  That
-driver calls every entry point family with invalid parameters and null
+program calls every entry point family with invalid parameters and null
 arguments, all of which return before any device work, so the whole run
 needs no GPU.  A sanitizer report or a failed expectation fails the test.
 """
