@@ -27,7 +27,7 @@ def _gpu_params(prm, r_free=True):
     A1, r = C.resolved(prm)
     return clb.make_params(prm.nx, prm.ny, xbc="pressure", kn=prm.kn, p_ratio=prm.p_ratio, a=prm.a,
                            A1=A1, A2=prm.A2, r=r if r_free else None, sigma=prm.sigma,
-                           cbbsr_shift=prm.cbbsr_shift)
+                           cbbsr_shift=prm.cbbsr_shift, tq_den=prm.tq_den, rho_out=prm.rho_out)
 
 
 def _adjoint(prm, T, K, r_free=True):
@@ -35,11 +35,13 @@ def _adjoint(prm, T, K, r_free=True):
     return Adjoint(_gpu_params(prm, r_free), T, K)
 
 
-@pytest.mark.parametrize("nx,ny,shift", [(48, 6, 1), (130, 5, 1), (20, 2, 1), (33, 4, 0), (2, 3, 1)])
-def test_vjp_step_dot_product(nx, ny, shift):
+@pytest.mark.parametrize("nx,ny,shift,extra", [(48, 6, 1, {}), (130, 5, 1, {}), (20, 2, 1, {}), (33, 4, 0, {}),
+                                               (2, 3, 1, {}),
+                                               (40, 7, 1, dict(tq_den=24.0, A2=0.3, sigma=0.8, rho_out=1.2))])
+def test_vjp_step_dot_product(nx, ny, shift, extra):
     """<lambda, J v> (J v by complex step of the reference step) equals
     <J^T lambda, v> from the GPU reverse step; same for the parameters."""
-    prm = C.Params(nx=nx, ny=ny, xbc="pressure", kn=0.2, p_ratio=1.7, cbbsr_shift=shift)
+    prm = C.Params(nx=nx, ny=ny, xbc="pressure", kn=0.2, p_ratio=1.7, cbbsr_shift=shift, **extra)
     A1, r = C.resolved(prm)
     prm = dataclasses.replace(prm, A1=A1, r=r)
     P = C.init_linear_rho(prm) + uniform_populations(nx, ny, seed=31, lo=-5e-3, hi=5e-3)
