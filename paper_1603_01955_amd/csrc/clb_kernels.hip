@@ -69,6 +69,12 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 // here equal K one-step launches bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int kTileX = 64;   // tile columns
+// Tiles are handed out in strips of kStripBands tile rows, each strip walked
+// column by column: the tiles an XCD runs at the same time (consecutive
+// logical blocks) then sit above and beside each other and share their halo
+// rows and columns in that XCD's L2.  In row-major order the rows shared
+// with the next band were read from HBM twice.
+constexpr int kStripBands = 16;
 
 // Populations of a tile region in LDS, [9][h][w], addressed with global
 // (unwrapped) coordinates.
@@ -98,8 +104,12 @@ __global__ __launch_bounds__(tile_w<K>() * H, K == 2 ? 8 : 4) void k_stepk_perio
   extern __shared__ double s1[];   // [9][H][W]
   const int nx = a.g.nx, ny = a.g.ny;
   const int ntx = (nx + kTileX - 1) / kTileX;
+  const int nty = (ny + H - 2 * K + 1) / (H - 2 * (K - 1));
   const int b = logical_block(a.xcd_remap);
-  const int by = b / ntx, bx = b - by * ntx;
+  const int strip = b / (ntx * kStripBands);
+  const int rb = b - strip * (ntx * kStripBands);
+  const int bands = min(kStripBands, nty - strip * kStripBands);   // the last strip may be shorter
+  const int bx = rb / bands, by = strip * kStripBands + (rb - bx * bands);
   const int x0 = bx * kTileX - (K - 1), y0 = by * (H - 2 * (K - 1)) - (K - 1);   // LDS (0, 0)
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x = x0 + lx, y = y0 + ly;
