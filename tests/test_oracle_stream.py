@@ -124,6 +124,62 @@ def test_pressure_ghost_density_is_linear():
     assert np.allclose(0.5 * (g_out.sum(0) + P[:, :, -1].sum(0)), 1.0, rtol=0, atol=1e-15)
 
 
+def _second_moments(f):
+    """Pxx, Pyy, Pxy of populations f (9, ny), straight from Eq. (1)'s velocities."""
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)[:, None]
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)[:, None]
+    return (ex * ex * f).sum(0), (ey * ey * f).sum(0), (ex * ey * f).sum(0)
+
+
+def test_pressure_ghost_velocity_is_extrapolated():
+    """The ghost column's velocity (its own first moments over its density)
+    continues the two adjacent columns linearly: u_g = 2 u_1 - u_2.  The
+    copied non-equilibrium part carries no mass or momentum, so this holds
+    for an arbitrary state."""
+    prm = C.Params(nx=6, ny=4, xbc="pressure", kn=0.2, p_ratio=1.6, rho_out=1.1)
+    P = uniform_populations(6, 4, 29, lo=0.05, hi=0.2)
+    g_in, g_out = C.ghost_columns(P, prm)
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)[:, None]
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)[:, None]
+
+    def vel(f):
+        return (ex * f).sum(0) / f.sum(0), (ey * f).sum(0) / f.sum(0)
+    for g, c1, c2 in ((g_in, 0, 1), (g_out, -1, -2)):
+        ug, vg = vel(g)
+        u1, v1 = vel(P[:, :, c1])
+        u2, v2 = vel(P[:, :, c2])
+        assert np.allclose(ug, 2 * u1 - u2, rtol=0, atol=1e-14)
+        assert np.allclose(vg, 2 * v1 - v2, rtol=0, atol=1e-14)
+
+
+def test_pressure_ghost_copies_the_nonequilibrium_stress():
+    """The ghost column keeps the adjacent column's non-equilibrium part: its
+    second moments minus those of the D2Q9 equilibrium at its own density
+    and velocity (rho/3 + rho u u, from Eq. 11's moments) equal the same
+    difference for the adjacent column; an equilibrium neighbour gives an
+    equilibrium ghost."""
+    prm = C.Params(nx=5, ny=3, xbc="pressure", kn=0.2, p_ratio=1.8, rho_out=1.0)
+    P = uniform_populations(5, 3, 30, lo=0.05, hi=0.2)
+    g_in, g_out = C.ghost_columns(P, prm)
+
+    def neq_stress(f):
+        rho = f.sum(0)
+        ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)[:, None]
+        ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)[:, None]
+        u, v = (ex * f).sum(0) / rho, (ey * f).sum(0) / rho
+        pxx, pyy, pxy = _second_moments(f)
+        return pxx - (rho / 3 + rho * u * u), pyy - (rho / 3 + rho * v * v), pxy - rho * u * v
+    for g, c1 in ((g_in, 0), (g_out, -1)):
+        for a, b in zip(neq_stress(g), neq_stress(P[:, :, c1])):
+            assert np.allclose(a, b, rtol=0, atol=1e-14)
+    # equilibrium neighbours: the ghost is itself an equilibrium (no stress left)
+    Q = C.init_linear_rho(prm)
+    g_in, g_out = C.ghost_columns(Q, prm)
+    for g in (g_in, g_out):
+        for a in neq_stress(g):
+            assert np.max(np.abs(a)) <= 1e-15
+
+
 def test_perturbed_start_counter_layout():
     """The seeded start depends only on (seed, node, direction)."""
     prm = C.Params(nx=5, ny=3)
