@@ -117,3 +117,34 @@ def test_pressure_driven_channel_carries_the_eq19_slip():
     m18, _ = A.lubrication_profile(200, 4, 0.5, 1.8, 2.0, A1, 0.55, nsub=2, c2=18.0)
     assert abs(m / m12 - 1.0) < 0.01
     assert m / m18 < 0.95
+
+
+@pytest.mark.parametrize("ny", [5, 6])
+def test_local_knudsen_number_follows_the_centre_line(ny):
+    """Section 3.2: the local Kn scales inversely with the centre-line
+    pressure.  A column whose centre-line density is k rho_out relaxes with
+    the rates a periodic channel of Kn = Kn_out / k has, whatever the density
+    of the rows off the centre line."""
+    prm = C.Params(nx=4, ny=ny, xbc="pressure", kn=0.3, p_ratio=1.5, rho_out=1.1)
+    ks = np.array([0.7, 1.0, 1.3, 2.1])
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(0.5, 2.0, size=(ny, 4))        # off-centre rows: anything
+    mid = [ny // 2] if ny % 2 else [ny // 2 - 1, ny // 2]
+    if ny % 2:
+        rho[mid[0]] = ks * prm.rho_out
+    else:                                            # the mean of the two middle rows counts
+        rho[mid[0]] = ks * prm.rho_out * 0.8
+        rho[mid[1]] = ks * prm.rho_out * 1.2
+    pre = np.stack([w * rho for w in (4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36)])
+    s_nu, s_q = C.step_rates(pre, prm)
+    for x, k in enumerate(ks):
+        per = C.Params(nx=4, ny=ny, kn=prm.kn / k)
+        nu_ref, q_ref = C.step_rates(pre, per)
+        assert abs(s_nu[x] - nu_ref) <= 1e-15 and abs(s_q[x] - q_ref) <= 1e-15
+    # changing only off-centre rows leaves the rates alone
+    rho2 = rho.copy()
+    off = [y for y in range(ny) if y not in mid]
+    rho2[off] *= 1.7
+    pre2 = np.stack([w * rho2 for w in (4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36)])
+    s_nu2, s_q2 = C.step_rates(pre2, prm)
+    assert np.array_equal(s_nu, s_nu2) and np.array_equal(s_q, s_q2)
