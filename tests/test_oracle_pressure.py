@@ -148,3 +148,26 @@ def test_local_knudsen_number_follows_the_centre_line(ny):
     pre2 = np.stack([w * rho2 for w in (4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36)])
     s_nu2, s_q2 = C.step_rates(pre2, prm)
     assert np.array_equal(s_nu, s_nu2) and np.array_equal(s_q, s_q2)
+
+
+@pytest.mark.parametrize("ny", [4, 5])
+def test_linear_rest_state_has_no_pressure_deviation(ny):
+    """Closed-form special case: at rest with the density linear between
+    rho_in on the inlet plane and rho_out on the outlet plane, streaming keeps
+    every column's density (the ghost columns continue the line), so the
+    centre-line pressure is the linear profile itself: delta p(x) = 0 at
+    every column, the edge columns included.  The pull of Eq. (5) gives the
+    pre-collision state the momentum -(1/3) d rho/dx away from the walls,
+    the same in every column, and so the mass flow m(x) is uniform."""
+    prm = C.Params(nx=10, ny=ny, xbc="pressure", kn=0.2, p_ratio=1.7, rho_out=1.2)
+    P = C.init_linear_rho(prm)
+    rho0 = P.sum(0)[0]
+    x = np.arange(10) + 0.5                          # node centres; planes at 0 and 10
+    assert np.allclose(rho0, 1.7 * 1.2 + (1.2 - 1.7 * 1.2) * x / 10, rtol=0, atol=1e-15)
+    dp = C.pressure_deviation(P, prm)
+    assert np.max(np.abs(dp)) <= 1e-14
+    rho, ux, _ = C.moments(P, prm)
+    slope = (1.2 - 1.7 * 1.2) / 10
+    assert np.allclose((rho * ux)[1:-1], -slope / 3, rtol=0, atol=1e-15)
+    m = C.column_sums(P, prm)[0]
+    assert m.min() > 0 and np.max(np.abs(m - m[0])) <= 1e-14
