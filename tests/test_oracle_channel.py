@@ -52,6 +52,44 @@ def test_section3_parameters():
     assert round(2 * pv["fig1_k_max"] / sqrt(pi), 4) == pv["fig1_kn_last"]
 
 
+# A1 = B1 sigma_v with B1 = 1 - 0.1817 sigma (Section 3) and
+# sigma_v = (2 - sigma)/sigma (Section 2.3), worked out by hand as exact
+# fractions, e.g. sigma = 0.93: (0.831019 x 1.07)/0.93 = 88919033/93000000;
+# r = 1/(1 + A1 sqrt(pi/6)) (Eq. 21) to 12 digits.
+SLIP_LITERALS = [
+    # sigma, A1, r
+    (0.93, 0.956118634408602, 0.591069422151),   # the mass-flow study's TMAC (Section 3.2)
+    (0.7, 1.62093285714286, 0.460212543396),
+    (1.5, 0.242483333333333, 0.850729877251),
+]
+
+
+@pytest.mark.parametrize("sigma,A1,r", SLIP_LITERALS)
+def test_slip_coefficients_away_from_full_accommodation(sigma, A1, r):
+    """At sigma = 1 both sigma_v = 1 and B1 = 0.8183 hide a wrong sigma
+    dependence; these TMACs do not."""
+    assert abs(C.slip_A1(sigma) - A1) <= 1e-13
+    assert abs(C.bounce_fraction(C.slip_A1(sigma)) - r) <= 1e-11
+    prm = C.Params(nx=1, ny=8, sigma=sigma)
+    got_A1, got_r = C.resolved(prm)
+    assert abs(got_A1 - A1) <= 1e-13 and abs(got_r - r) <= 1e-11
+
+
+@pytest.mark.parametrize("ny,kn", [(16, 0.1), (12, 0.5)])
+def test_continuum_slip_at_tmac_093(ny, kn):
+    """With sigma = 0.93 and 24 in Eq. (21), the steady force-driven channel
+    of the reference carries the continuum slip law of Eq. (19): its
+    sum_y u_x equals the second-order slip Poiseuille flow whose A1 = B1
+    sigma_v is written out here from sigma, not taken from the reference."""
+    sigma = 0.93
+    A1 = (1.0 - 0.1817 * sigma) * ((2.0 - sigma) / sigma)
+    prm = C.Params(nx=1, ny=ny, kn=kn, gx=1e-6, sigma=sigma, tq_den=24.0)
+    P, _ = _steady(prm)
+    _, ux, _ = C.moments(P, prm)
+    cont = A.continuum_sum_u(ny, kn, 2.0, A1, 0.55, 1e-6)
+    assert abs(ux[:, 0].sum() / cont - 1) <= 1e-6
+
+
 @pytest.fixture(scope="module")
 def channel_4x32():
     """Force-driven periodic channel 4 x 32, Kn = 0.1, g = 1e-6, 20,000 steps."""
@@ -138,6 +176,23 @@ def test_no_slip_magic_combination():
     y = np.arange(16) + 0.5
     ref = 1.5e-6 / tt * y * (16 - y)
     assert np.max(np.abs(ux[:, 0] - ref)) <= 1e-6 * ref.max()
+
+
+@pytest.mark.parametrize("ny,kn", [(16, 0.1), (9, 0.4)])
+def test_flow_rate_scale_on_the_no_slip_parabola(ny, kn):
+    """The normalisation of Q (Section 3.1) on a flow known in closed form.
+    Q = int u dy / (F_x H^2 sqrt(RT/2) / p) with F_x = rho0 g, RT = 1/3 and
+    p = rho0/3 is sqrt(6) int u dy / (3 g H^2).  With r = 1 and the magic
+    combination the steady profile is the no-slip parabola u = g y (H - y)/(2 nu)
+    with nu = tt/3 (Eq. 14) and tt = sqrt(6/pi) H k_e, k_e = Kn/(1 + a Kn)
+    (Eqs. 15-18).  Its midpoint sum over the H rows at y = j + 1/2 is
+    (g/(2 nu)) (H^3/6 + H/12), so Q = (sqrt(pi)/(12 k_e)) (1 + 1/(2 H^2))."""
+    a = 2.0
+    prm = C.Params(nx=1, ny=ny, kn=kn, a=a, gx=1e-6, r=1.0, A2=0.0, tq_den=24.0)
+    P, _ = _steady(prm)
+    ke = kn / (1.0 + a * kn)
+    ref = sqrt(pi) / (12.0 * ke) * (1.0 + 1.0 / (2.0 * ny * ny))
+    assert abs(C.flow_rate_Q(P, prm) / ref - 1) <= 1e-6
 
 
 @pytest.mark.parametrize("kn", [0.3, 0.87, 3.0])
