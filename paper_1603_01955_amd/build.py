@@ -21,11 +21,14 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
-    # no packed FP32 instructions in device code
-    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
 ]
+
+# Device pass only: no packed FP32 instructions in device code.  The host
+# pass does not know the feature (and would warn for every source), so each
+# source is compiled in two passes: the device code object bundle first,
+# then the host object with that bundle embedded.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
@@ -55,18 +58,39 @@ def source_hash(names=STEP_SOURCES):
     return h.hexdigest()[:16]
 
 
-def build(verbose=False, extra_flags=()):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-x", "hip"] + FLAGS + list(extra_flags) + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs + LINK
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building %s" % LIB)
-    if verbose and res.stderr.strip():
+        raise RuntimeError("hipcc failed: %s" % " ".join(cmd[-3:]))
+    if res.stderr.strip():
         sys.stderr.write(res.stderr)
+
+
+def _compile(src, objdir, extra_flags, verbose):
+    """Device pass (gfx950 code object bundle), then the host object that
+    embeds it."""
+    base = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0])
+    inc = ["-I", INCLUDE, "-I", CSRC]
+    common = [hipcc(), "-x", "hip"] + FLAGS + list(extra_flags) + inc
+    _run(common + DEVICE_FLAGS + ["--offload-device-only", "-c", src, "-o", base + ".hipfb"], verbose)
+    _run(common + ["--offload-host-only", "-Xclang", "-fcuda-include-gpubinary", "-Xclang", base + ".hipfb",
+                   "-c", src, "-o", base + ".o"], verbose)
+    return base + ".o"
+
+
+def build(verbose=False, extra_flags=()):
+    import concurrent.futures
+    import tempfile
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    with tempfile.TemporaryDirectory(prefix="clb_build_") as objdir:
+        workers = max(1, min(len(srcs), os.cpu_count() or 1, 16))
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            objs = list(ex.map(lambda s: _compile(s, objdir, extra_flags, verbose), srcs))
+        tmp = LIB + ".tmp%d" % os.getpid()
+        _run([hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs + LINK, verbose)
     os.replace(tmp, LIB)
     return LIB
 
