@@ -39,6 +39,12 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden symbol visibility; the declarations of
+ * this header are its exported interface. */
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
 typedef enum clb_status {
   CLB_OK = 0,
   CLB_EINVAL = -1,     /* invalid argument; the message names the field      */
@@ -127,7 +133,8 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes,
                     void* hip_stream, clb_ctx** out);
 
 /* Advance nsteps >= 0 time steps (stream + boundaries + collision, Eqs. 4-5,
- * 20).  Asynchronous. */
+ * 20).  Asynchronous, unless checks are switched on (clb_set_check_every):
+ * then CLB_EUNSTABLE reports non-finite populations at a check. */
 clb_status clb_step(clb_ctx* c, int64_t nsteps);
 
 /* Number of steps taken since clb_init / the last clb_set_populations. */
@@ -169,6 +176,17 @@ clb_status clb_set_populations(clb_ctx* c, const double* d_in);
  * call returns CLB_EUNSTABLE.  Synchronises. */
 clb_status clb_check_finite(clb_ctx* c, int32_t* h_ok);
 
+/* Failure detection inside clb_step (the paper has none; an auxiliary check
+ * for long runs): with check_every > 0, clb_step stops at every step count
+ * that is a multiple of check_every (counted since clb_init or the last
+ * clb_set_populations), counts the non-finite populations of the state, and
+ * returns CLB_EUNSTABLE at the first check that finds any, leaving the
+ * state and the step counter at that step (steps after it are not taken).
+ * Each check synchronises the stream; between checks clb_step stays
+ * asynchronous.  0 (default) switches the checks off.  CLB_EINVAL if
+ * check_every < 0. */
+clb_status clb_set_check_every(clb_ctx* c, int64_t check_every);
+
 /* Step-kernel launch shape (tuning; defaults are chosen by measurement):
  * block_x threads per row segment (64, 128, 256, 512 or 1024) and
  * xcd_remap = 1 to map consecutive row segments onto the same XCD. */
@@ -204,6 +222,7 @@ clb_status clb_set_graph_steps(clb_ctx* c, int32_t steps_per_graph);
 
 /* Release the host context (not the caller's workspace or stream). */
 clb_status clb_destroy(clb_ctx* c);
+
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent small periodic channels advanced by one
@@ -398,6 +417,10 @@ clb_status clb_adjoint_destroy(clb_adjoint* a);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* clb_last_error(void);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
 
 #ifdef __cplusplus
 }

@@ -30,6 +30,11 @@ FLAGS = [
 # then the host object with that bundle embedded.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
+# Host pass only: every host symbol hidden except the C ABI, which
+# include/clb.h marks as exported.  No internal function can then be bound at
+# run time to a same-named symbol of another loaded object.
+HOST_FLAGS = ["-fvisibility=hidden", "-fvisibility-inlines-hidden"]
+
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
@@ -76,8 +81,8 @@ def _compile(src, objdir, extra_flags, verbose):
     inc = ["-I", INCLUDE, "-I", CSRC]
     common = [hipcc(), "-x", "hip"] + FLAGS + list(extra_flags) + inc
     _run(common + DEVICE_FLAGS + ["--offload-device-only", "-c", src, "-o", base + ".hipfb"], verbose)
-    _run(common + ["--offload-host-only", "-Xclang", "-fcuda-include-gpubinary", "-Xclang", base + ".hipfb",
-                   "-c", src, "-o", base + ".o"], verbose)
+    _run(common + HOST_FLAGS + ["--offload-host-only", "-Xclang", "-fcuda-include-gpubinary", "-Xclang",
+                                base + ".hipfb", "-c", src, "-o", base + ".o"], verbose)
     return base + ".o"
 
 

@@ -66,6 +66,7 @@ _SIGNATURES = {
     "clb_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "clb_set_check_every": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "clb_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "clb_set_steps_per_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_set_pressure_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -165,6 +166,12 @@ class Solver:
         v = ctypes.c_int64()
         check(lib().clb_steps_done(self._ctx, ctypes.byref(v)))
         return v.value
+
+    def set_check_every(self, check_every):
+        """step() checks for non-finite populations at every multiple of
+        check_every steps and raises ClbError (CLB_EUNSTABLE) at the first
+        failed check; 0 switches the checks off."""
+        check(lib().clb_set_check_every(self._ctx, int(check_every)))
 
     def set_launch(self, block_x=1024, xcd_remap=1):
         check(lib().clb_set_launch(self._ctx, int(block_x), int(xcd_remap)))

@@ -165,6 +165,7 @@ struct clb_ctx {
   double* ghosts;        // pressure mode, large grids: ghost columns
   int xcd_remap;
   int steps_per_launch;  // periodic mode: steps per launch, 1-4 (those before the last kept in LDS)
+  int64_t check_every;   // clb_step checks for non-finite populations at multiples of this step count (0: never)
   // optional hipGraph of graph_steps steps, one per starting buffer
   int graph_steps;
   int graph_flip;        // buffer parity change of one graph replay (launches mod 2)
@@ -346,6 +347,11 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   return CLB_OK;
 }
 
+}  // extern "C"
+
+// Helpers of the stepping entry points.  They sit outside the extern "C"
+// block: C language linkage would give them plain exported names, which any
+// other loaded object defining the same name could take over at run time.
 namespace {
 
 void drop_graphs(clb_ctx* c) {
@@ -407,20 +413,56 @@ clb_status record_graph(clb_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// Enqueue n >= 0 steps: hipGraph replays while whole graphs fit, then single
+// launches.  Updates the buffer parity and the step counter.
+clb_status advance(clb_ctx* c, int64_t n) {
+  clb_status st = CLB_OK;
+  while (c->graph_steps > 0 && n >= c->graph_steps) {
+    if (!c->gexec[c->cur] && (st = record_graph(c)) != CLB_OK) return st;
+    CLB_HIP(hipGraphLaunch(c->gexec[c->cur], c->stream));
+    c->cur ^= c->graph_flip;
+    c->steps += c->graph_steps;
+    n -= c->graph_steps;
+  }
+  CLB_HIP(enqueue_steps(c, n, c->stream, &c->cur));
+  c->steps += n;
+  return CLB_OK;
+}
+
+// Number of non-finite populations of the current state (synchronises).
+clb_status count_nonfinite(clb_ctx* c, double* bad) {
+  const size_t n = (size_t)c->p.nx * c->p.ny;
+  size_t nb = (n + 255) / 256;
+  if (nb > (size_t)kPartials) nb = kPartials;
+  CLB_HIP(clb::launch_nonfinite(c->buf[c->cur], c->g, c->partial, (int)nb, c->result, c->stream));
+  return read_result(c, bad);
+}
+
+}  // namespace
+
+extern "C" {
+
 clb_status clb_step(clb_ctx* c, int64_t nsteps) {
   const clb::TraceRange trace("clb_step");
   clb_status st = check_ctx(c);
   if (st != CLB_OK) return st;
   if (nsteps < 0) return fail(CLB_EINVAL, "nsteps: must be >= 0");
-  while (c->graph_steps > 0 && nsteps >= c->graph_steps) {
-    if (!c->gexec[c->cur] && (st = record_graph(c)) != CLB_OK) return st;
-    CLB_HIP(hipGraphLaunch(c->gexec[c->cur], c->stream));
-    c->cur ^= c->graph_flip;
-    c->steps += c->graph_steps;
-    nsteps -= c->graph_steps;
+  if (c->check_every <= 0) return advance(c, nsteps);
+  // Failure detection: stop at every multiple of check_every (counted from
+  // the start) and look for non-finite populations before going on.
+  while (nsteps > 0) {
+    const int64_t to_check = c->check_every - c->steps % c->check_every;
+    const int64_t m = nsteps < to_check ? nsteps : to_check;
+    if ((st = advance(c, m)) != CLB_OK) return st;
+    nsteps -= m;
+    if (c->steps % c->check_every != 0) break;
+    double bad = 0;
+    if ((st = count_nonfinite(c, &bad)) != CLB_OK) return st;
+    if (bad != 0.0)
+      return fail(CLB_EUNSTABLE, "populations: %.0f non-finite values after step %lld", bad, (long long)c->steps);
   }
-  CLB_HIP(enqueue_steps(c, nsteps, c->stream, &c->cur));
-  c->steps += nsteps;
   return CLB_OK;
 }
 
@@ -521,14 +563,18 @@ clb_status clb_check_finite(clb_ctx* c, int32_t* h_ok) {
   clb_status st = check_ctx(c);
   if (st != CLB_OK) return st;
   if (!h_ok) return fail(CLB_EINVAL, "h_ok: NULL");
-  const size_t n = (size_t)c->p.nx * c->p.ny;
-  size_t nb = (n + 255) / 256;
-  if (nb > (size_t)kPartials) nb = kPartials;
-  CLB_HIP(clb::launch_nonfinite(c->buf[c->cur], c->g, c->partial, (int)nb, c->result, c->stream));
   double bad = 0;
-  if ((st = read_result(c, &bad)) != CLB_OK) return st;
+  if ((st = count_nonfinite(c, &bad)) != CLB_OK) return st;
   *h_ok = bad == 0.0 ? 1 : 0;
   if (!*h_ok) return fail(CLB_EUNSTABLE, "populations: %.0f non-finite values", bad);
+  return CLB_OK;
+}
+
+clb_status clb_set_check_every(clb_ctx* c, int64_t check_every) {
+  clb_status st = check_ctx(c);
+  if (st != CLB_OK) return st;
+  if (check_every < 0) return fail(CLB_EINVAL, "check_every: must be >= 0");
+  c->check_every = check_every;
   return CLB_OK;
 }
 

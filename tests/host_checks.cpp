@@ -105,6 +105,7 @@ int main() {
   EXPECT(clb_set_steps_per_launch(nullptr, 2) == CLB_EINVAL);
   EXPECT(clb_set_pressure_path(nullptr, 0) == CLB_EINVAL);
   EXPECT(clb_set_graph_steps(nullptr, 8) == CLB_EINVAL);
+  EXPECT(clb_set_check_every(nullptr, 8) == CLB_EINVAL);
   EXPECT(clb_destroy(nullptr) == CLB_EINVAL);
 
   // Kn-sweep batch

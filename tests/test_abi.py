@@ -43,6 +43,33 @@ def test_exports_every_declared_symbol(lib):
     assert not missing, missing
 
 
+def test_exports_nothing_but_the_declared_api(lib):
+    """The library's dynamic symbol table holds the entry points of
+    include/*.h and nothing else of its own: no internal helper may carry an
+    exported plain name, which another loaded object defining the same name
+    would take over at run time (calls between exported functions of a shared
+    library go through its PLT).  Template code of the C++ standard library
+    (namespace std, exported by its own headers) and the per-source
+    __hip_cuid markers are allowed."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not found")
+    out = subprocess.run([nm, "-D", "--defined-only", clb.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    declared = set(_declared_symbols())
+    extra = []
+    for line in out.splitlines():
+        name = line.split()[-1]
+        if name in declared or name.startswith("__hip_cuid_"):
+            continue
+        if re.match(r"_ZN?K?St|_ZN9__gnu_cxx", name):
+            continue
+        extra.append(name)
+    assert not extra, extra
+
+
 def test_defaults_are_section3_values(lib):
     p = clb.clb_params()
     lib.clb_params_default(ctypes.byref(p))

@@ -432,6 +432,36 @@ def test_nonfinite_detection():
     assert not s.check_finite()
 
 
+@pytest.mark.parametrize("kw", [dict(nx=100, ny=9, kn=0.5, gx=1e-4),
+                                dict(nx=40, ny=6, xbc="pressure", kn=0.1, p_ratio=2.0)])
+def test_in_step_failure_check(kw):
+    """clb_step with checks every k steps: bitwise the same run as without
+    them while the state stays finite; a planted NaN stops the call with
+    CLB_EUNSTABLE at the first multiple of k, step counter and state there."""
+    from paper_1603_01955_amd import clb
+    ref = _solver(**kw)
+    ref.step(73)
+    s = _solver(**kw)
+    s.set_check_every(10)
+    s.step(31)
+    s.step(42)
+    assert s.steps_done == 73
+    assert torch.equal(s.populations(), ref.populations())
+    P = s.populations()
+    P[5, 1, 3] = float("nan")
+    s.set_populations(P)               # the step counter restarts at 0
+    s.set_check_every(25)
+    with pytest.raises(clb.ClbError) as err:
+        s.step(60)
+    assert err.value.status == clb.CLB_EUNSTABLE
+    assert "after step 25" in str(err.value)
+    assert s.steps_done == 25
+    assert not s.check_finite()
+    s.set_check_every(0)
+    s.step(5)                          # no checks: no error
+    assert s.steps_done == 30
+
+
 def test_bad_workspace_rejected():
     from paper_1603_01955_amd import clb
     p = clb.make_params(64, 8)
