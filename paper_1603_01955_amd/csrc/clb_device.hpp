@@ -17,116 +17,131 @@ struct Rates {
 };
 
 // ---------------------------------------------------------------------------
-// Cascaded collision with semi-implicit forcing, in place on f[9]:
-//   raw moments of the pre-collision f-bar (Eq. 8), velocity from Eq. (13)
-//   (rho u = sum e f + rho F / 2, F = (gx, gy) the body acceleration),
-//   collision kernels g3..g8 in ascending order (Eq. 7, g0 = g1 = g2 = 0),
-//   forcing S = T^-1 S_hat (Eqs. 9, 10) with T^-1 in closed form, and the
-//   update f + K g + S written out per direction (Eqs. 4, 6).
-// THIRD adds (1 - s_q/2) rho F/3 to the source's raw moments k_xxy (F_y) and
-// k_xyy (F_x): the third-order moments of a second-order (Guo-type) force
-// term, which Eq. (9) leaves out; with them Eq. (21)'s printed denominator
-// reproduces the slip law of Eq. (19) in a force-driven channel.
+// Cascaded collision with semi-implicit forcing, in place on f[9].
+//
+// The collision of Eqs. (6)-(9) relaxes the central moments of the
+// pre-collision f-bar (Eq. 8), taken about the velocity of Eq. (13)
+// (rho u = sum e f + rho F / 2, F = (gx, gy) the body acceleration), towards
+// those of the equilibrium of Eq. (11): the second-order trace towards
+// 2 rho / 3 at s3, the deviator and the shear moment towards 0 at s_nu
+// (Eq. 18), the third-order moments towards 0 at s_q (Eq. 21), the
+// fourth-order one towards rho / 9 at s8; the force source of Eq. (9) adds
+// rho F to the first-order central moments (from -rho F/2 to +rho F/2) and
+// nothing above first order.  Here the central moments are reached without
+// the moment matrices of Eq. (10): the D2Q9 velocities factor into x and y
+// components in {-1, 0, 1}, so a pass along x over each of the three rows
+// (moments 1, e_x - u_x, (e_x - u_x)^2 of each row), then a pass along y over
+// the three results gives all nine central moments; after the relaxation the
+// two passes run backwards (central -> raw -> populations along y, then
+// along x).  About 120 FP64 operations instead of the ~220 of the raw-moment
+// form of Eqs. (6)-(9) written out.
+// THIRD adds (1 - s_q/2) rho F/3 to the post-collision raw moments k_xxy
+// (F_y) and k_xyy (F_x): the third-order moments of a second-order
+// (Guo-type) force term, which Eq. (9) leaves out; with them Eq. (21)'s
+// printed denominator reproduces the slip law of Eq. (19) in a force-driven
+// channel.
 // ---------------------------------------------------------------------------
+namespace detail {
+
+// One axis, forward: populations (m, z, p) at e = -1, 0, +1 -> moments
+// (sum, central first, central second) about u, with u2 = u^2, tu = 2u.
+__device__ __forceinline__ void axis_central(double m, double z, double p, double u, double u2, double tu,
+                                             double& k0, double& k1, double& k2) {
+#pragma clang fp contract(off)
+  const double sum = p + m, dif = p - m;
+  k0 = z + sum;
+  k1 = fma(-u, k0, dif);
+  k2 = fma(u2, k0, fma(-tu, dif, sum));
+}
+
+// One axis, backward: central moments (k0, k1, k2) about u -> populations
+// (m, z, p) at e = -1, 0, +1.
+__device__ __forceinline__ void axis_populations(double k0, double k1, double k2, double u, double u2, double tu,
+                                                 double& m, double& z, double& p) {
+#pragma clang fp contract(off)
+  const double r1 = fma(u, k0, k1);                   // raw sum of e f
+  const double r2 = fma(u2, k0, fma(tu, k1, k2));     // raw sum of e^2 f
+  const double h1 = 0.5 * r1;
+  z = k0 - r2;
+  p = fma(0.5, r2, h1);
+  m = fma(0.5, r2, -h1);
+}
+
+}  // namespace detail
+
 template <bool FORCE, bool THIRD = false>
 __device__ __forceinline__ void collide(double f[9], double gx, double gy, const Rates& s) {
   // Products and sums round on their own except where written as fma(): the
   // same FP64 result in every kernel that inlines this, whatever the
   // compiler fuses around it.
 #pragma clang fp contract(off)
-  const double f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4];
-  const double f5 = f[5], f6 = f[6], f7 = f[7], f8 = f[8];
-
-  // Eq. (8)
-  const double d57 = f5 + f7, d68 = f6 + f8;
-  const double diag = d57 + d68;                      // k'_xxyy
-  const double s13 = f1 + f3, s24 = f2 + f4;
-  const double k_xx = s13 + diag;
-  const double k_yy = s24 + diag;
-  const double k_xy = d57 - d68;
-  const double k_xxy = (f5 + f6) - (f7 + f8);
-  const double k_xyy = (f5 + f8) - (f6 + f7);
-  const double rho = f0 + s13 + s24 + diag;
-  const double m57 = f5 - f7;
-  const double jx = (f1 - f3) + m57 + (f8 - f6);
-  const double jy = (f2 - f4) + m57 + (f6 - f8);
-
-  // Eq. (13)
+  using detail::axis_central;
+  using detail::axis_populations;
+  // Rows of the velocity set (Eq. 1), each ordered e_x = -1, 0, +1:
+  // e_y = 0: f3 f0 f1, e_y = +1: f6 f2 f5, e_y = -1: f7 f4 f8.
+  // Zeroth x moment and the moving-population difference of each row.
+  const double kz = f[0] + (f[1] + f[3]), tz = f[1] - f[3];
+  const double kp = f[2] + (f[5] + f[6]), tp = f[5] - f[6];
+  const double km = f[4] + (f[8] + f[7]), tm = f[8] - f[7];
+  // Eqs. (12)-(13)
+  const double rho = kz + (kp + km);
+  const double jx = tz + (tp + tm);
   const double inv_rho = 1.0 / rho;
   const double ux = FORCE ? fma(jx, inv_rho, 0.5 * gx) : jx * inv_rho;
-  const double uy = FORCE ? fma(jy, inv_rho, 0.5 * gy) : jy * inv_rho;
-  const double ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
-  const double tux = 2.0 * ux, tuy = 2.0 * uy, trho = 2.0 * rho;
+  const double uy = FORCE ? fma(kp - km, inv_rho, 0.5 * gy) : (kp - km) * inv_rho;
+  const double ux2 = ux * ux, uy2 = uy * uy, tux = ux + ux, tuy = uy + uy;
 
-  // Eq. (7): the force corrections are the "-1/2 rho (...)" terms.
-  double c3 = fma(rho, ux2 + uy2, (2.0 / 3.0) * rho) - (k_xx + k_yy);
-  double c4 = fma(rho, ux2 - uy2, -(k_xx - k_yy));
-  double c5 = fma(rho, uxy, -k_xy);
-  double c6 = fma(-uy, k_xx, fma(-tux, k_xy, fma(trho * ux2, uy, k_xxy)));
-  double c7 = fma(-ux, k_yy, fma(-tuy, k_xy, fma(trho * uy2, ux, k_xyy)));
-  const double inner =
-      fma(4.0 * uxy, k_xy, fma(uy2, k_xx, fma(ux2, k_yy, fma(-tuy, k_xxy, fma(-tux, k_xyy, diag)))));
-  double c8 = fma(3.0 * rho * ux2, uy2, rho * (1.0 / 9.0)) - inner;
+  // x pass: central moments along x of each row (order 0 is kz, kp, km).
+  double az, bz, cz, ap, bp, cp, am, bm, cm;
+  axis_central(f[3], f[0], f[1], ux, ux2, tux, az, bz, cz);
+  axis_central(f[6], f[2], f[5], ux, ux2, tux, ap, bp, cp);
+  axis_central(f[7], f[4], f[8], ux, ux2, tux, am, bm, cm);
+  // y pass: k_ab = central moment of order a in x and b in y.
+  double k00, k01, k02, k10, k11, k12, k20, k21, k22;
+  axis_central(am, az, ap, uy, uy2, tuy, k00, k01, k02);
+  axis_central(bm, bz, bp, uy, uy2, tuy, k10, k11, k12);
+  axis_central(cm, cz, cp, uy, uy2, tuy, k20, k21, k22);
+
+  // Relaxation (Eq. 14 rates) and the force source of Eq. (9).
   if (FORCE) {
-    c3 -= rho * fma(gx, ux, gy * uy);
-    c4 -= rho * fma(gx, ux, -(gy * uy));
-    c5 -= 0.5 * rho * fma(gx, uy, gy * ux);
-    c6 -= 0.5 * rho * fma(gy, ux2, 2.0 * gx * uxy);
-    c7 -= 0.5 * rho * fma(gx, uy2, 2.0 * gy * uxy);
-    c8 -= rho * fma(gx * ux, uy2, gy * uy * ux2);
+    k10 = fma(rho, gx, k10);
+    k01 = fma(rho, gy, k01);
   }
-  const double g3 = s.s3 * (1.0 / 12.0) * c3;
-  const double qnu = 0.25 * s.snu;
-  const double g4 = qnu * c4;
-  const double g5 = qnu * c5;
-  const double a34 = fma(3.0, g3, g4);    // appears in g6 and g8
-  const double b34 = fma(3.0, g3, -g4);   // appears in g7 and g8
-  const double qq = 0.25 * s.sq;
-  const double g6 = fma(-tux, g5, fma(-0.5 * uy, a34, qq * c6));
-  const double g7 = fma(-tuy, g5, fma(-0.5 * ux, b34, qq * c7));
-  const double g8 = fma(-tux, g7, fma(-tuy, g6, fma(-4.0 * uxy, g5, fma(-0.5 * ux2, b34,
-                    fma(-0.5 * uy2, a34, fma(-2.0, g3, 0.25 * s.s8 * c8))))));
+  const double tr = k20 + k02, dv = k20 - k02;
+  const double tr1 = fma(-s.s3, fma(-(2.0 / 3.0), rho, tr), tr);
+  const double onu = 1.0 - s.snu, oq = 1.0 - s.sq;
+  const double dv1 = onu * dv;
+  k20 = 0.5 * (tr1 + dv1);
+  k02 = 0.5 * (tr1 - dv1);
+  k11 = onu * k11;
+  k21 = oq * k21;
+  k12 = oq * k12;
+  k22 = fma(-s.s8, fma(-(1.0 / 9.0), rho, k22), k22);
 
-  // Eq. (6): f + K g (columns of K from Eq. 3).
-  const double g38 = g3 - g8, g78 = g7 - g8, g68 = g6 - g8;
-  double o0 = fma(-4.0, g38, f0);
-  double o1 = fma(2.0, g78, (f1 - g3) + g4);
-  double o2 = fma(2.0, g68, (f2 - g3) - g4);
-  double o3 = fma(-2.0, g7 + g8, (f3 - g3) + g4);
-  double o4 = fma(-2.0, g6 + g8, (f4 - g3) - g4);
-  const double t = fma(2.0, g3, g8);
-  double o5 = f5 + t + g5 - g6 - g7;
-  double o6 = f6 + t - g5 - g6 + g7;
-  double o7 = f7 + t + g5 + g6 + g7;
-  double o8 = f8 + t - g5 + g6 - g7;
+  // Back: y pass for each x order, then x pass for each row.
+  axis_populations(rho, k01, k02, uy, uy2, tuy, am, az, ap);
+  axis_populations(k10, k11, k12, uy, uy2, tuy, bm, bz, bp);
+  axis_populations(k20, k21, k22, uy, uy2, tuy, cm, cz, cp);
+  axis_populations(az, bz, cz, ux, ux2, tux, f[3], f[0], f[1]);
+  axis_populations(ap, bp, cp, ux, ux2, tux, f[6], f[2], f[5]);
+  axis_populations(am, bm, cm, ux, ux2, tux, f[7], f[4], f[8]);
 
-  if (FORCE) {
-    // Eq. (9) source moments in the basis of Eq. (10) ...
-    const double Sx = rho * gx, Sy = rho * gy;
-    const double Sxy = rho * fma(ux, gy, uy * gx);
-    double Sxxy = fma(Sy, ux2, 2.0 * Sx * uxy);
-    double Sxyy = fma(Sx, uy2, 2.0 * Sy * uxy);
-    if (THIRD) {
-      const double c = (1.0 - 0.5 * s.sq) * (1.0 / 3.0);
-      Sxxy = fma(c, Sy, Sxxy);
-      Sxyy = fma(c, Sx, Sxyy);
-    }
-    const double Sxxyy = 2.0 * fma(Sx * ux, uy2, Sy * uy * ux2);
-    const double Sxx = 2.0 * Sx * ux;   // (S3 + S4)/2
-    const double Syy = 2.0 * Sy * uy;   // (S3 - S4)/2
-    // ... mapped back to populations by the inverse of T (closed form).
-    o0 += Sxxyy - Sxx - Syy;
-    o1 += 0.5 * (Sxx - Sxxyy + Sx - Sxyy);
-    o3 += 0.5 * (Sxx - Sxxyy - Sx + Sxyy);
-    o2 += 0.5 * (Syy - Sxxyy + Sy - Sxxy);
-    o4 += 0.5 * (Syy - Sxxyy - Sy + Sxxy);
-    o5 += 0.25 * (Sxxyy + Sxy + Sxxy + Sxyy);
-    o6 += 0.25 * (Sxxyy - Sxy + Sxxy - Sxyy);
-    o7 += 0.25 * (Sxxyy + Sxy - Sxxy - Sxyy);
-    o8 += 0.25 * (Sxxyy - Sxy - Sxxy + Sxyy);
+  if (FORCE && THIRD) {
+    // (1 - s_q/2) rho F / 3 added to the raw moments k_xxy (F_y) and k_xyy
+    // (F_x), mapped to populations by the inverse of Eq. (10).
+    const double c = (1.0 - 0.5 * s.sq) * (1.0 / 3.0) * rho;
+    const double dxxy = c * gy, dxyy = c * gx;
+    const double qa = 0.25 * (dxxy + dxyy), qb = 0.25 * (dxxy - dxyy);
+    const double hx = 0.5 * dxyy, hy = 0.5 * dxxy;
+    f[5] += qa;
+    f[7] -= qa;
+    f[6] += qb;
+    f[8] -= qb;
+    f[1] -= hx;
+    f[3] += hx;
+    f[2] -= hy;
+    f[4] += hy;
   }
-  f[0] = o0; f[1] = o1; f[2] = o2; f[3] = o3; f[4] = o4;
-  f[5] = o5; f[6] = o6; f[7] = o7; f[8] = o8;
 }
 
 // Equilibrium of Eq. (11).  Its T-moments factor per axis into the D1Q3
@@ -181,6 +196,17 @@ __device__ __forceinline__ void rho_u(const double f[9], double& rho, double& ux
   const double inv = 1.0 / rho;
   ux = ((f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6])) * inv;
   uy = ((f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8])) * inv;
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed order: a butterfly over
+// lane distances 32, 16, ..., 1 (cross-lane moves, no LDS, no barrier).  At
+// every level lanes i and i ^ d add the same two partial sums, so every lane
+// ends with the same bits, and the result does not depend on timing.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
 }
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014): first output of a stream

@@ -40,6 +40,7 @@ struct View {
   const double* __restrict__ P;
   Geo g;
   __device__ __forceinline__ double at(int i, int x, int y) const { return P[g.index(i, x, y)]; }
+  __device__ __forceinline__ const double* ptr(int i, int x, int y) const { return P + g.index(i, x, y); }
   __device__ __forceinline__ int nx() const { return g.nx; }
   __device__ __forceinline__ int ny() const { return g.ny; }
 };
@@ -49,6 +50,18 @@ struct LdsView {
   const double* P;
   int nx_, ny_, n;
   __device__ __forceinline__ double at(int i, int x, int y) const { return P[i * n + y * nx_ + x]; }
+  __device__ __forceinline__ int nx() const { return nx_; }
+  __device__ __forceinline__ int ny() const { return ny_; }
+};
+
+// Populations in the ABI layout [9][ny][nx] (x fastest) in device memory.
+struct PlaneView {
+  const double* __restrict__ P;
+  int nx_, ny_;
+  __device__ __forceinline__ const double* ptr(int i, int x, int y) const {
+    return P + ((size_t)i * (size_t)ny_ + (size_t)y) * (size_t)nx_ + (size_t)x;
+  }
+  __device__ __forceinline__ double at(int i, int x, int y) const { return *ptr(i, x, y); }
   __device__ __forceinline__ int nx() const { return nx_; }
   __device__ __forceinline__ int ny() const { return ny_; }
 };
@@ -174,9 +187,9 @@ struct Gather {
   template <bool CLAMP>
   __device__ __forceinline__ const double* addr(int i, int xs, int ys) const {
     static_assert(MODE >= 1 && MODE <= 3, "addresses exist for the pressure modes only");
-    if (MODE == 3) return v.P + v.g.index(i, xs, ys);
+    if (MODE == 3) return v.ptr(i, xs, ys);
     const int xc = xs < 0 ? 0 : (xs >= v.nx() ? v.nx() - 1 : xs);
-    const double* p = v.P + v.g.index(i, xc, ys);
+    const double* p = v.ptr(i, xc, ys);
     if (MODE == 2 && !CLAMP) {
       p = xs < 0 ? gin + i * v.ny() + ys : p;
       p = xs >= v.nx() ? gout + i * v.ny() + ys : p;

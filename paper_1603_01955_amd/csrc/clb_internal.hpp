@@ -161,6 +161,9 @@ hipError_t launch_step2_pressure(const StepArgs& a, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st);
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);
+// The same sums over populations in the ABI layout [9][ny][nx] (a.src and
+// a.g.lshift / nseg unused; a.g.nx, a.g.ny give the grid).
+hipError_t launch_column_sums_plane(const DiagArgs& a, const double* P, hipStream_t st);
 hipError_t launch_mean(const double* v, int n, double* out, hipStream_t st);
 hipError_t launch_pressure_dev(const double* rhoc, int nx, double rho_in, double rho_out, double* dp,
                                hipStream_t st);

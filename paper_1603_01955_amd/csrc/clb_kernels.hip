@@ -164,8 +164,6 @@ __global__ __launch_bounds__(tile_w<K>() * H, K == 2 ? 8 : 4) void k_stepk_perio
 // x-boundary code, the first and last stage the two ghost columns in LDS
 // (channels taller than 512 rows evaluate ghost populations inline).
 // ---------------------------------------------------------------------------
-constexpr int PX = 16;   // column-sum diagnostics: 16 columns x 16 row lanes
-constexpr int PY = 16;
 
 // One workgroup's CX columns with the gather of MODE 3 (interior), 2 (ghost
 // columns staged in s_ghost by this workgroup) or 1 (ghosts inline).
@@ -580,16 +578,24 @@ __global__ void k_moments(DiagArgs a) {
   if (a.uy) a.uy[idx] = uy;
 }
 
-// Per-column sums, block = PX columns x PY row lanes, fixed summation order.
-template <int MODE>
-__global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
-  __shared__ double sm[PY][PX], su[PY][PX];
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * PX + tx;
-  Gather<MODE, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
+// Per-column sums.  A workgroup owns kColLanes adjacent columns, one per
+// lane, so every population load of a wavefront is one contiguous 512-byte
+// row piece; its kColWaves wavefronts split the rows (wave w takes rows w,
+// w + kColWaves, ...), and the per-wave partial sums of each column are
+// added in wave order through LDS: a fixed summation order.
+constexpr int kColLanes = 64;
+constexpr int kColWaves = 16;
+
+template <int MODE, class V>
+__global__ __launch_bounds__(kColLanes * kColWaves) void k_column_sums(DiagArgs a, V v) {
+  __shared__ double sm[kColWaves][kColLanes], su[kColWaves][kColLanes];
+  const int lane = threadIdx.x & (kColLanes - 1), w = threadIdx.x / kColLanes;
+  const int x = blockIdx.x * kColLanes + lane;
+  const int nx = v.nx(), ny = v.ny();
+  Gather<MODE, V> gat{v, a.r, 1.0 - a.r, a.shift, a.rho_in, a.rho_out};
   double accm = 0.0, accu = 0.0;
-  if (x < a.g.nx) {
-    for (int y = ty; y < a.g.ny; y += PY) {
+  if (x < nx) {
+    for (int y = w; y < ny; y += kColWaves) {
       double f[9];
       gather_node(gat, x, y, f);
       double rho, ux, uy;
@@ -599,21 +605,21 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
       accu += ux;
     }
   }
-  sm[ty][tx] = accm;
-  su[ty][tx] = accu;
+  sm[w][lane] = accm;
+  su[w][lane] = accu;
   __syncthreads();
-  if (ty == 0 && x < a.g.nx) {
-    double m = sm[0][tx], u = su[0][tx];
+  if (w == 0 && x < nx) {
+    double m = sm[0][lane], u = su[0][lane];
 #pragma unroll
-    for (int k = 1; k < PY; ++k) {
-      m += sm[k][tx];
-      u += su[k][tx];
+    for (int k = 1; k < kColWaves; ++k) {
+      m += sm[k][lane];
+      u += su[k][lane];
     }
     double f[9];
-    const int yc = a.g.ny / 2;
+    const int yc = ny / 2;
     gather_node(gat, x, yc, f);
     double rc = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    if ((a.g.ny & 1) == 0) {
+    if ((ny & 1) == 0) {
       gather_node(gat, x, yc - 1, f);
       rc = 0.5 * ((f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]) + rc);
     }
@@ -623,20 +629,18 @@ __global__ __launch_bounds__(PX * PY) void k_column_sums(DiagArgs a) {
   }
 }
 
-// Sum of n values in a fixed order (one block of 256 threads), divided by
-// `divisor` (n for a mean, 1 for a plain sum).
+// Sum of n values in a fixed order (one workgroup of 256 threads): strided
+// per-thread sums, a wavefront butterfly, then the four wavefront totals in
+// order; divided by `divisor` (n for a mean, 1 for a plain sum).
 __global__ __launch_bounds__(256) void k_sum(const double* __restrict__ v, int n, double divisor,
                                              double* __restrict__ out) {
-  __shared__ double s[256];
+  __shared__ double s[4];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
-  s[threadIdx.x] = acc;
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = s[0] / divisor;
+  if (threadIdx.x == 0) out[0] = ((s[0] + s[1]) + (s[2] + s[3])) / divisor;
 }
 
 // delta p(x) = (rho_c/3 - p_l(x)) / p_out, p_l linear from p_in to p_out.
@@ -653,7 +657,7 @@ __global__ void k_pressure_dev(const double* __restrict__ rhoc, int nx, double r
 // block sums them in order.
 __global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restrict__ p, Geo g,
                                                            double* __restrict__ partial) {
-  __shared__ double s[256];
+  __shared__ double s[4];
   const size_t n = (size_t)g.nx * (size_t)g.ny;
   double cnt = 0.0;
   for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
@@ -665,13 +669,10 @@ __global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restr
       cnt += (v - v == 0.0) ? 0.0 : 1.0;   // inf - inf and NaN - NaN are NaN
     }
   }
-  s[threadIdx.x] = cnt;
+  cnt = wave_sum(cnt);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = cnt;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+  if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 unsigned grid_for(size_t n, unsigned cap = 65536) {
@@ -969,13 +970,22 @@ hipError_t launch_moments(const DiagArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st) {
-  const dim3 grid((unsigned)((a.g.nx + PX - 1) / PX));
+template <class V>
+hipError_t launch_column_sums_v(const DiagArgs& a, const V& v, hipStream_t st) {
+  const dim3 grid((unsigned)((a.g.nx + kColLanes - 1) / kColLanes));
   if (a.mode == 0)
-    k_column_sums<0><<<grid, dim3(PX, PY), 0, st>>>(a);
+    k_column_sums<0, V><<<grid, kColLanes * kColWaves, 0, st>>>(a, v);
   else
-    k_column_sums<1><<<grid, dim3(PX, PY), 0, st>>>(a);
+    k_column_sums<1, V><<<grid, kColLanes * kColWaves, 0, st>>>(a, v);
   return hipGetLastError();
+}
+
+hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st) {
+  return launch_column_sums_v(a, View{a.src, a.g}, st);
+}
+
+hipError_t launch_column_sums_plane(const DiagArgs& a, const double* P, hipStream_t st) {
+  return launch_column_sums_v(a, PlaneView{P, a.g.nx, a.g.ny}, st);
 }
 
 hipError_t launch_mean(const double* v, int n, double* out, hipStream_t st) {

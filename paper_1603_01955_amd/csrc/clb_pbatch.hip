@@ -32,7 +32,9 @@ constexpr int kMassThreads = 1024;
 
 // Column-mean mass flow (1/nx) sum_x sum_y rho u_x of one channel's
 // pre-collision state (Eqs. 5, 12, 13, 20 and the ghost columns), summed
-// in a fixed order by one workgroup of kMassThreads threads.
+// in a fixed order by one workgroup of kMassThreads threads: each thread
+// walks whole columns, the threads' totals are added by wavefront
+// butterflies and the wavefront totals in order.
 __device__ double channel_massflow(const PBatchArgs& p, const PChan& ch, const double* P, double* s_red) {
   const Gather<1, View> gat{{P, p.g}, ch.r, 1.0 - ch.r, p.shift, ch.rho_in, ch.rho_out};
   double acc = 0.0;
@@ -47,13 +49,14 @@ __device__ double channel_massflow(const PBatchArgs& p, const PChan& ch, const d
     }
     acc += m;
   }
-  s_red[threadIdx.x] = acc;
+  // wavefront sums, then the wavefront totals in order
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int w = kMassThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
-    __syncthreads();
-  }
-  return s_red[0] / (double)p.g.nx;
+  double m = s_red[0];
+#pragma unroll
+  for (int k = 1; k < kMassThreads / 64; ++k) m += s_red[k];
+  return m / (double)p.g.nx;
 }
 
 // After `add` steps of the running channels, whose state is now in buffer
@@ -62,7 +65,7 @@ __device__ double channel_massflow(const PBatchArgs& p, const PChan& ch, const d
 // |m - m_prev| <= tol |m|.  One workgroup per channel.
 __global__ __launch_bounds__(kMassThreads) void k_pbatch_check(PBatchArgs p, PChanState* st, int add, int cur,
                                                                 int check, double tol) {
-  __shared__ double s_red[kMassThreads];
+  __shared__ double s_red[kMassThreads / 64];
   const int c = blockIdx.x;
   PChanState s = st[c];
   __syncthreads();   // every thread has read st[c] before thread 0 rewrites it
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(kMassThreads) void k_pbatch_check(PBatchArgs p, PCh
 
 // Mass flow of every channel's current state into m[nch].
 __global__ __launch_bounds__(kMassThreads) void k_pbatch_mass(PBatchArgs p, const PChanState* st, double* m) {
-  __shared__ double s_red[kMassThreads];
+  __shared__ double s_red[kMassThreads / 64];
   const int c = blockIdx.x;
   const double v = channel_massflow(p, p.ch[c], p.buf[st[c].cur] + (size_t)c * p.stride, s_red);
   if (threadIdx.x == 0) m[c] = v;
