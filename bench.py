@@ -18,8 +18,11 @@ METRIC = "D2Q9 CLB MLUPS & HBM GB/s; batched Kn-sweep vs loop; adjoint/forward t
 WORKLOAD = dict(nx=32768, ny=2048, kn=1.0, gx=1e-7, init="perturbed", init_amp=1e-4, seed=12345)
 BYTES_PER_NODE = 144          # 9 FP64 loads + 9 FP64 stores per node update
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E, published
-CPU_SAMPLE_ROWS = 128
-CPU_SAMPLE_STEPS = 3
+# FP64 vector issue: one wave64 FP64 instruction per clock per CU
+# (78.6 TFLOP/s = 256 CUs x 2.4 GHz x 64 lanes x 2 flops per FMA).
+FP64_WAVE_INSTS_PER_S = 256 * 2.4e9
+CPU_SAMPLE_NX = 512           # full-height slab of the workload: wall rows 2 of 2048, as on the full grid
+CPU_SAMPLE_STEPS = 15
 
 
 def parse():
@@ -61,10 +64,11 @@ def copy_calibration(gb):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
 
 
-def traffic_from_profile():
-    """HBM bytes per step-kernel launch (FETCH_SIZE + WRITE_SIZE, each scaled by
-    the same counter on a plain copy of known size) from the committed counter
-    summary; None unless it was taken on the current kernel sources."""
+def profile_record():
+    """Per-launch counter figures of the step kernel from the committed
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a
+    plain copy of known size; FP64 VALU instructions), or {} unless they were
+    taken on the current kernel sources."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                         "step_periodic_32768x2048_traffic.txt")
     rec = {}
@@ -75,11 +79,35 @@ def traffic_from_profile():
                     k, v = line.split("=", 1)
                     rec[k.strip()] = v.strip()
     except OSError:
-        return None
+        return {}
     from paper_1603_01955_amd.build import source_hash
-    if rec.get("source_hash") != source_hash() or "bytes_per_launch" not in rec:
-        return None
-    return float(rec["bytes_per_launch"])
+    if rec.get("source_hash") != source_hash():
+        return {}
+    return rec
+
+
+def copy_bandwidth(gb=2.0, reps=10):
+    """HBM ceiling measured on this GPU: a plain device-to-device copy of gb
+    GB (torch's copy kernel), bytes read + written over the time of reps
+    copies (HIP events)."""
+    import torch
+    n = int(gb * 1e9) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / s / 1e9
 
 
 def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True, forcing=0):
@@ -128,12 +156,11 @@ def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True, forc
             s.close()
         return dt, steps
 
-    kmin = float(np.array(kns)[int(np.argmin(q))])
     updates = int(sum(4 * int(ny) * int(n) for ny, n in zip(heights, steps_b)))   # node updates
     if not baselines:
         return {"channels": len(params), "all_converged": bool(conv.all()),
                 "steps_total": int(steps_b.sum()), "node_updates": updates, "batched_s": round(t_batch, 4),
-                "batched_mlups": round(updates / t_batch / 1e6, 1), "kn_at_min_Q": kmin}
+                "batched_mlups": round(updates / t_batch / 1e6, 1)}
     t_loop, steps_l = loop(graph=False)
     t_graph, _ = loop(graph=True)
     return {
@@ -145,8 +172,32 @@ def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True, forc
         "batched_s": round(t_batch, 4), "loop_s": round(t_loop, 4), "graph_loop_s": round(t_graph, 4),
         "speedup_vs_loop": round(t_loop / t_batch, 2), "speedup_vs_graph_loop": round(t_graph / t_batch, 2),
         "tuned": {"threads": threads, "longest_first": longest, "tune_s": round(t_tune, 3)},
-        "kn_at_min_Q": kmin,
     }
+
+
+def kn_minimum(ny=64, count=48, kn_lo=0.3, kn_hi=3.0, forcing=0, max_steps=400000, check_every=1000,
+               tol=1e-12):
+    """The Knudsen minimum of the flow rate (Section 3.1) read off one batched
+    launch of channels of a single height (Q depends on the height too):
+    count channels 4 x ny, Kn log-spaced over [kn_lo, kn_hi], g = 1e-6, each
+    to steady state.  Reports the Kn of the smallest steady Q and the grid
+    spacing."""
+    import numpy as np
+    from clb_inputs import kn_minimum_channels
+    from paper_1603_01955_amd import Batch, clb
+
+    heights, kns = kn_minimum_channels(count, ny=ny, kn_lo=kn_lo, kn_hi=kn_hi)
+    b = Batch([clb.make_params(4, h, kn=k, gx=1e-6, forcing=forcing) for h, k in zip(heights, kns)])
+    t0 = time.perf_counter()
+    steps, conv = b.run(max_steps, check_every, tol)
+    dt = time.perf_counter() - t0
+    q = b.flow_rate()
+    b.close()
+    k = int(np.argmin(q))
+    return {"ny": ny, "channels": count, "kn_range": [kn_lo, kn_hi], "grid_ratio": round(kns[1] / kns[0], 4),
+            "all_converged": bool(conv.all()), "steps_max": int(steps.max()), "batched_s": round(dt, 4),
+            "kn_at_min_Q": round(kns[k], 4), "Q_min": round(float(q[k]), 6),
+            "interior_minimum": bool(0 < k < count - 1)}
 
 
 def adjoint_calibration(T=2000, K=45, repeats=3):
@@ -194,14 +245,17 @@ def adjoint_calibration(T=2000, K=45, repeats=3):
             "backward_over_forward": round(b / f, 3)}
 
 
-def pressure_step(nx=4000, ny=40, steps=20000):
-    """The pressure-driven step of Section 3.2 at its figure shape (L/H = 100,
-    H = 40, ratio 2, Kn_out = 0.1, linear-density start): time per step with
-    HIP events on the solver's stream."""
+def pressure_step(nx=4000, ny=40, steps=200000):
+    """The long pressure-driven channel of Section 3.2 (L/H = 100, 4000 x 40,
+    p_in/p_out = 2, Kn_out = 0.1, linear-density start) run for its 2e5
+    steps: time per step with HIP events on the solver's stream over the
+    whole run, then the physics it is run for -- the non-linear centre-line
+    pressure deviation dp(x) = (p_c - p_l)/p_out along the channel and the
+    mass flow m = sum_y rho u_x (its column mean and its spread along x,
+    which vanishes at steady state)."""
     import torch
     from paper_1603_01955_amd import Solver
     s = Solver(nx=nx, ny=ny, xbc="pressure", kn=0.1, p_ratio=2.0, init="linear_rho")
-    s.step(200)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -210,9 +264,20 @@ def pressure_step(nx=4000, ny=40, steps=20000):
     e1.record(s.stream)
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / steps
+    dp, _ = s.pressure_deviation()
+    m_col, m = s.massflow()
+    dp = dp.cpu()
+    m_col = m_col.cpu()
+    ok = s.check_finite()
     s.close()
+    k = int(torch.argmax(dp))
+    at = [0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95]
     return {"workload": "pressure_%dx%d" % (nx, ny), "steps": steps, "us_per_step": round(us, 3),
-            "mlups": round(nx * ny / us, 1), "algorithmic_gbs": round(BYTES_PER_NODE * nx * ny / us / 1e3, 1)}
+            "mlups": round(nx * ny / us, 1), "finite": ok,
+            "dp_max": round(float(dp[k]), 6), "x_over_L_at_dp_max": round((k + 0.5) / nx, 4),
+            "dp_profile": {"x_over_L": at, "dp": [round(float(dp[min(nx - 1, int(a * nx))]), 6) for a in at]},
+            "massflow_mean": float(m),
+            "massflow_spread": float((m_col.max() - m_col.min()) / abs(m))}
 
 
 def forcing_variant(steps=200, warmup=10):
@@ -237,9 +302,10 @@ def forcing_variant(steps=200, warmup=10):
     del s
     torch.cuda.empty_cache()
     sw = kn_sweep(baselines=False, forcing=1)
+    km = kn_minimum(forcing=1)
     return {"forcing": 1, "step_ms": round(ms, 4), "step_mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
             "kn_sweep_all_converged": sw["all_converged"], "kn_sweep_batched_s": sw["batched_s"],
-            "kn_at_min_Q": sw["kn_at_min_Q"]}
+            "kn_minimum": km}
 
 
 def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2000, baselines=True):
@@ -322,12 +388,13 @@ def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2
 
 def cpu_baseline():
     """The CPU reference, as it stands, on a bounded sample of the workload:
-    CPU_SAMPLE_STEPS steps of a 32768 x CPU_SAMPLE_ROWS slab of the same
-    channel (same Kn, force and seeded start), BLAS limited to one thread."""
-    import numpy as np  # noqa: F401
+    CPU_SAMPLE_STEPS steps of a CPU_SAMPLE_NX x 2048 slab of the same channel
+    (full height, so the wall rows are 2 of 2048 as on the full grid; same Kn,
+    force and seeded start; periodic over the slab), BLAS and OpenMP pools
+    limited to one thread."""
     from threadpoolctl import threadpool_limits
     from oracle import clb_ref as C
-    prm = C.Params(nx=WORKLOAD["nx"], ny=CPU_SAMPLE_ROWS, kn=WORKLOAD["kn"], gx=WORKLOAD["gx"])
+    prm = C.Params(nx=CPU_SAMPLE_NX, ny=WORKLOAD["ny"], kn=WORKLOAD["kn"], gx=WORKLOAD["gx"])
     with threadpool_limits(limits=1):
         P = C.init_perturbed(prm, WORKLOAD["seed"], WORKLOAD["init_amp"])
         P = C.step(P, prm)                      # warm-up
@@ -336,8 +403,10 @@ def cpu_baseline():
         dt = time.perf_counter() - t0
     nodes = prm.nx * prm.ny
     return {"value": nodes * CPU_SAMPLE_STEPS / dt / 1e6, "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d steps of a %dx%d slab of the same channel (Kn=1, g=1e-7, seeded start), "
+            "kind": "oracle", "host_cores": os.cpu_count(),
+            "thread_pins": {"threadpool_limits": 1, "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+                            "OPENBLAS_NUM_THREADS": os.environ.get("OPENBLAS_NUM_THREADS")},
+            "sample": "%d steps of a %dx%d slab of the same channel (full height; Kn=1, g=1e-7, seeded start), "
                       "NumPy FP64, one thread, %.1f s" % (CPU_SAMPLE_STEPS, prm.nx, prm.ny, dt)}
 
 
@@ -351,7 +420,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.part == "sweep":
-        print(json.dumps({"kn_sweep": kn_sweep(baselines=not args.no_loop_baseline)}), flush=True)
+        print(json.dumps({"kn_sweep": kn_sweep(baselines=not args.no_loop_baseline),
+                          "kn_minimum": kn_minimum()}), flush=True)
         return
     if args.part == "pressure":
         print(json.dumps({"pressure_step": pressure_step()}), flush=True)
@@ -384,8 +454,18 @@ def main():
     ms = t0.elapsed_time(t1) / args.steps
     ok = s.check_finite()
     mlups = nodes / (ms * 1e-3) / 1e6
-    achieved = BYTES_PER_NODE * nodes / (ms * 1e-3) / 1e9
-    traffic = traffic_from_profile()
+    k = args.steps_per_launch if s.nx >= 64 else 1   # narrower grids step one at a time
+    launch_s = ms * 1e-3 * k                          # average duration of one k-step launch
+    # Algorithmic bytes of one k-step launch: every population read once and
+    # written once (72 B + 72 B per node); the steps before the last stay in LDS.
+    alg = BYTES_PER_NODE * nodes
+    achieved = alg / launch_s / 1e9
+    prof = profile_record()
+    traffic = float(prof["bytes_per_launch"]) if "bytes_per_launch" in prof and int(
+        prof.get("steps_per_launch", 0)) == k else None
+    fp64 = float(prof["fp64_valu_insts_per_launch"]) if "fp64_valu_insts_per_launch" in prof and int(
+        prof.get("steps_per_launch", 0)) == k else None
+    copy_gbs = copy_bandwidth()
     rec = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -402,17 +482,26 @@ def main():
         "config": {"workload": "periodic_32768x2048", "nx": s.nx, "ny": s.ny, "kn": WORKLOAD["kn"],
                    "g": WORKLOAD["gx"], "start": "seeded perturbed equilibrium, amp 1e-4, seed 12345",
                    "buffers": "A-B", "block_x": args.block_x, "xcd_remap": args.xcd_remap,
-                   "steps_per_launch": args.steps_per_launch},
-        "hbm_gbs": round(achieved, 1),
+                   "steps_per_launch": k},
         "finite": ok,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic if args.steps_per_launch == 2 else None,
-                     "steps_per_launch": args.steps_per_launch,
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * args.steps_per_launch,
-                     # measured HBM bytes per launch over the launch time: the bandwidth actually drawn
-                     "traffic_gbs": (round(traffic / (ms * args.steps_per_launch * 1e-3) / 1e9, 1)
-                                     if traffic and args.steps_per_launch == 2 else None)},
+                     "traffic": traffic,
+                     "steps_per_launch": k,
+                     "launch_us": round(launch_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": alg,
+                     "unit_bytes": "144 B per node per launch (9 FP64 read + 9 written once; "
+                                   "a launch advances every node k steps)",
+                     # the HBM ceiling measured on this GPU
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4),
+                     # counter bytes per launch over the launch time: the bandwidth actually drawn
+                     "traffic_gbs": round(traffic / launch_s / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+                     # FP64 VALU instructions per launch (counters) against one per clock per CU
+                     "fp64_issue_frac": round(fp64 / launch_s / FP64_WAVE_INSTS_PER_S, 4) if fp64 else None,
+                     # node updates x 144 B over the time: the bandwidth a one-step kernel would need
+                     "effective_gbs": round(BYTES_PER_NODE * nodes * k / launch_s / 1e9, 1)},
     }
     s.close()
     del s
@@ -422,6 +511,7 @@ def main():
         return
     if not args.no_sweep:
         rec["kn_sweep"] = kn_sweep(baselines=not args.no_loop_baseline)
+        rec["kn_minimum"] = kn_minimum()
     rec["pressure_step"] = pressure_step()
     rec["forcing_variant"] = forcing_variant()
     if not args.no_msweep:

@@ -45,6 +45,15 @@ def kn_sweep_channels(count=64, seed=7, heights=(16, 24, 32, 48, 64, 96, 128),
     return [int(v) for v in ny], [float(v) for v in kn]
 
 
+def kn_minimum_channels(count=48, ny=32, kn_lo=0.3, kn_hi=3.0):
+    """A single-height Kn sweep around the Knudsen minimum: ``count``
+    periodic channels of ``ny`` rows with Kn log-spaced over [kn_lo, kn_hi]
+    (Q depends on the height too, so its minimum over Kn is read off
+    channels of one height)."""
+    kn = kn_lo * (kn_hi / kn_lo) ** (np.arange(count) / max(count - 1, 1))
+    return [int(ny)] * count, [float(v) for v in kn]
+
+
 # Pressure ratio and TMAC of the paper's mass-flow study (Section 3.2).
 MASS_FLOW_P_RATIO = 1.8
 MASS_FLOW_SIGMA = 0.93
