@@ -223,6 +223,23 @@ clb_status clb_set_graph_steps(clb_ctx* c, int32_t steps_per_graph);
 /* Release the host context (not the caller's workspace or stream). */
 clb_status clb_destroy(clb_ctx* c);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the mass
+ * flow of clb_massflow computed from populations the caller holds, with no
+ * context and no workspace.  d_P holds post-collision populations in the
+ * [9][ny][nx] layout of clb_get_populations (device memory, read only) of
+ * the problem *p; the outputs are those of clb_massflow: per-column
+ * d_m_col[nx] (device, may be NULL) and the column mean *h_m_mean (host, may
+ * be NULL; synchronises hip_stream).  Work is enqueued on hip_stream.  The
+ * scratch (the per-column sums when d_m_col is NULL, and the mean) is a fixed
+ * device array of the library, CLB_NOALLOC_MAX_NX + 32 doubles per GPU, held
+ * until the process ends; the call never allocates device memory.  Calls
+ * that overlap on one GPU share that array and race.  CLB_EINVAL for an
+ * invalid *p, nx > CLB_NOALLOC_MAX_NX, or pointers that are not device
+ * memory of the needed size. */
+#define CLB_NOALLOC_MAX_NX (1 << 20)
+clb_status clb_massflow_noalloc(const clb_params* p, const double* d_P, double* d_m_col, double* h_m_mean,
+                                void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent small periodic channels advanced by one

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libclb.so")
 
-SOURCES = ["clb_api.cpp", "clb_kernels.hip", "clb_batch.hip", "clb_pbatch.hip", "clb_adjoint.hip"]
+SOURCES = ["clb_api.cpp", "clb_kernels.hip", "clb_batch.hip", "clb_pbatch.hip", "clb_adjoint.hip", "clb_noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

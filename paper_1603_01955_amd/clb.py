@@ -72,6 +72,8 @@ _SIGNATURES = {
     "clb_set_pressure_path": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_set_graph_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "clb_massflow_noalloc": (ctypes.c_int, [ctypes.POINTER(clb_params), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "clb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -246,6 +248,19 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def massflow_noalloc(params, P, m_col=None, stream=None):
+    """clb_massflow of caller-held populations P ([9][ny][nx] float64 on the
+    GPU) with no device allocation: returns the column mean; fills m_col
+    ([nx] float64 on the GPU) if given.  Enqueued on ``stream`` (default: the
+    current stream of P's device)."""
+    if stream is None:
+        stream = torch.cuda.current_stream(P.device)
+    mean = ctypes.c_double()
+    check(lib().clb_massflow_noalloc(ctypes.byref(params), _ptr(P), _ptr(m_col), ctypes.byref(mean),
+                                     ctypes.c_void_p(stream.cuda_stream)))
+    return mean.value
 
 
 _BATCH_SIGNATURES = {
