@@ -22,4 +22,8 @@ analytic  Closed-form steady solutions used to pin the above (discrete
           slip-channel profile, continuum second-order slip profile, Knudsen
           minimum, lubrication mass flow).
 rng       SplitMix64 counter-based generator for the seeded perturbed start.
+clb3d_ref The 3-D extension to rectangular microducts (D3Q27, central
+          moments by definition, walls of Eq. 20 carried to 3-D), which the
+          paper names as future work; pinned by mathematics and by reduction
+          to the 2-D reference (tests/test_oracle_3d.py).
 """

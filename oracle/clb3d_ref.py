@@ -1,0 +1,275 @@
+"""Plain NumPy FP64 reference of a 3-D cascaded LB step for force-driven gas
+flow in a rectangular microduct (test infrastructure only).
+
+Not part of the product path: only tests, the smoke check and the CPU-baseline
+leg of the benchmark may import it.  Written to be checked by eye, not for
+speed.
+
+The paper (Liu & He, arXiv:1603.01955) builds its cascaded scheme in 2-D and
+names the extension to 3-D rectangular ducts as future work (Section 4); it
+prints no 3-D velocity set, moment basis, duct-edge wall rule or slip
+calibration.  This reference carries the 2-D method over as directly as the
+definitions allow; every point below is a reading, not a printed formula:
+
+  * Velocity set D3Q27: e = (a, b, c) with a, b, c in {-1, 0, 1}; direction
+    index i = (a + 1) + 3 (b + 1) + 9 (c + 1) (rest population i = 13).
+  * Collision (the 2-D collision of Eqs. 6-9 as read in clb_ref: central
+    moments of the pre-collision populations about the velocity of Eq. 13,
+    u = (sum e f + rho F/2) / rho, relaxed towards the central moments of the
+    equilibrium): central moment k_pqr = sum_i f_i (e_x - u_x)^p
+    (e_y - u_y)^q (e_z - u_z)^r, p, q, r in {0, 1, 2}; equilibrium values
+    rho c_p c_q c_r with c_0 = 1, c_1 = 0, c_2 = 1/3 (the 2-D ones are
+    rho c_p c_q); first order from -rho F/2 to +rho F/2 (Eq. 9's source);
+    second order: trace k_200 + k_020 + k_002 towards rho at the bulk rate
+    s_b (the paper's s3), its deviator and k_110, k_101, k_011 towards 0 at
+    s_nu (Eq. 18); all seven third-order moments towards 0 at s_q (Eq. 21);
+    every moment of order four to six at s8.
+  * Rates: Eqs. (18) and (21) with N = H = ny, the duct height (Kn is the
+    Knudsen number of the height); r from Eq. (21), the same on every wall.
+  * Walls: half-way planes below row y = 0 and above y = ny - 1 and, for a
+    duct, below layer z = 0 and above z = nz - 1 (or z periodic: a channel).
+    x is periodic (force-driven, Section 3.1).  Eq. (20) in 3-D: when the
+    pull source n - e of direction e at node n lies behind the wall planes of
+    a set S of axes (one axis, or both y and z at a duct edge),
+        pre_e(n) = r P_{-e}(n) + (1 - r) P_{e'}(n - e_t),
+    where e' is e with its components along S reversed (specular reflection)
+    and e_t is e with its components along S removed (the reflected particle
+    arrives displaced along the wall by the tangential part of its path);
+    with cbbsr_shift = 0 the specular source is the node n itself.  For a
+    2-D slice this is exactly the rule the 2-D reference uses.  At the edges
+    of a duct only the displaced source conserves mass (the same-node source
+    reflects a population leaving across one wall into a direction that
+    crosses both), so ducts take cbbsr_shift = 1; the same-node variant is
+    kept for z-periodic channels.
+
+Parity with the paper: unpinned (no 3-D scheme or number is printed).  The
+reference is pinned instead by mathematics (tests/test_oracle_3d.py):
+conservation, the relaxed central moments, the closed-form D3Q27
+equilibrium as a fixed point, the single-rate (BGK) reduction, reduction to
+the pinned 2-D reference on z-uniform states, y-z symmetry of square ducts,
+the discrete slip channel of the 2-D analysis, and the continuum Poiseuille
+flow rate of a rectangular duct.
+"""
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from .clb_ref import bounce_fraction, rate_nu, rate_q, slip_A1
+from .rng import uniform01
+
+# ---------------------------------------------------------------------------
+# Velocity set and moment exponents.
+# ---------------------------------------------------------------------------
+E3 = np.array([(a, b, c) for c in (-1, 0, 1) for b in (-1, 0, 1) for a in (-1, 0, 1)], dtype=np.int64)
+Q3 = 27
+OPP = np.array([int(np.flatnonzero((E3 == -e).all(axis=1))[0]) for e in E3], dtype=np.int64)
+REST = 13
+
+
+def direction(a, b, c):
+    return (a + 1) + 3 * (b + 1) + 9 * (c + 1)
+
+
+# moment k = p + 3 q + 9 r  <->  exponents (p, q, r)
+PQR = np.array([(p, q, r) for r in range(3) for q in range(3) for p in range(3)], dtype=np.int64)
+ORDER = PQR.sum(axis=1)
+C_EQ = np.array([1.0, 0.0, 1.0 / 3.0])
+
+
+def moment_index(p, q, r):
+    return p + 3 * q + 9 * r
+
+
+@dataclasses.dataclass
+class Params3D:
+    nx: int
+    ny: int
+    nz: int
+    zbc: str = "walls"            # "walls" (rectangular duct) or "periodic" (channel)
+    kn: float = 0.1
+    a: float = 2.0                # Bosanquet factor, Eq. (16)
+    sigma: float = 1.0            # TMAC
+    A1: Optional[float] = None    # B1 sigma_v; None -> from sigma
+    A2: float = 0.55              # B2
+    r: Optional[float] = None     # bounce-back fraction; None -> Eq. (21)
+    s_b: float = 1.1              # bulk rate (the paper's s3)
+    s8: float = 1.2               # rate of orders 4-6 (the paper's s8)
+    gx: float = 0.0               # body acceleration
+    gy: float = 0.0
+    gz: float = 0.0
+    rho0: float = 1.0
+    tq_den: float = 16.0          # Eq. (21) denominator
+    cbbsr_shift: int = 1
+
+
+def resolved(prm):
+    A1 = prm.A1 if prm.A1 is not None else slip_A1(prm.sigma)
+    r = prm.r if prm.r is not None else bounce_fraction(A1)
+    return A1, r
+
+
+def rates(prm):
+    """(s_b, s_nu, s_q, s8) with Eqs. (18), (21) for N = ny."""
+    return (prm.s_b, rate_nu(prm.kn, prm.ny, prm.a), rate_q(prm.kn, prm.ny, prm.a, prm.A2, prm.tq_den),
+            prm.s8)
+
+
+# ---------------------------------------------------------------------------
+# Central moments by their definition, and back.
+# ---------------------------------------------------------------------------
+def central_matrix(u):
+    """C[n, k, i] = (e_x,i - u_x)^p (e_y,i - u_y)^q (e_z,i - u_z)^r for
+    moment k = (p, q, r) and direction i, at each of the n velocities u (3, n)."""
+    d = E3.T[:, None, :].astype(np.float64) - u[:, :, None]        # (3, n, 27)
+    out = np.ones((u.shape[1], Q3, Q3))
+    for k, (p, q, r) in enumerate(PQR):
+        out[:, k, :] = d[0] ** p * d[1] ** q * d[2] ** r
+    return out
+
+
+def macroscopic(f, g=(0.0, 0.0, 0.0)):
+    """rho and u = (sum e f + rho g / 2) / rho (Eqs. 12-13) of populations
+    f (27, ...)."""
+    shape = f.shape[1:]
+    ff = f.reshape(Q3, -1)
+    rho = ff.sum(axis=0)
+    j = E3.T.astype(np.float64) @ ff
+    u = j / rho + 0.5 * np.asarray(g, dtype=np.float64)[:, None]
+    return rho.reshape(shape), u.reshape((3,) + shape)
+
+
+def equilibrium(rho, u):
+    """Populations whose central moments about u are those of the
+    equilibrium, rho c_p c_q c_r: solved from the definition."""
+    rho = np.atleast_1d(rho).astype(np.float64)
+    u = np.asarray(u, dtype=np.float64).reshape(3, -1)
+    kap = rho[None, :] * np.array([C_EQ[p] * C_EQ[q] * C_EQ[r] for p, q, r in PQR])[:, None]
+    C = central_matrix(u)
+    return np.linalg.solve(C, kap.T[:, :, None])[:, :, 0].T
+
+
+def collide(pre, g, s_b, s_nu, s_q, s8):
+    """Post-collision populations of pre (27, ...): central moments about u
+    relaxed as listed in the module docstring."""
+    shape = pre.shape
+    f = pre.reshape(Q3, -1)
+    n = f.shape[1]
+    g = np.asarray(g, dtype=np.float64)
+    rho = f.sum(axis=0)
+    u = (E3.T.astype(np.float64) @ f) / rho + 0.5 * g[:, None]
+    C = central_matrix(u)
+    kap = np.einsum("nki,in->kn", C, f)
+    post = np.empty_like(kap)
+    k = moment_index
+    # order 0 and 1
+    post[k(0, 0, 0)] = kap[k(0, 0, 0)]
+    post[k(1, 0, 0)] = kap[k(1, 0, 0)] + rho * g[0]
+    post[k(0, 1, 0)] = kap[k(0, 1, 0)] + rho * g[1]
+    post[k(0, 0, 1)] = kap[k(0, 0, 1)] + rho * g[2]
+    # order 2: trace at s_b towards rho, deviator at s_nu towards 0
+    diag = [k(2, 0, 0), k(0, 2, 0), k(0, 0, 2)]
+    tr = kap[diag].sum(axis=0)
+    tr_post = tr - s_b * (tr - rho)
+    for d in diag:
+        post[d] = tr_post / 3.0 + (1.0 - s_nu) * (kap[d] - tr / 3.0)
+    for m in (k(1, 1, 0), k(1, 0, 1), k(0, 1, 1)):
+        post[m] = (1.0 - s_nu) * kap[m]
+    # orders 3 to 6
+    for m in range(Q3):
+        if ORDER[m] >= 3:
+            s = s_q if ORDER[m] == 3 else s8
+            p, q, r = PQR[m]
+            eq = rho * C_EQ[p] * C_EQ[q] * C_EQ[r]
+            post[m] = kap[m] - s * (kap[m] - eq)
+    assert n == post.shape[1]
+    out = np.linalg.solve(C, post.T[:, :, None])[:, :, 0].T
+    return out.reshape(shape)
+
+
+# ---------------------------------------------------------------------------
+# Streaming (Eq. 5) with the walls (Eq. 20 in 3-D) -> pre-collision state.
+# ---------------------------------------------------------------------------
+def stream_bc(P, prm, r=None):
+    if r is None:
+        r = resolved(prm)[1]
+    _, nz, ny, nx = P.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    zwalls = prm.zbc == "walls"
+    pre = np.empty_like(P)
+    for i, (a, b, c) in enumerate(E3):
+        xs = (x - a) % nx
+        ys = y - b
+        zs = z - c
+        out_y = (ys < 0) | (ys >= ny)
+        if zwalls:
+            out_z = (zs < 0) | (zs >= nz)
+        else:
+            zs = zs % nz
+            out_z = np.zeros_like(out_y)
+        inside = ~out_y & ~out_z
+        pre[i][inside] = P[i, zs[inside], ys[inside], xs[inside]]
+        wall = ~inside
+        if not wall.any():
+            continue
+        # reflected direction e' and the source node of its specular part
+        bb = P[OPP[i], z[wall], y[wall], x[wall]]
+        oy, oz = out_y[wall], out_z[wall]
+        b2 = np.where(oy, -b, b)
+        c2 = np.where(oz, -c, c)
+        i2 = (a + 1) + 3 * (b2 + 1) + 9 * (c2 + 1)
+        if prm.cbbsr_shift:
+            sx = xs[wall]
+            sy = np.where(oy, y[wall], ys[wall])
+            sz = np.where(oz, z[wall], zs[wall])
+        else:
+            sx, sy, sz = x[wall], y[wall], z[wall]
+        spec = P[i2, sz, sy, sx]
+        pre[i][wall] = r * bb + (1.0 - r) * spec
+    return pre
+
+
+def step(P, prm):
+    _, r = resolved(prm)
+    pre = stream_bc(P, prm, r)
+    return collide(pre, (prm.gx, prm.gy, prm.gz), *rates(prm))
+
+
+def run(P, prm, nsteps):
+    for _ in range(nsteps):
+        P = step(P, prm)
+    return P
+
+
+# ---------------------------------------------------------------------------
+# Initial states and diagnostics.
+# ---------------------------------------------------------------------------
+def init_uniform(prm):
+    n = prm.nx * prm.ny * prm.nz
+    feq = equilibrium(np.full(n, prm.rho0), np.zeros((3, n)))
+    return feq.reshape(Q3, prm.nz, prm.ny, prm.nx)
+
+
+def init_perturbed(prm, seed, amp):
+    """P_i = f_i^eq(rho0, 0) + amp (2U - 1), U from SplitMix64 keyed by
+    seed XOR (27 * node + i), node = (z * ny + y) * nx + x."""
+    P = init_uniform(prm)
+    node = np.arange(prm.nz * prm.ny * prm.nx, dtype=np.uint64).reshape(prm.nz, prm.ny, prm.nx)
+    for i in range(Q3):
+        U = uniform01(seed, np.uint64(27) * node + np.uint64(i))
+        P[i] += amp * (2.0 * U - 1.0)
+    return P
+
+
+def moments(P, prm):
+    """rho (nz, ny, nx) and u (3, nz, ny, nx) of the pre-collision state."""
+    return macroscopic(stream_bc(P, prm), (prm.gx, prm.gy, prm.gz))
+
+
+def flow_rate_Q(P, prm):
+    """Dimensionless flow rate of Section 3.1 carried over to a duct of
+    height H = ny and width W = nz: Q = sqrt(6) sum_{y,z} u_x / (3 g H^2 W),
+    averaged over x (for a z-periodic channel the 2-D Q)."""
+    _, u = moments(P, prm)
+    H, W = float(prm.ny), float(prm.nz)
+    return u[0].sum(axis=(0, 1)).mean() * np.sqrt(6.0) / (3.0 * prm.gx * H * H * W)
