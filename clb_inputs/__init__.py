@@ -22,6 +22,13 @@ def uniform_populations(nx, ny, seed, lo=0.05, hi=0.15):
     return rng.uniform(lo, hi, size=(9, ny, nx))
 
 
+def uniform_populations_3d(nx, ny, nz, seed, lo=0.02, hi=0.06):
+    """Random positive D3Q27 populations, shape (27, nz, ny, nx), uniform in
+    [lo, hi) (density about 1, far from equilibrium)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(27, nz, ny, nx))
+
+
 def sample_nodes(nx, ny, count, seed):
     """Distinct node coordinates (ys, xs): all four corners, the wall rows,
     the first and last columns, plus uniform random interior picks."""
@@ -78,6 +85,9 @@ WORKLOADS = {
                                 init="perturbed", init_amp=1e-4, seed=12345),
     # Long channel for the adjoint calibration, L/H = 100.
     "long_2000x20": dict(nx=2000, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, steps=2000),
+    # Rectangular microduct (3-D extension): square cross-section, force driven.
+    "duct_256x128x128": dict(nx=256, ny=128, nz=128, kn=0.5, gx=1e-6, init="perturbed", init_amp=1e-4,
+                             seed=2468),
     # Mass-flow sweep: 16 long channels, L/H = 100, Kn_out 0.01 .. 1.
     "mass_flow_sweep_16x2000x20": dict(nx=2000, ny=20, xbc="pressure", p_ratio=MASS_FLOW_P_RATIO,
                                        sigma=MASS_FLOW_SIGMA, channels=16, kn_lo=0.01, kn_hi=1.0),

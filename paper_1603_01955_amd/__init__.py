@@ -7,3 +7,4 @@ include/clb.h; ``clb`` is its Python binding.
 from .clb import (Batch, ClbError, PressureBatch, Solver, derive, lib, make_params, workspace_size,  # noqa: F401
                   CLB_OK, CLB_EINVAL, CLB_ENOMEM, CLB_EHIP, CLB_ESTATE, CLB_EUNSTABLE)
 from .adjoint import Adjoint, CLBRunLoss  # noqa: F401,E402
+from .clb3d import Duct, make_params3  # noqa: E402,F401

@@ -14,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libclb.so")
 
-SOURCES = ["clb_api.cpp", "clb_kernels.hip", "clb_batch.hip", "clb_pbatch.hip", "clb_adjoint.hip", "clb_noalloc.hip"]
+SOURCES = ["clb_api.cpp", "clb_kernels.hip", "clb_batch.hip", "clb_pbatch.hip", "clb_adjoint.hip", "clb_noalloc.hip",
+           "clb3d.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,582 @@
+// 3-D cascaded LB step for force-driven gas flow in a rectangular microduct
+// (D3Q27, FP64), declared in include/clb3d.h.
+//
+// Method: the 2-D scheme of Liu & He (arXiv:1603.01955) carried to 3-D, the
+// extension the paper names as future work (Section 4): pull streaming
+// (Eq. 5) with the combined bounce-back / specular wall of Eq. (20) on the
+// duct walls, then the cascaded collision (Eqs. 6-9, 13) in central-moment
+// form.  One kernel per step: gather, collide, store -- 216 B read and
+// 216 B written per node update.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "clb3d.h"
+#include "clb_device.hpp"
+#include "clb_internal.hpp"
+#include "clb_trace.hpp"
+
+namespace clb3 {
+namespace {
+
+struct Args {
+  const double* src;    // post-collision populations at t - 1, [27][nz][ny][nx]
+  double* dst;          // post-collision populations at t
+  int nx, ny, nz;
+  size_t plane;         // nx * ny * nz
+  int zwalls;           // 1: walls in z (duct), 0: z periodic (channel)
+  int shift;            // Eq. (20) specular source displaced along the walls
+  double r, omr;        // bounce-back fraction and 1 - r
+  double gx, gy, gz;
+  double sb, snu, sq, s8;
+};
+
+__device__ __forceinline__ size_t node_index(const Args& a, int x, int y, int z) {
+  return ((size_t)z * (size_t)a.ny + (size_t)y) * (size_t)a.nx + (size_t)x;
+}
+
+// Pre-collision populations of node (x, y, z): pull streaming (Eq. 5), x
+// periodic, z periodic or walled; where the source n - e lies behind the
+// wall planes of a set S of axes, Eq. (20) carried to 3-D:
+//   pre_e(n) = r P_{-e}(n) + (1 - r) P_{e'}(n - e_t),
+// e' = e with its components along S reversed, e_t = e without them (the
+// node itself when shift = 0).
+__device__ __forceinline__ void gather(const Args& a, int x, int y, int z, double f[27]) {
+#pragma clang fp contract(off)
+  const double* __restrict__ P = a.src;
+  const size_t self = node_index(a, x, y, z);
+#pragma unroll
+  for (int c = -1; c <= 1; ++c) {
+#pragma unroll
+    for (int b = -1; b <= 1; ++b) {
+#pragma unroll
+      for (int e = -1; e <= 1; ++e) {
+        const int i = (e + 1) + 3 * (b + 1) + 9 * (c + 1);
+        int xs = x - e;
+        xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+        const int ys = y - b;
+        int zs = z - c;
+        const bool oy = ys < 0 || ys >= a.ny;
+        bool oz = false;
+        if (a.zwalls)
+          oz = zs < 0 || zs >= a.nz;
+        else
+          zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
+        if (!oy && !oz) {
+          f[i] = P[(size_t)i * a.plane + node_index(a, xs, ys, zs)];
+        } else {
+          const int i2 = (e + 1) + 3 * ((oy ? -b : b) + 1) + 9 * ((oz ? -c : c) + 1);
+          const double bb = P[(size_t)(26 - i) * a.plane + self];
+          const size_t sn = a.shift ? node_index(a, xs, oy ? y : ys, oz ? z : zs) : self;
+          const double sp = P[(size_t)i2 * a.plane + sn];
+          f[i] = a.r * bb + a.omr * sp;
+        }
+      }
+    }
+  }
+}
+
+// Density and momentum of the populations (x, y, z components).
+__device__ __forceinline__ void rho_j(const double f[27], double& rho, double& jx, double& jy, double& jz) {
+#pragma clang fp contract(off)
+  double s[9], t[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {   // row (b, c) along x
+    s[k] = f[3 * k + 1] + (f[3 * k + 2] + f[3 * k]);
+    t[k] = f[3 * k + 2] - f[3 * k];
+  }
+  rho = ((s[0] + s[1] + s[2]) + (s[3] + s[4] + s[5])) + (s[6] + s[7] + s[8]);
+  jx = ((t[0] + t[1] + t[2]) + (t[3] + t[4] + t[5])) + (t[6] + t[7] + t[8]);
+  jy = ((s[2] - s[0]) + (s[5] - s[3])) + (s[8] - s[6]);
+  jz = ((s[6] - s[0]) + (s[7] - s[1])) + (s[8] - s[2]);
+}
+
+// The central-moment collision, in place on f[27] (slot A + 3B + 9C holds
+// direction (A - 1, B - 1, C - 1), then moment order (A, B, C)).  Three
+// passes of the one-axis transform of the 2-D step give the central moments
+// k_pqr about u; relaxation (trace at s_b towards rho, deviator and shear at
+// s_nu, third order at s_q, orders 4-6 at s8 towards rho c_p c_q c_r with
+// c = (1, 0, 1/3), first order + rho F); three passes back.
+template <bool FORCE>
+__device__ __forceinline__ void collide(double f[27], const Args& a) {
+#pragma clang fp contract(off)
+  using clb::detail::axis_central;
+  using clb::detail::axis_populations;
+  double rho, jx, jy, jz;
+  rho_j(f, rho, jx, jy, jz);
+  const double inv = 1.0 / rho;
+  const double ux = FORCE ? fma(jx, inv, 0.5 * a.gx) : jx * inv;
+  const double uy = FORCE ? fma(jy, inv, 0.5 * a.gy) : jy * inv;
+  const double uz = FORCE ? fma(jz, inv, 0.5 * a.gz) : jz * inv;
+  const double ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const double tux = ux + ux, tuy = uy + uy, tuz = uz + uz;
+  // forward: x, y, z
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    axis_central(f[3 * k], f[3 * k + 1], f[3 * k + 2], ux, ux2, tux, f[3 * k], f[3 * k + 1], f[3 * k + 2]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int o = p + 9 * c;
+      axis_central(f[o], f[o + 3], f[o + 6], uy, uy2, tuy, f[o], f[o + 3], f[o + 6]);
+    }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) axis_central(f[k], f[k + 9], f[k + 18], uz, uz2, tuz, f[k], f[k + 9], f[k + 18]);
+
+  // relaxation; k_pqr sits in slot p + 3 q + 9 r
+  if (FORCE) {
+    f[1] = f[1] + rho * a.gx;
+    f[3] = f[3] + rho * a.gy;
+    f[9] = f[9] + rho * a.gz;
+  }
+  const double third = 1.0 / 3.0;
+  const double tr = (f[2] + f[6]) + f[18];
+  const double tr1 = tr - a.sb * (tr - rho);
+  const double onu = 1.0 - a.snu;
+  const double mean = tr * third, mean1 = tr1 * third;
+  f[2] = mean1 + onu * (f[2] - mean);
+  f[6] = mean1 + onu * (f[6] - mean);
+  f[18] = mean1 + onu * (f[18] - mean);
+  f[4] = onu * f[4];     // k110
+  f[10] = onu * f[10];   // k101
+  f[12] = onu * f[12];   // k011
+  const double oq = 1.0 - a.sq;
+  // third order: k210 k120 k201 k021 k102 k012 k111
+  f[5] = oq * f[5];
+  f[7] = oq * f[7];
+  f[11] = oq * f[11];
+  f[15] = oq * f[15];
+  f[19] = oq * f[19];
+  f[21] = oq * f[21];
+  f[13] = oq * f[13];
+  // orders 4-6: k220 k202 k022 towards rho/9, k222 towards rho/27, the rest to 0
+  const double e9 = rho * (1.0 / 9.0), e27 = rho * (1.0 / 27.0);
+  f[8] = f[8] - a.s8 * (f[8] - e9);
+  f[20] = f[20] - a.s8 * (f[20] - e9);
+  f[24] = f[24] - a.s8 * (f[24] - e9);
+  f[26] = f[26] - a.s8 * (f[26] - e27);
+  const double o8 = 1.0 - a.s8;
+  f[14] = o8 * f[14];    // k211
+  f[16] = o8 * f[16];    // k121
+  f[22] = o8 * f[22];    // k112
+  f[17] = o8 * f[17];    // k221
+  f[23] = o8 * f[23];    // k212
+  f[25] = o8 * f[25];    // k122
+
+  // back: z, y, x
+#pragma unroll
+  for (int k = 0; k < 9; ++k) axis_populations(f[k], f[k + 9], f[k + 18], uz, uz2, tuz, f[k], f[k + 9], f[k + 18]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int o = p + 9 * c;
+      axis_populations(f[o], f[o + 3], f[o + 6], uy, uy2, tuy, f[o], f[o + 3], f[o + 6]);
+    }
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    axis_populations(f[3 * k], f[3 * k + 1], f[3 * k + 2], ux, ux2, tux, f[3 * k], f[3 * k + 1], f[3 * k + 2]);
+}
+
+constexpr int kBX = 64, kBY = 4;
+
+template <bool FORCE>
+__global__ __launch_bounds__(kBX * kBY) void k3_step(Args a) {
+  const int x = blockIdx.x * kBX + (threadIdx.x & (kBX - 1));
+  const int y = blockIdx.y * kBY + (int)(threadIdx.x / kBX);
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  double f[27];
+  gather(a, x, y, z, f);
+  collide<FORCE>(f, a);
+  const size_t n = node_index(a, x, y, z);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(f[i], a.dst + (size_t)i * a.plane + n);
+}
+
+// Macroscopic fields of the pre-collision state (Eqs. 12-13).
+__global__ __launch_bounds__(kBX * kBY) void k3_moments(Args a, double* rho, double* ux, double* uy, double* uz) {
+#pragma clang fp contract(off)
+  const int x = blockIdx.x * kBX + (threadIdx.x & (kBX - 1));
+  const int y = blockIdx.y * kBY + (int)(threadIdx.x / kBX);
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  double f[27];
+  gather(a, x, y, z, f);
+  double r, jx, jy, jz;
+  rho_j(f, r, jx, jy, jz);
+  const size_t n = node_index(a, x, y, z);
+  if (rho) rho[n] = r;
+  if (ux) ux[n] = jx / r + 0.5 * a.gx;
+  if (uy) uy[n] = jy / r + 0.5 * a.gy;
+  if (uz) uz[n] = jz / r + 0.5 * a.gz;
+}
+
+// Per-workgroup partial sums of u_x (pre-collision state) over the nodes,
+// in a fixed order: strided per-thread sums, wavefront butterflies, the four
+// wavefront totals in order.
+__global__ __launch_bounds__(256) void k3_ux_partial(Args a, double* partial) {
+#pragma clang fp contract(off)
+  __shared__ double s[4];
+  double acc = 0.0;
+  for (size_t n = blockIdx.x * (size_t)256 + threadIdx.x; n < a.plane; n += (size_t)gridDim.x * 256) {
+    const int x = (int)(n % (size_t)a.nx);
+    const size_t rest = n / (size_t)a.nx;
+    const int y = (int)(rest % (size_t)a.ny);
+    const int z = (int)(rest / (size_t)a.ny);
+    double f[27];
+    gather(a, x, y, z, f);
+    double r, jx, jy, jz;
+    rho_j(f, r, jx, jy, jz);
+    acc += jx / r + 0.5 * a.gx;
+  }
+  acc = clb::wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// Count of non-finite values among all populations, per workgroup.
+__global__ __launch_bounds__(256) void k3_nonfinite_partial(const double* __restrict__ p, size_t n,
+                                                            double* partial) {
+  __shared__ double s[4];
+  double cnt = 0.0;
+  for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+    const double v = p[k];
+    cnt += (v - v == 0.0) ? 0.0 : 1.0;
+  }
+  cnt = clb::wave_sum(cnt);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// Sum of n partials in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void k3_sum(const double* __restrict__ v, int n, double* out) {
+  __shared__ double s[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
+  acc = clb::wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// Start: f^eq(rho0, 0) (product of the one-axis factors 2/3, 1/6, 1/6) plus
+// the seeded perturbation.
+__global__ void k3_init(double* dst, size_t plane, double rho0, int perturbed, double amp, uint64_t seed) {
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < plane; n += (size_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const int e0 = i % 3 - 1, e1 = (i / 3) % 3 - 1, e2 = i / 9 - 1;
+      const double w0 = e0 == 0 ? 2.0 / 3.0 : 1.0 / 6.0, w1 = e1 == 0 ? 2.0 / 3.0 : 1.0 / 6.0,
+                   w2 = e2 == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+      double v = rho0 * w0 * w1 * w2;
+      if (perturbed) {
+        const uint64_t key = seed ^ (27ull * (uint64_t)n + (uint64_t)i);
+        const double U = (double)(clb::splitmix64_first(key) >> 11) * (1.0 / 9007199254740992.0);
+        v += amp * (2.0 * U - 1.0);
+      }
+      dst[(size_t)i * plane + n] = v;
+    }
+  }
+}
+
+constexpr int kPartials = 1024;
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+unsigned blocks_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > (size_t)kPartials) b = kPartials;
+  return (unsigned)(b == 0 ? 1 : b);
+}
+
+}  // namespace
+}  // namespace clb3
+
+struct clb3_ctx {
+  clb3_params p;
+  clb_derived d;
+  double* buf[2];
+  int cur;
+  double* partial;
+  double* result;
+  hipStream_t stream;
+  int64_t steps;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+clb_status fail3(clb_status st, const char* fmt, ...) {
+  char msg[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof(msg), fmt, ap);
+  va_end(ap);
+  return clb::set_error(st, msg);
+}
+
+#define CLB3_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) return fail3(CLB_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+bool finite(double v) { return std::isfinite(v); }
+
+clb_status validate3(const clb3_params* p, clb_derived* d) {
+  if (!p) return fail3(CLB_EINVAL, "params: NULL");
+  if (p->nx < 1) return fail3(CLB_EINVAL, "nx: must be >= 1 (got %d)", p->nx);
+  if (p->ny < 1) return fail3(CLB_EINVAL, "ny: must be >= 1 (got %d)", p->ny);
+  if (p->nz < 1 || p->nz > 65535) return fail3(CLB_EINVAL, "nz: must lie in [1, 65535] (got %d)", p->nz);
+  if ((p->ny + 3) / 4 > 65535) return fail3(CLB_EINVAL, "ny: at most 262140 rows");
+  if (p->zbc != CLB3_Z_WALLS && p->zbc != CLB3_Z_PERIODIC) return fail3(CLB_EINVAL, "zbc: unknown kind %d", p->zbc);
+  if (p->init != CLB_INIT_UNIFORM && p->init != CLB_INIT_PERTURBED)
+    return fail3(CLB_EINVAL, "init: must be CLB_INIT_UNIFORM or CLB_INIT_PERTURBED");
+  if (p->cbbsr_shift != 0 && p->cbbsr_shift != 1) return fail3(CLB_EINVAL, "cbbsr_shift: must be 0 or 1");
+  if (p->cbbsr_shift == 0 && p->zbc == CLB3_Z_WALLS)
+    return fail3(CLB_EINVAL, "cbbsr_shift: the same-node specular source does not conserve mass at duct edges; "
+                             "z-periodic channels only");
+  if (!(finite(p->kn) && p->kn > 0)) return fail3(CLB_EINVAL, "kn: must be finite and > 0");
+  if (!(finite(p->a) && p->a >= 0)) return fail3(CLB_EINVAL, "a: must be finite and >= 0");
+  if (!(finite(p->sigma) && p->sigma > 0 && p->sigma <= 2)) return fail3(CLB_EINVAL, "sigma: must lie in (0, 2]");
+  if (!std::isnan(p->A1) && !(finite(p->A1) && p->A1 >= 0))
+    return fail3(CLB_EINVAL, "A1: must be NaN (derive from sigma) or finite and >= 0");
+  if (!(finite(p->A2) && p->A2 >= 0)) return fail3(CLB_EINVAL, "A2: must be finite and >= 0");
+  if (!std::isnan(p->r) && !(p->r >= 0 && p->r <= 1))
+    return fail3(CLB_EINVAL, "r: must be NaN (derive from A1) or lie in [0, 1]");
+  if (!(finite(p->s_b) && p->s_b > 0 && p->s_b < 2)) return fail3(CLB_EINVAL, "s_b: must lie in (0, 2)");
+  if (!(finite(p->s8) && p->s8 > 0 && p->s8 < 2)) return fail3(CLB_EINVAL, "s8: must lie in (0, 2)");
+  if (!(finite(p->gx) && finite(p->gy) && finite(p->gz))) return fail3(CLB_EINVAL, "gx/gy/gz: must be finite");
+  if (!(finite(p->rho0) && p->rho0 > 0)) return fail3(CLB_EINVAL, "rho0: must be finite and > 0");
+  if (!(finite(p->init_amp) && p->init_amp >= 0)) return fail3(CLB_EINVAL, "init_amp: must be finite and >= 0");
+  if (!(finite(p->tq_den) && p->tq_den > 0)) return fail3(CLB_EINVAL, "tq_den: must be finite and > 0");
+  clb_derived dd;
+  dd.A1 = std::isnan(p->A1) ? (1.0 - 0.1817 * p->sigma) * (2.0 - p->sigma) / p->sigma : p->A1;
+  dd.r = std::isnan(p->r) ? 1.0 / (1.0 + dd.A1 * std::sqrt(kPi / 6.0)) : p->r;
+  dd.tau_tilde = std::sqrt(6.0 / kPi) * (double)p->ny * p->kn / (1.0 + p->a * p->kn);
+  dd.s_nu = 1.0 / (0.5 + dd.tau_tilde);
+  dd.s_q = 1.0 / (0.5 + (3.0 + 4.0 * kPi * dd.tau_tilde * dd.tau_tilde * p->A2) / (p->tq_den * dd.tau_tilde));
+  if (!(dd.s_nu > 0 && dd.s_nu < 2 && dd.s_q > 0 && dd.s_q < 2 && finite(dd.r)))
+    return fail3(CLB_EINVAL, "kn/a/A2: derived relaxation rates out of (0, 2)");
+  if (d) *d = dd;
+  return CLB_OK;
+}
+
+size_t plane_of(const clb3_params* p) { return (size_t)p->nx * (size_t)p->ny * (size_t)p->nz; }
+
+size_t buffer_bytes(const clb3_params* p) { return clb3::align256(27 * plane_of(p) * sizeof(double)); }
+
+size_t total_bytes(const clb3_params* p) {
+  return 2 * buffer_bytes(p) + clb3::align256(clb3::kPartials * sizeof(double)) + clb3::align256(32 * sizeof(double));
+}
+
+clb3::Args args_of(const clb3_ctx* c) {
+  clb3::Args a{};
+  a.src = c->buf[c->cur];
+  a.dst = c->buf[c->cur ^ 1];
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.nz = c->p.nz;
+  a.plane = plane_of(&c->p);
+  a.zwalls = c->p.zbc == CLB3_Z_WALLS;
+  a.shift = c->p.cbbsr_shift;
+  a.r = c->d.r;
+  a.omr = 1.0 - c->d.r;
+  a.gx = c->p.gx;
+  a.gy = c->p.gy;
+  a.gz = c->p.gz;
+  a.sb = c->p.s_b;
+  a.snu = c->d.s_nu;
+  a.sq = c->d.s_q;
+  a.s8 = c->p.s8;
+  return a;
+}
+
+dim3 node_grid(const clb3_params* p) {
+  return dim3((unsigned)((p->nx + clb3::kBX - 1) / clb3::kBX), (unsigned)((p->ny + clb3::kBY - 1) / clb3::kBY),
+              (unsigned)p->nz);
+}
+
+clb_status read_result3(clb3_ctx* c, double* h) {
+  CLB3_HIP(hipMemcpyAsync(h, c->result, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  CLB3_HIP(hipStreamSynchronize(c->stream));
+  return CLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void clb3_params_default(clb3_params* p) {
+  if (!p) return;
+  *p = clb3_params{};
+  p->nx = p->ny = p->nz = 1;
+  p->zbc = CLB3_Z_WALLS;
+  p->init = CLB_INIT_UNIFORM;
+  p->cbbsr_shift = 1;
+  p->kn = 0.1;
+  p->a = 2.0;       // Section 3
+  p->sigma = 1.0;
+  p->A1 = NAN;
+  p->A2 = 0.55;     // Section 3
+  p->r = NAN;
+  p->s_b = 1.1;     // the paper's s3
+  p->s8 = 1.2;      // Section 3
+  p->rho0 = 1.0;
+  p->tq_den = 16.0;
+}
+
+clb_status clb3_derive(const clb3_params* p, clb_derived* out) {
+  if (!out) return fail3(CLB_EINVAL, "out: NULL");
+  return validate3(p, out);
+}
+
+clb_status clb3_workspace_size(const clb3_params* p, size_t* bytes) {
+  if (!bytes) return fail3(CLB_EINVAL, "bytes: NULL");
+  clb_status st = validate3(p, nullptr);
+  if (st != CLB_OK) return st;
+  *bytes = total_bytes(p);
+  return CLB_OK;
+}
+
+clb_status clb3_init(const clb3_params* p, void* d_workspace, size_t bytes, void* hip_stream, clb3_ctx** out) {
+  const clb::TraceRange trace("clb3_init");
+  if (!out) return fail3(CLB_EINVAL, "out: NULL");
+  *out = nullptr;
+  clb_derived d;
+  clb_status st = validate3(p, &d);
+  if (st != CLB_OK) return st;
+  const size_t need = total_bytes(p);
+  if (!d_workspace) return fail3(CLB_EINVAL, "d_workspace: NULL");
+  if (bytes < need) return fail3(CLB_ENOMEM, "workspace: %zu bytes given, %zu needed", bytes, need);
+  if ((st = clb::check_device_ptr(d_workspace, need, "d_workspace")) != CLB_OK) return st;
+  clb3_ctx* c = new (std::nothrow) clb3_ctx();
+  if (!c) return fail3(CLB_ENOMEM, "host context allocation failed");
+  c->p = *p;
+  c->d = d;
+  char* base = static_cast<char*>(d_workspace);
+  c->buf[0] = reinterpret_cast<double*>(base);
+  c->buf[1] = reinterpret_cast<double*>(base + buffer_bytes(p));
+  c->partial = reinterpret_cast<double*>(base + 2 * buffer_bytes(p));
+  c->result = c->partial + clb3::kPartials;
+  c->cur = 0;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->steps = 0;
+  const size_t plane = plane_of(p);
+  clb3::k3_init<<<clb3::blocks_for(plane) * 16, 256, 0, c->stream>>>(c->buf[0], plane, p->rho0,
+                                                                     p->init == CLB_INIT_PERTURBED, p->init_amp, p->seed);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete c;
+    return fail3(CLB_EHIP, "clb3_init: init kernel: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return CLB_OK;
+}
+
+clb_status clb3_step(clb3_ctx* c, int64_t nsteps) {
+  const clb::TraceRange trace("clb3_step");
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  if (nsteps < 0) return fail3(CLB_EINVAL, "nsteps: must be >= 0");
+  const dim3 grid = node_grid(&c->p);
+  const bool force = c->p.gx != 0.0 || c->p.gy != 0.0 || c->p.gz != 0.0;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const clb3::Args a = args_of(c);
+    if (force)
+      clb3::k3_step<true><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
+    else
+      clb3::k3_step<false><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
+    CLB3_HIP(hipGetLastError());
+    c->cur ^= 1;
+    c->steps += 1;
+  }
+  return CLB_OK;
+}
+
+clb_status clb3_steps_done(const clb3_ctx* c, int64_t* h_steps) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  if (!h_steps) return fail3(CLB_EINVAL, "h_steps: NULL");
+  *h_steps = c->steps;
+  return CLB_OK;
+}
+
+clb_status clb3_moments(clb3_ctx* c, double* d_rho, double* d_ux, double* d_uy, double* d_uz) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  const size_t bytes = plane_of(&c->p) * sizeof(double);
+  clb_status st;
+  if (d_rho && (st = clb::check_device_ptr(d_rho, bytes, "d_rho")) != CLB_OK) return st;
+  if (d_ux && (st = clb::check_device_ptr(d_ux, bytes, "d_ux")) != CLB_OK) return st;
+  if (d_uy && (st = clb::check_device_ptr(d_uy, bytes, "d_uy")) != CLB_OK) return st;
+  if (d_uz && (st = clb::check_device_ptr(d_uz, bytes, "d_uz")) != CLB_OK) return st;
+  if (!d_rho && !d_ux && !d_uy && !d_uz) return CLB_OK;
+  clb3::k3_moments<<<node_grid(&c->p), clb3::kBX * clb3::kBY, 0, c->stream>>>(args_of(c), d_rho, d_ux, d_uy, d_uz);
+  CLB3_HIP(hipGetLastError());
+  return CLB_OK;
+}
+
+clb_status clb3_flow_rate(clb3_ctx* c, double* h_Q) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  if (!h_Q) return fail3(CLB_EINVAL, "h_Q: NULL");
+  if (c->p.gx == 0) return fail3(CLB_ESTATE, "clb3_flow_rate: needs gx != 0");
+  const unsigned nb = clb3::blocks_for(plane_of(&c->p));
+  clb3::k3_ux_partial<<<nb, 256, 0, c->stream>>>(args_of(c), c->partial);
+  clb3::k3_sum<<<1, 256, 0, c->stream>>>(c->partial, (int)nb, c->result);
+  CLB3_HIP(hipGetLastError());
+  double su = 0;
+  clb_status st = read_result3(c, &su);
+  if (st != CLB_OK) return st;
+  const double H = (double)c->p.ny, W = (double)c->p.nz;
+  *h_Q = (su / (double)c->p.nx) * std::sqrt(6.0) / (3.0 * c->p.gx * H * H * W);
+  return CLB_OK;
+}
+
+clb_status clb3_get_populations(clb3_ctx* c, double* d_out) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  const size_t bytes = 27 * plane_of(&c->p) * sizeof(double);
+  clb_status st = clb::check_device_ptr(d_out, bytes, "d_out");
+  if (st != CLB_OK) return st;
+  CLB3_HIP(hipMemcpyAsync(d_out, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+  return CLB_OK;
+}
+
+clb_status clb3_set_populations(clb3_ctx* c, const double* d_in) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  const size_t bytes = 27 * plane_of(&c->p) * sizeof(double);
+  clb_status st = clb::check_device_ptr(d_in, bytes, "d_in");
+  if (st != CLB_OK) return st;
+  CLB3_HIP(hipMemcpyAsync(c->buf[c->cur], d_in, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->steps = 0;
+  return CLB_OK;
+}
+
+clb_status clb3_check_finite(clb3_ctx* c, int32_t* h_ok) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  if (!h_ok) return fail3(CLB_EINVAL, "h_ok: NULL");
+  const size_t n = 27 * plane_of(&c->p);
+  const unsigned nb = clb3::blocks_for(n);
+  clb3::k3_nonfinite_partial<<<nb, 256, 0, c->stream>>>(c->buf[c->cur], n, c->partial);
+  clb3::k3_sum<<<1, 256, 0, c->stream>>>(c->partial, (int)nb, c->result);
+  CLB3_HIP(hipGetLastError());
+  double bad = 0;
+  clb_status st = read_result3(c, &bad);
+  if (st != CLB_OK) return st;
+  *h_ok = bad == 0.0 ? 1 : 0;
+  if (!*h_ok) return fail3(CLB_EUNSTABLE, "populations: %.0f non-finite values", bad);
+  return CLB_OK;
+}
+
+clb_status clb3_destroy(clb3_ctx* c) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  delete c;
+  return CLB_OK;
+}
+
+}  // extern "C"

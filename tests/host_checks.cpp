@@ -8,7 +8,7 @@
 #include <cstdio>
 #include <cstring>
 
-#include "clb.h"
+#include "clb3d.h"
 
 #define EXPECT(cond)                                                   \
   do {                                                                 \
@@ -106,6 +106,41 @@ int main() {
   EXPECT(clb_set_pressure_path(nullptr, 0) == CLB_EINVAL);
   EXPECT(clb_set_graph_steps(nullptr, 8) == CLB_EINVAL);
   EXPECT(clb_set_check_every(nullptr, 8) == CLB_EINVAL);
+
+  // 3-D duct step: validation and null handles
+  clb3_params q3;
+  clb3_params_default(&q3);
+  q3.nx = 16;
+  q3.ny = 12;
+  q3.nz = 10;
+  EXPECT(clb3_derive(&q3, &d) == CLB_OK && d.s_nu > 0 && d.s_nu < 2);
+  EXPECT(clb3_workspace_size(&q3, &n) == CLB_OK && n >= 2 * 216 * 16 * 12 * 10);
+  {
+    clb3_params b3 = q3;
+    b3.nz = 0;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3 = q3;
+    b3.cbbsr_shift = 0;   // same-node specular source with walls in z
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3.zbc = CLB3_Z_PERIODIC;
+    EXPECT(clb3_derive(&b3, &d) == CLB_OK);
+    b3 = q3;
+    b3.init = CLB_INIT_LINEAR_RHO;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3 = q3;
+    b3.s_b = 2.0;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3 = q3;
+    b3.kn = -1.0;
+    EXPECT(clb3_workspace_size(&b3, &n) == CLB_EINVAL);
+  }
+  EXPECT(clb3_derive(nullptr, &d) == CLB_EINVAL);
+  EXPECT(clb3_derive(&q3, nullptr) == CLB_EINVAL);
+  EXPECT(clb3_step(nullptr, 1) == CLB_EINVAL);
+  EXPECT(clb3_flow_rate(nullptr, nullptr) == CLB_EINVAL);
+  EXPECT(clb3_destroy(nullptr) == CLB_EINVAL);
+  clb3_ctx* c3 = nullptr;
+  EXPECT(clb3_init(&q3, nullptr, n, nullptr, &c3) == CLB_EINVAL && c3 == nullptr);
   EXPECT(clb_destroy(nullptr) == CLB_EINVAL);
 
   // Kn-sweep batch

@@ -24,7 +24,7 @@ def _declared_symbols():
             with open(os.path.join(HEADER_DIR, fn)) as fh:
                 text = fh.read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-            names |= set(re.findall(r"\b(clb_[a-z_0-9]+)\s*\(", text))
+            names |= set(re.findall(r"\b(clb3?_[a-z_0-9]+)\s*\(", text))
     return sorted(names)
 
 

@@ -12,16 +12,17 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "clb.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 clb = pytest.importorskip("paper_1603_01955_amd.clb")
+clb3d = pytest.importorskip("paper_1603_01955_amd.clb3d")
 
-MIRRORS = {"clb_params": clb.clb_params, "clb_derived": clb.clb_derived}
+MIRRORS = {"clb_params": clb.clb_params, "clb_derived": clb.clb_derived, "clb3_params": clb3d.clb3_params}
 
 
 def _header_fields(name):
     """Field names of `typedef struct name { ... } name;` in declaration order."""
-    text = open(HEADER).read()
+    text = "".join(open(os.path.join(INCLUDE, h)).read() for h in sorted(os.listdir(INCLUDE)) if h.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     m = re.search(r"typedef\s+struct\s+%s\s*\{(.*?)\}\s*%s\s*;" % (name, name), text, flags=re.S)
     assert m, name
@@ -41,7 +42,7 @@ def c_layout(tmp_path_factory):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "clb.h"', "int main(void) {"]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "clb3d.h"', "int main(void) {"]
     for name in MIRRORS:
         lines.append('  printf("%s SIZE %%zu 0\\n", sizeof(%s));' % (name, name))
         for f in _header_fields(name):
@@ -51,7 +52,7 @@ def c_layout(tmp_path_factory):
     d = tmp_path_factory.mktemp("layout")
     src, exe = d / "layout.c", d / "layout"
     src.write_text("\n".join(lines) + "\n")
-    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", INCLUDE, str(src), "-o", str(exe)],
                    check=True, capture_output=True, text=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     layout = {}

@@ -1,0 +1,138 @@
+"""GPU tests of the 3-D duct step (include/clb3d.h) against the 3-D CPU
+reference: element-wise parity on random far-from-equilibrium states over
+ducts and channels of several shapes (walls and edges, one-row and
+one-layer cross-sections, several workgroups along x), the start states,
+the diagnostics, determinism and failure detection."""
+import numpy as np
+import pytest
+import torch
+
+from clb_inputs import uniform_populations_3d
+from oracle import clb3d_ref as D
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+
+
+def _duct(**kw):
+    from paper_1603_01955_amd import Duct
+    return Duct(**kw)
+
+
+def _oracle_params(kw):
+    keys = ("nx", "ny", "nz", "zbc", "kn", "a", "sigma", "A1", "A2", "r", "s_b", "s8", "gx", "gy", "gz", "rho0",
+            "tq_den", "cbbsr_shift")
+    return D.Params3D(**{k: v for k, v in kw.items() if k in keys})
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+CASES = [
+    (dict(nx=16, ny=12, nz=10, kn=0.3, gx=1e-4), 5),                                   # square-ish duct
+    (dict(nx=5, ny=1, nz=7, kn=0.5, gx=1e-4, gy=2e-5, gz=-1e-5, r=0.3), 4),             # one row: both y walls
+    (dict(nx=3, ny=4, nz=1, kn=0.2, gx=1e-4, r=1.0), 4),                                # one layer: both z walls
+    (dict(nx=70, ny=6, nz=5, kn=1.0, gx=1e-4, r=0.0), 3),                               # two blocks in x, specular
+    (dict(nx=9, ny=8, nz=3, zbc="periodic", cbbsr_shift=0, kn=0.4, gx=1e-4), 4),         # channel, same-node source
+    (dict(nx=1, ny=5, nz=6, kn=0.1, gx=1e-4, tq_den=24.0, sigma=0.8), 5),               # one column
+    (dict(nx=4, ny=7, nz=7, kn=2.0), 3),                                                # no force
+]
+
+
+@pytest.mark.parametrize("kw,steps", CASES)
+def test_random_state_parity(kw, steps):
+    P0 = uniform_populations_3d(kw["nx"], kw["ny"], kw["nz"], seed=31)
+    s = _duct(**kw)
+    s.set_populations(torch.from_numpy(P0))
+    s.step(steps)
+    got = s.populations().cpu().numpy()
+    ref = D.run(P0, _oracle_params(kw), steps)
+    assert _rel(got, ref) <= TOL
+    s.close()
+
+
+def test_larger_duct_parity():
+    """130 x 20 x 18: three workgroups along x, five along y, every wall and
+    edge, two steps from a perturbed equilibrium."""
+    kw = dict(nx=130, ny=20, nz=18, kn=0.5, gx=1e-5, init="perturbed", init_amp=1e-3, seed=5)
+    s = _duct(**kw)
+    s.step(2)
+    got = s.populations().cpu().numpy()
+    prm = _oracle_params(kw)
+    ref = D.run(D.init_perturbed(prm, 5, 1e-3), prm, 2)
+    assert _rel(got, ref) <= TOL
+    s.close()
+
+
+@pytest.mark.parametrize("init", ["uniform", "perturbed"])
+def test_start_states(init):
+    kw = dict(nx=6, ny=5, nz=4, kn=0.2, rho0=1.1, init=init, init_amp=1e-3, seed=11)
+    s = _duct(**kw)
+    got = s.populations().cpu().numpy()
+    prm = _oracle_params(kw)
+    ref = D.init_perturbed(prm, 11, 1e-3) if init == "perturbed" else D.init_uniform(prm)
+    assert np.max(np.abs(got - ref)) <= 1e-15
+    s.close()
+
+
+def test_moments_and_flow_rate():
+    kw = dict(nx=8, ny=9, nz=7, kn=0.3, gx=1e-4, gz=1e-5)
+    P0 = uniform_populations_3d(8, 9, 7, seed=12)
+    s = _duct(**kw)
+    s.set_populations(torch.from_numpy(P0))
+    s.step(3)
+    prm = _oracle_params(kw)
+    P = D.run(P0, prm, 3)
+    rho, u = D.moments(P, prm)
+    got = [t.cpu().numpy() for t in s.moments()]
+    assert np.max(np.abs(got[0] - rho)) <= 1e-12
+    for k in range(3):
+        assert np.max(np.abs(got[k + 1] - u[k])) <= 1e-12
+    assert abs(s.flow_rate() / D.flow_rate_Q(P, prm) - 1) <= 1e-10
+    s.close()
+
+
+def test_square_duct_flow_matches_reference_over_many_steps():
+    """A force-driven square duct from rest, 1500 steps (most of the way to
+    steady state): populations and flow rate within the parity bound."""
+    kw = dict(nx=2, ny=8, nz=8, kn=0.3, gx=1e-6)
+    s = _duct(**kw)
+    s.step(1500)
+    prm = _oracle_params(kw)
+    ref = D.run(D.init_uniform(prm), prm, 1500)
+    assert _rel(s.populations().cpu().numpy(), ref) <= TOL
+    assert abs(s.flow_rate() / D.flow_rate_Q(ref, prm) - 1) <= 1e-8
+    s.close()
+
+
+def test_deterministic_and_resumable():
+    kw = dict(nx=40, ny=10, nz=9, kn=0.4, gx=1e-4, init="perturbed", init_amp=1e-3, seed=3)
+    a = _duct(**kw).step(6).populations()
+    b = _duct(**kw).step(6).populations()
+    assert torch.equal(a, b)
+    s = _duct(**kw).step(2)
+    mid = s.populations()
+    t = _duct(**kw)
+    t.set_populations(mid)
+    t.step(4)
+    assert t.steps_done == 4
+    assert torch.equal(t.populations(), a)
+
+
+def test_failure_detection():
+    s = _duct(nx=6, ny=5, nz=4, kn=0.3, gx=1e-4)
+    assert s.check_finite()
+    P = s.populations()
+    P[7, 2, 3, 1] = float("nan")
+    s.set_populations(P)
+    assert not s.check_finite()
+    s.step(2)
+    assert not s.check_finite()

@@ -370,6 +370,9 @@ def test_graph_replay_identical(graph_steps):
     (dict(nx=90, ny=70, xbc="pressure", kn=0.1, p_ratio=2.0), 4),             # taller: one step per launch
     (dict(nx=100, ny=64, xbc="pressure", kn=0.1, p_ratio=2.0), 4),
     (dict(nx=9000, ny=12, xbc="pressure", kn=0.2, p_ratio=1.5), 5),           # 32 columns
+    (dict(nx=121, ny=65, kn=0.6, gx=1e-4, gy=1e-5), 5),            # ragged tiles both ways
+    (dict(nx=180, ny=2, kn=0.4, gx=1e-4, r=1.0), 4),               # two rows, pure bounce-back
+    (dict(nx=250, ny=130, kn=0.3, gx=1e-5, cbbsr_shift=0, forcing=1), 7),
 ])
 def test_several_steps_per_launch_bitwise(kw, steps):
     """Two, three or four steps per launch (the earlier ones in LDS) give the
