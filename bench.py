@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched Kn-sweep comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
-    ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "msweep", "adjoint"), default="all",
+    ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "msweep", "adjoint", "duct"), default="all",
                     help="run one part alone (step: the periodic step only; sweep / pressure / msweep / adjoint: "
                          "that measurement only, printed as its own JSON line) -- for profiling runs")
     ap.add_argument("--no-loop-baseline", action="store_true",
@@ -280,6 +280,37 @@ def pressure_step(nx=4000, ny=40, steps=200000):
             "massflow_spread": float((m_col.max() - m_col.min()) / abs(m))}
 
 
+def duct3d(steps=100, warmup=5):
+    """The 3-D extension (rectangular microduct, D3Q27, 512 x 256 x 256,
+    Kn = 0.5 of the height, g = 1e-6, seeded perturbed start): time per step
+    with HIP events on the solver's stream; one step reads and writes every
+    population once, 432 B per node update."""
+    import torch
+    from clb_inputs import WORKLOADS
+    from paper_1603_01955_amd import Duct
+    w = dict(WORKLOADS["duct_512x256x256"])
+    s = Duct(**w)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nodes = s.nx * s.ny * s.nz
+    ok = s.check_finite()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    gbs = 432.0 * nodes / (ms * 1e-3) / 1e9
+    return {"workload": "duct_512x256x256", "steps": steps, "ms_per_step": round(ms, 4), "finite": ok,
+            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "unit_bytes": "432 B per node update"}}
+
+
 def forcing_variant(steps=200, warmup=10):
     """The source with third-order force moments (clb_params.forcing = 1):
     the periodic step's throughput on the benchmark grid, and the batched Kn
@@ -433,6 +464,9 @@ def main():
     if args.part == "adjoint":
         print(json.dumps({"adjoint": adjoint_calibration()}), flush=True)
         return
+    if args.part == "duct":
+        print(json.dumps({"duct3d": duct3d()}), flush=True)
+        return
     import torch
     from paper_1603_01955_amd import Solver
 
@@ -519,6 +553,7 @@ def main():
                                                  baselines=not args.no_loop_baseline)
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_calibration()
+    rec["duct3d"] = duct3d()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec), flush=True)

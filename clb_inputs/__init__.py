@@ -86,7 +86,7 @@ WORKLOADS = {
     # Long channel for the adjoint calibration, L/H = 100.
     "long_2000x20": dict(nx=2000, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, steps=2000),
     # Rectangular microduct (3-D extension): square cross-section, force driven.
-    "duct_256x128x128": dict(nx=256, ny=128, nz=128, kn=0.5, gx=1e-6, init="perturbed", init_amp=1e-4,
+    "duct_512x256x256": dict(nx=512, ny=256, nz=256, kn=0.5, gx=1e-6, init="perturbed", init_amp=1e-4,
                              seed=2468),
     # Mass-flow sweep: 16 long channels, L/H = 100, Kn_out 0.01 .. 1.
     "mass_flow_sweep_16x2000x20": dict(nx=2000, ny=20, xbc="pressure", p_ratio=MASS_FLOW_P_RATIO,
