@@ -43,6 +43,8 @@ def parse():
                     help="msweep: step cap per channel (lower it for traced runs)")
     ap.add_argument("--steps-per-launch", type=int, default=2,
                     help="periodic step: steps per launch (1-4; the earlier ones kept in LDS)")
+    ap.add_argument("--pressure-steps", type=int, default=200000,
+                    help="pressure: steps of the long-channel run (2e5 is the paper's run; fewer for traced runs)")
     ap.add_argument("--block-x", type=int, default=1024)
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -455,7 +457,7 @@ def main():
                           "kn_minimum": kn_minimum()}), flush=True)
         return
     if args.part == "pressure":
-        print(json.dumps({"pressure_step": pressure_step()}), flush=True)
+        print(json.dumps({"pressure_step": pressure_step(steps=args.pressure_steps)}), flush=True)
         return
     if args.part == "msweep":
         print(json.dumps({"mass_flow_sweep": mass_flow_sweep(max_steps=args.msweep_max_steps,
