@@ -192,16 +192,18 @@ clb_status clb_set_check_every(clb_ctx* c, int64_t check_every);
  * xcd_remap = 1 to map consecutive row segments onto the same XCD. */
 clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap);
 
-/* Temporal blocking (tuning): steps = 2 (default) advances two steps per
- * launch -- each workgroup computes the first step for its tile and a
- * one-node halo into LDS, then the second step from LDS -- so a node update
- * moves about 79 instead of 144 bytes (periodic mode, nx >= 64; narrower
- * grids step one at a time); in pressure mode the
- * same for channels of at most 48 rows on the column-kernel path (the edge
- * workgroups rebuild the ghost columns from the LDS values).  steps = 3 or 4
- * (periodic mode; pressure mode takes 2) keep more steps in LDS; a shorter
- * remainder of clb_step takes fewer.  steps = 1: one step per launch.  All
- * give bitwise the same populations.  CLB_EINVAL for other values. */
+/* Temporal blocking (tuning).  Periodic mode (nx >= 64; narrower grids step
+ * one at a time): steps = k in 2..4 advances k steps per launch -- each
+ * workgroup computes the first step for its 64-column tile and a
+ * (k - 1)-node halo into LDS, the next ones from LDS on a region one node
+ * smaller each time, and writes only the last -- so a node update moves
+ * about 144 / k bytes plus the halo reads (k = 3, the default: about 59
+ * bytes; k = 2: 79).  Pressure mode takes two steps per launch for any
+ * steps >= 2, on channels of at most 48 rows on the column-kernel path (the
+ * edge workgroups rebuild the ghost columns from the LDS values).  A
+ * shorter remainder of clb_step takes fewer.  steps = 1: one step per
+ * launch.  All give bitwise the same populations.  CLB_EINVAL for other
+ * values. */
 clb_status clb_set_steps_per_launch(clb_ctx* c, int32_t steps);
 
 /* Pressure-mode kernel choice (tuning; Section 3.2 step): 0 = by grid size
@@ -431,6 +433,16 @@ clb_status clb_adjoint_vjp_step(clb_adjoint* a, const double* d_P, const double*
 
 /* Release the host context (synchronises the stream first). */
 clb_status clb_adjoint_destroy(clb_adjoint* a);
+
+/* Measurement support (not part of the method): a plain device-to-device
+ * copy of `bytes` bytes, one 16-byte load and store per thread, enqueued on
+ * hip_stream.  Timed, it gives the HBM bandwidth a streaming kernel reaches
+ * on the GPU at hand -- the practical ceiling beside the 8 TB/s peak against
+ * which the step kernels are read -- and its FETCH_SIZE / WRITE_SIZE
+ * counters calibrate the traffic counters (exactly `bytes` read and written).
+ * d_src, d_dst: device memory, 16-byte aligned, not overlapping; bytes a
+ * multiple of 16 (0: nothing to do).  CLB_EINVAL otherwise. */
+clb_status clb_hbm_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* clb_last_error(void);

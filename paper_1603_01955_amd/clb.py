@@ -74,6 +74,7 @@ _SIGNATURES = {
     "clb_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "clb_massflow_noalloc": (ctypes.c_int, [ctypes.POINTER(clb_params), ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "clb_hbm_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "clb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -178,7 +179,7 @@ class Solver:
     def set_launch(self, block_x=1024, xcd_remap=1):
         check(lib().clb_set_launch(self._ctx, int(block_x), int(xcd_remap)))
 
-    def set_steps_per_launch(self, steps=2):
+    def set_steps_per_launch(self, steps=3):
         check(lib().clb_set_steps_per_launch(self._ctx, int(steps)))
 
     def set_pressure_path(self, path=0):
@@ -261,6 +262,18 @@ def massflow_noalloc(params, P, m_col=None, stream=None):
     check(lib().clb_massflow_noalloc(ctypes.byref(params), _ptr(P), _ptr(m_col), ctypes.byref(mean),
                                      ctypes.c_void_p(stream.cuda_stream)))
     return mean.value
+
+
+def hbm_copy(src, dst, stream=None):
+    """Plain device copy of src into dst (same byte size, both CUDA tensors),
+    the library's HBM ceiling probe, enqueued on ``stream`` (default: the
+    current stream of src's device)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device)
+    check(lib().clb_hbm_copy(_ptr(src), _ptr(dst), nbytes, ctypes.c_void_p(stream.cuda_stream)))
 
 
 _BATCH_SIGNATURES = {

@@ -317,7 +317,7 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->pressure_path = 0;
   c->cus = clb::device_cus();
   c->step_lds = 0;
-  c->steps_per_launch = 2;
+  c->steps_per_launch = 3;
   {
     hipError_t e = clb::periodic_step_lds(c->block_x, &c->step_lds);
     if (e == hipSuccess) e = clb::stepk_setup();
@@ -638,6 +638,21 @@ clb_status clb_destroy(clb_ctx* c) {
   drop_graphs(c);
   if (c->capture) (void)hipStreamDestroy(c->capture);
   delete c;
+  return CLB_OK;
+}
+
+clb_status clb_hbm_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream) {
+  if (bytes % 16 != 0) return fail(CLB_EINVAL, "bytes: %zu is not a multiple of 16", bytes);
+  if (!d_src || !d_dst) return fail(CLB_EINVAL, "d_src / d_dst: NULL");
+  if (((uintptr_t)d_src & 15) != 0 || ((uintptr_t)d_dst & 15) != 0)
+    return fail(CLB_EINVAL, "d_src / d_dst: must be 16-byte aligned");
+  if (bytes == 0) return CLB_OK;
+  clb_status st = check_device_range(d_src, bytes, "d_src");
+  if (st != CLB_OK) return st;
+  if ((st = check_device_range(d_dst, bytes, "d_dst")) != CLB_OK) return st;
+  const uintptr_t s0 = (uintptr_t)d_src, t0 = (uintptr_t)d_dst;
+  if (s0 < t0 + bytes && t0 < s0 + bytes) return fail(CLB_EINVAL, "d_src / d_dst: ranges overlap");
+  CLB_HIP(clb::launch_copy16(d_src, d_dst, bytes / 16, static_cast<hipStream_t>(hip_stream)));
   return CLB_OK;
 }
 

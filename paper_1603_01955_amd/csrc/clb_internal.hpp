@@ -159,6 +159,8 @@ bool periodic_multi_step_ok(const StepArgs& a);   // nx >= 64
 bool pressure_two_step_ok(const StepArgs& a);
 hipError_t launch_step2_pressure(const StepArgs& a, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
+// Plain copy of n16 16-byte words (HBM ceiling probe).
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t st);
 hipError_t launch_moments(const DiagArgs& a, hipStream_t st);
 hipError_t launch_column_sums(const DiagArgs& a, hipStream_t st);
 // The same sums over populations in the ABI layout [9][ny][nx] (a.src and

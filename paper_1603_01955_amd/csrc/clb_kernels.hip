@@ -58,8 +58,8 @@ __global__ __launch_bounds__(1024) void k_step_periodic(StepArgs a) {
 
 // ---------------------------------------------------------------------------
 // K1b: K periodic steps in one launch (temporal blocking).  A workgroup of
-// (64 + 2(K - 1)) x H threads owns a tile of 64 columns x (H - 2(K - 1))
-// rows.  The first step is computed for the tile and a (K - 1)-node halo
+// 1024 threads owns a tile of 64 columns x (H - 2(K - 1)) rows.  The first
+// step is computed for the tile and a (K - 1)-node halo
 // around it (rows beyond a wall are skipped) and kept in LDS; each further
 // step gathers from LDS for a region one node smaller on every side and
 // overwrites LDS in place (barriers between reading and writing); the last
@@ -95,12 +95,42 @@ constexpr int tile_w() {
   return kTileX + 2 * (K - 1);
 }
 
-// Occupancy target: two steps fit 8 waves per SIMD (64 VGPRs, no spill), so
-// two workgroups share a CU; three or four steps would spill at that target
-// and keep their natural 90-102 VGPRs (4 waves per SIMD).
+// Threads of a multi-step workgroup: 16 wavefronts, enough for the first
+// step's region ((64 + 2(K - 1)) x H <= 1024 nodes for the shipped H).
+constexpr int kStepKThreads = 1024;
+
+// Node of step k's region (k = 1 .. K: columns k - 1 .. W - k, rows
+// k - 1 .. H - k of the LDS tile) taken by thread t.  The region's share of
+// the tile's 64 columns comes first, one row per wavefront, so that every
+// wavefront reads and writes whole aligned 512-byte row pieces of each
+// direction slot and finds the same wall rule on all its lanes; the
+// K - k halo columns on either side of those rows follow.  False for
+// threads beyond the region.
+template <int K, int H>
+__device__ __forceinline__ bool region_node(int k, int t, int& lx, int& ly) {
+  const int hw = K - k;
+  const int rows = H - 2 * (k - 1);
+  const int main = kTileX * rows;
+  if (t < main) {
+    lx = (K - 1) + (t & (kTileX - 1));
+    ly = (k - 1) + t / kTileX;
+    return true;
+  }
+  const int j = t - main;
+  if (j >= 2 * hw * rows) return false;
+  const int r = j / (2 * hw), c = j - r * 2 * hw;
+  ly = (k - 1) + r;
+  lx = c < hw ? (k - 1) + c : (K - 1) + kTileX + (c - hw);
+  return true;
+}
+
+// Occupancy target: 8 waves per SIMD (at most 64 VGPRs; two to four steps
+// need 54-58 with no spill), so two workgroups (and their 71-74 KB of LDS)
+// share a CU.
 template <bool FORCE, bool THIRD, int K, int H>
-__global__ __launch_bounds__(tile_w<K>() * H, K == 2 ? 8 : 4) void k_stepk_periodic(StepArgs a) {
+__global__ __launch_bounds__(kStepKThreads, 8) void k_stepk_periodic(StepArgs a) {
   constexpr int W = tile_w<K>();
+  static_assert(W * H <= kStepKThreads, "first-step region larger than the workgroup");
   extern __shared__ double s1[];   // [9][H][W]
   const int nx = a.g.nx, ny = a.g.ny;
   const int ntx = (nx + kTileX - 1) / kTileX;
@@ -111,44 +141,55 @@ __global__ __launch_bounds__(tile_w<K>() * H, K == 2 ? 8 : 4) void k_stepk_perio
   const int bands = min(kStripBands, nty - strip * kStripBands);   // the last strip may be shorter
   const int bx = rb / bands, by = strip * kStripBands + (rb - bx * bands);
   const int x0 = bx * kTileX - (K - 1), y0 = by * (H - 2 * (K - 1)) - (K - 1);   // LDS (0, 0)
-  const int lx = threadIdx.x, ly = threadIdx.y;
-  const int x = x0 + lx, y = y0 + ly;
-  const bool row = y >= 0 && y < ny;
+  const int t = threadIdx.x;
   const Rates s{a.s3, a.snu, a.sq, a.s8};
-  if (row) {
-    int xw = x % nx;                 // x >= -(K - 1)
-    if (xw < 0) xw += nx;
-    const Gather<0, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
-    double f[9];
-    gat(xw, y, f);
-    collide<FORCE, THIRD>(f, a.gx, a.gy, s);
+  {
+    int lx, ly;
+    if (region_node<K, H>(1, t, lx, ly)) {
+      const int x = x0 + lx, y = y0 + ly;
+      if (y >= 0 && y < ny) {          // rows beyond a wall are skipped
+        int xw = x % nx;               // x >= -(K - 1)
+        if (xw < 0) xw += nx;
+        const Gather<0, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+        double f[9];
+        gat(xw, y, f);
+        collide<FORCE, THIRD>(f, a.gx, a.gy, s);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) s1[(i * H + ly) * W + lx] = f[i];
+        for (int i = 0; i < 9; ++i) s1[(i * H + ly) * W + lx] = f[i];
+      }
+    }
   }
   const Gather<3, TileView> lds{{s1, x0, y0, W, H, nx, ny}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
   // intermediate steps: gather and collide, barrier, overwrite in place
 #pragma unroll
-  for (int k = 1; k < K - 1; ++k) {
-    const bool inside = row && lx >= k && lx < W - k && ly >= k && ly < H - k;
+  for (int k = 2; k < K; ++k) {
+    int lx, ly;
+    bool in = region_node<K, H>(k, t, lx, ly);
+    const int x = x0 + lx, y = y0 + ly;
+    in = in && y >= 0 && y < ny;
     __syncthreads();
     double f[9];
-    if (inside) {
+    if (in) {
       lds(x, y, f);
       collide<FORCE, THIRD>(f, a.gx, a.gy, s);
     }
     __syncthreads();
-    if (inside) {
+    if (in) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) s1[(i * H + ly) * W + lx] = f[i];
     }
   }
   // last step: the tile itself, written to HBM
   __syncthreads();
-  if (row && lx >= K - 1 && lx < W - (K - 1) && ly >= K - 1 && ly < H - (K - 1) && x < nx) {
-    double f[9];
-    lds(x, y, f);
-    collide<FORCE, THIRD>(f, a.gx, a.gy, s);
-    store9(a.dst, a.g, x, y, f);
+  int lx, ly;
+  if (region_node<K, H>(K, t, lx, ly)) {
+    const int x = x0 + lx, y = y0 + ly;
+    if (y >= 0 && y < ny && x < nx) {
+      double f[9];
+      lds(x, y, f);
+      collide<FORCE, THIRD>(f, a.gx, a.gy, s);
+      store9(a.dst, a.g, x, y, f);
+    }
   }
 }
 
@@ -914,7 +955,7 @@ hipError_t launch_stepk_t(const StepArgs& a, hipStream_t st) {
   constexpr int H = stepk_h<K>();
   const size_t tiles =
       (size_t)((a.g.nx + kTileX - 1) / kTileX) * (size_t)((a.g.ny + H - 2 * K + 1) / (H - 2 * (K - 1)));
-  const dim3 grid((unsigned)tiles), block(tile_w<K>(), H);
+  const dim3 grid((unsigned)tiles), block(kStepKThreads);
   const size_t lds = stepk_lds<K>();
   if ((a.gx != 0.0 || a.gy != 0.0) && a.forcing)
     k_stepk_periodic<true, true, K, H><<<grid, block, lds, st>>>(a);
@@ -944,6 +985,23 @@ hipError_t launch_stepk(const StepArgs& a, int k, hipStream_t st) {
   if (k == 4) return launch_stepk_t<4>(a, st);
   if (k == 3) return launch_stepk_t<3>(a, st);
   return launch_stepk_t<2>(a, st);
+}
+
+namespace {
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+}  // namespace
+
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t st) {
+  if (n16 == 0) return hipSuccess;
+  const size_t blocks = (n16 + 255) / 256;
+  k_copy16<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(static_cast<const u32x4*>(src), static_cast<u32x4*>(dst),
+                                                          n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const InitArgs& a, hipStream_t st) {

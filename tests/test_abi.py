@@ -154,6 +154,20 @@ def test_null_arguments(lib):
     assert out.value is None
 
 
+def test_hbm_copy_argument_checks(lib):
+    """The copy probe rejects sizes that are not whole 16-byte words, NULL
+    and misaligned pointers before touching the GPU, and a zero-byte copy is
+    a no-op."""
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)
+    assert lib.clb_hbm_copy(a, b, 24, None) == clb.CLB_EINVAL
+    assert "multiple of 16" in lib.clb_last_error().decode()
+    assert lib.clb_hbm_copy(None, b, 32, None) == clb.CLB_EINVAL
+    assert lib.clb_hbm_copy(a, None, 32, None) == clb.CLB_EINVAL
+    assert lib.clb_hbm_copy(ctypes.c_void_p((1 << 20) + 8), b, 32, None) == clb.CLB_EINVAL
+    assert "16-byte aligned" in lib.clb_last_error().decode()
+    assert lib.clb_hbm_copy(a, b, 0, None) == clb.CLB_OK
+
+
 def test_batch_validation(lib):
     """Batched channels are periodic, start from a uniform or perturbed state,
     and the workspace holds at least every channel's populations."""

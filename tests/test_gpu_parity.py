@@ -306,21 +306,42 @@ def test_full_size_periodic_sampled():
     s.close()
 
 
-def test_full_size_two_steps_per_launch_equal_one_step():
-    """The benchmarked launch configuration itself: 32768 x 2048, two steps
-    per launch (the default, as bench.py times it) against one step per
-    launch -- whose single steps the test above pins to the reference at
-    this size -- after 21 steps (ten two-step launches and a one-step
-    remainder): every population equal bit for bit."""
+@pytest.mark.parametrize("spl", [3, 2])
+def test_full_size_multi_step_launches_equal_one_step(spl):
+    """The benchmarked launch configuration itself: 32768 x 2048, three steps
+    per launch (the default, as bench.py times it) or two, against one step
+    per launch -- whose single steps the test above pins to the reference at
+    this size -- after 21 steps (seven three-step launches; ten two-step
+    launches and a one-step remainder): every population equal bit for bit."""
     kw = dict(nx=32768, ny=2048, kn=1.0, gx=1e-7, init="perturbed", init_amp=1e-4, seed=12345)
-    two = _solver(**kw)
-    two.step(21)
+    multi = _solver(**kw)
+    if spl != 3:
+        multi.set_steps_per_launch(spl)
+    multi.step(21)
     one = _solver(**kw)
     one.set_steps_per_launch(1)
     one.step(21)
-    assert torch.equal(two.populations(), one.populations())
-    two.close()
+    assert torch.equal(multi.populations(), one.populations())
+    multi.close()
     one.close()
+
+
+def test_hbm_copy_probe():
+    """The copy kernel bench.py times for the HBM ceiling copies every byte
+    (a ragged size: not a whole number of workgroups) and rejects overlapping
+    ranges and host memory."""
+    from paper_1603_01955_amd import clb
+    src = torch.randint(-2 ** 62, 2 ** 62, (3 * 4096 + 6,), dtype=torch.int64, device="cuda")
+    dst = torch.zeros_like(src)
+    clb.hbm_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    lib = clb.lib()
+    n = src.numel() * 8
+    assert lib.clb_hbm_copy(clb._ptr(src), clb._ptr(src[2:]), n - 16, None) == clb.CLB_EINVAL
+    assert "overlap" in lib.clb_last_error().decode()
+    host = torch.zeros(64, dtype=torch.int64).pin_memory()
+    assert lib.clb_hbm_copy(clb._ptr(src), clb._ptr(host), 512, None) == clb.CLB_EINVAL
 
 
 def test_deterministic_and_resumable():
