@@ -43,6 +43,8 @@ def parse():
                     help="msweep: step cap per channel (lower it for traced runs)")
     ap.add_argument("--steps-per-launch", type=int, default=3,
                     help="periodic step: steps per launch (1-4; the earlier ones kept in LDS)")
+    ap.add_argument("--channel-steps-per-launch", type=int, default=None,
+                    help="pressure and msweep parts: steps per launch (default: the library's)")
     ap.add_argument("--pressure-steps", type=int, default=200000,
                     help="pressure: steps of the long-channel run (2e5 is the paper's run; fewer for traced runs)")
     ap.add_argument("--block-x", type=int, default=1024)
@@ -250,7 +252,7 @@ def adjoint_calibration(T=2000, K=45, repeats=3):
             "backward_over_forward": round(b / f, 3)}
 
 
-def pressure_step(nx=4000, ny=40, steps=200000):
+def pressure_step(nx=4000, ny=40, steps=200000, spl=None):
     """The long pressure-driven channel of Section 3.2 (L/H = 100, 4000 x 40,
     p_in/p_out = 2, Kn_out = 0.1, linear-density start) run for its 2e5
     steps: time per step with HIP events on the solver's stream over the
@@ -261,6 +263,8 @@ def pressure_step(nx=4000, ny=40, steps=200000):
     import torch
     from paper_1603_01955_amd import Solver
     s = Solver(nx=nx, ny=ny, xbc="pressure", kn=0.1, p_ratio=2.0, init="linear_rho")
+    if spl is not None:
+        s.set_steps_per_launch(spl)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -344,7 +348,7 @@ def forcing_variant(steps=200, warmup=10):
             "kn_minimum": km}
 
 
-def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2000, baselines=True):
+def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2000, baselines=True, spl=None):
     """Mass-flow study of Section 3.2: 16 long channels (2000 x 20, L/H = 100,
     p_in/p_out = 1.8, sigma = 0.93, Kn_out log-spaced 0.01-1, linear-density
     start) advanced together by the pressure batch, each to steady state
@@ -374,10 +378,22 @@ def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e3 / step_probe
 
-    pb = PressureBatch(params)
+    def batch():
+        b = PressureBatch(params)
+        if spl is not None:
+            b.set_steps_per_launch(spl)
+        return b
+
+    def single(p):
+        one = Solver(params=p)
+        if spl is not None:
+            one.set_steps_per_launch(spl)
+        return one
+
+    pb = batch()
     us_batch = per_step_us(pb)
     pb.close()
-    pb = PressureBatch(params)
+    pb = batch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps_b, conv = pb.run(max_steps, check_every, tol)        # synchronises
@@ -393,7 +409,7 @@ def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2
            "batched_algorithmic_gbs": round(BYTES_PER_NODE * nodes / us_batch / 1e3, 1)}
     if not baselines:
         return out
-    s = Solver(params=params[0])
+    s = single(params[0])
     s.set_graph_steps(step_probe // 10)
     us_single = per_step_us(s)
     s.close()
@@ -403,7 +419,7 @@ def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2
     steps_l = []
     t0 = time.perf_counter()
     for p in params:
-        s = Solver(params=p)
+        s = single(p)
         s.set_graph_steps(check_every)
         prev, n = float("nan"), 0
         while n < max_steps:
@@ -460,11 +476,13 @@ def main():
                           "kn_minimum": kn_minimum()}), flush=True)
         return
     if args.part == "pressure":
-        print(json.dumps({"pressure_step": pressure_step(steps=args.pressure_steps)}), flush=True)
+        print(json.dumps({"pressure_step": pressure_step(steps=args.pressure_steps,
+                                                         spl=args.channel_steps_per_launch)}), flush=True)
         return
     if args.part == "msweep":
         print(json.dumps({"mass_flow_sweep": mass_flow_sweep(max_steps=args.msweep_max_steps,
-                                                             baselines=not args.no_loop_baseline)}), flush=True)
+                                                             baselines=not args.no_loop_baseline,
+                                                             spl=args.channel_steps_per_launch)}), flush=True)
         return
     if args.part == "adjoint":
         print(json.dumps({"adjoint": adjoint_calibration()}), flush=True)

@@ -192,18 +192,17 @@ clb_status clb_set_check_every(clb_ctx* c, int64_t check_every);
  * xcd_remap = 1 to map consecutive row segments onto the same XCD. */
 clb_status clb_set_launch(clb_ctx* c, int32_t block_x, int32_t xcd_remap);
 
-/* Temporal blocking (tuning).  Periodic mode (nx >= 64; narrower grids step
- * one at a time): steps = k in 2..4 advances k steps per launch -- each
- * workgroup computes the first step for its 64-column tile and a
- * (k - 1)-node halo into LDS, the next ones from LDS on a region one node
- * smaller each time, and writes only the last -- so a node update moves
- * about 144 / k bytes plus the halo reads (k = 3, the default: about 59
- * bytes; k = 2: 79).  Pressure mode takes two steps per launch for any
- * steps >= 2, on channels of at most 48 rows on the column-kernel path (the
- * edge workgroups rebuild the ghost columns from the LDS values).  A
- * shorter remainder of clb_step takes fewer.  steps = 1: one step per
- * launch.  All give bitwise the same populations.  CLB_EINVAL for other
- * values. */
+/* Temporal blocking (tuning): steps = k in 2..4 advances k steps per launch
+ * -- each workgroup computes the first step for its tile and a (k - 1)-node
+ * halo into LDS, the next ones from LDS on a region one node smaller each
+ * time, and writes only the last.  Periodic mode (nx >= 64; narrower grids
+ * step one at a time): 64-column tiles, a node update moves about 144 / k
+ * bytes plus the halo reads (k = 3, the default: about 59 bytes).  Pressure
+ * mode (channels of at most 48 rows on the column-kernel path; others step
+ * one at a time): tiles of whole columns, the edge workgroups rebuilding the
+ * ghost columns from the LDS values of each step; default k = 4.  A shorter
+ * remainder of clb_step takes fewer.  steps = 1: one step per launch.  All
+ * give bitwise the same populations.  CLB_EINVAL for other values. */
 clb_status clb_set_steps_per_launch(clb_ctx* c, int32_t steps);
 
 /* Pressure-mode kernel choice (tuning; Section 3.2 step): 0 = by grid size
@@ -337,10 +336,11 @@ clb_status clb_pbatch_step(clb_pbatch* b, int64_t nsteps);
 clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every, double tol,
                           int64_t* h_steps, int32_t* h_converged);
 
-/* Steps per launch (tuning): 2 (default) advances the running channels two
- * steps per launch (first step kept in LDS, as clb_set_steps_per_launch in
- * pressure mode) where the grid allows it (ny <= 48, column kernel), 1 one
- * step per launch.  Bitwise the same populations.  CLB_EINVAL otherwise. */
+/* Steps per launch (tuning): k = 2..4 (default 4) advances the running
+ * channels k steps per launch (the steps before the last kept in LDS, as
+ * clb_set_steps_per_launch in pressure mode) where the grid allows it
+ * (ny <= 48, column kernel), 1 one step per launch.  Bitwise the same
+ * populations.  CLB_EINVAL otherwise. */
 clb_status clb_pbatch_set_steps_per_launch(clb_pbatch* b, int32_t steps);
 
 /* Kernel choice (tuning): 0 = by total size (default; the row form from

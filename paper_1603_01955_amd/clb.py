@@ -179,7 +179,7 @@ class Solver:
     def set_launch(self, block_x=1024, xcd_remap=1):
         check(lib().clb_set_launch(self._ctx, int(block_x), int(xcd_remap)))
 
-    def set_steps_per_launch(self, steps=3):
+    def set_steps_per_launch(self, steps):
         check(lib().clb_set_steps_per_launch(self._ctx, int(steps)))
 
     def set_pressure_path(self, path=0):
@@ -449,7 +449,7 @@ class PressureBatch:
         """0: by total size, 1: column kernel, 2: row kernel."""
         check(lib().clb_pbatch_set_path(self._h, int(path)))
 
-    def set_steps_per_launch(self, steps=2):
+    def set_steps_per_launch(self, steps=4):
         check(lib().clb_pbatch_set_steps_per_launch(self._h, int(steps)))
 
     def massflow(self):

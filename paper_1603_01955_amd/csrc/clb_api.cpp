@@ -164,7 +164,7 @@ struct clb_ctx {
   double* col_rates;     // pressure mode, large grids: per-column s_nu, s_q
   double* ghosts;        // pressure mode, large grids: ghost columns
   int xcd_remap;
-  int steps_per_launch;  // periodic mode: steps per launch, 1-4 (those before the last kept in LDS)
+  int steps_per_launch;  // steps per launch, 1-4 (those before the last kept in LDS)
   int64_t check_every;   // clb_step checks for non-finite populations at multiples of this step count (0: never)
   // optional hipGraph of graph_steps steps, one per starting buffer
   int graph_steps;
@@ -317,7 +317,7 @@ clb_status clb_init(const clb_params* p, void* d_workspace, size_t bytes, void* 
   c->pressure_path = 0;
   c->cus = clb::device_cus();
   c->step_lds = 0;
-  c->steps_per_launch = 3;
+  c->steps_per_launch = p->xbc == CLB_X_PERIODIC ? 3 : 4;
   {
     hipError_t e = clb::periodic_step_lds(c->block_x, &c->step_lds);
     if (e == hipSuccess) e = clb::stepk_setup();
@@ -364,14 +364,15 @@ void drop_graphs(clb_ctx* c) {
 }
 
 // Enqueue n steps on stream st starting from buffer parity *cur (updated):
-// periodic mode (nx >= 64) steps_per_launch steps per launch while that many
-// remain, then the remainder in one launch; pressure mode two per launch
-// where the two-step kernel applies and steps_per_launch >= 2; else one.
+// steps_per_launch steps per launch while that many remain, then the
+// remainder in one launch, where the multi-step kernels apply (periodic
+// mode: nx >= 64; pressure mode: at most 48 rows on the column path); else
+// one per launch.
 hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) {
   const bool periodic = c->p.xbc == CLB_X_PERIODIC;
   int k = c->steps_per_launch;
   if (periodic && !clb::periodic_multi_step_ok(step_args(c))) k = 1;
-  if (!periodic) k = (k >= 2 && clb::pressure_two_step_ok(step_args(c))) ? 2 : 1;
+  if (!periodic && !clb::pressure_two_step_ok(step_args(c))) k = 1;
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {
     clb::StepArgs a = step_args(c);
@@ -379,7 +380,7 @@ hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) 
     a.dst = c->buf[*cur ^ 1];
     const int m = n < k ? (int)n : k;
     if (m >= 2) {
-      e = periodic ? clb::launch_stepk(a, m, st) : clb::launch_step2_pressure(a, st);
+      e = periodic ? clb::launch_stepk(a, m, st) : clb::launch_stepk_pressure(a, m, st);
       n -= m;
     } else {
       e = clb::launch_step(a, c->block_x, st, c->step_lds);

@@ -313,93 +313,111 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_step_pressure(S
 }
 
 // ---------------------------------------------------------------------------
-// K2e: two pressure-driven steps in one launch, for channels of at most 64
-// rows (taken up to 48 rows, see pressure_two_step_ok).  A workgroup of
-// (CX + 2) x ny threads computes the first step for
-// its CX columns and one column on each side (inlet / outlet ghost columns
-// staged from HBM as in K2) and keeps it in LDS; the workgroups holding the
-// first or last column then rebuild the ghost columns from those LDS values,
-// and every workgroup computes the second step for its CX columns from LDS
-// and stores it.  Each step takes its per-column rates from its own centre
+// K2e: K = 2..4 pressure-driven steps in one launch, for channels of at most
+// 48 rows.  A workgroup of (CX + 2(K - 1)) x ny threads owns CX columns; the
+// first step is computed for them and K - 1 columns on each side (inlet /
+// outlet ghost columns staged from HBM as in K2) and kept in LDS, each
+// further step from LDS for a region one column narrower on each side, the
+// last one stored to HBM.  A step whose region holds the first or last
+// column of the channel rebuilds that ghost column from the previous step's
+// LDS values, and every step takes its per-column rates from its own centre
 // rows.  The gather, ghost, rate and collision arithmetic is K2's, so the
-// result equals two K2 steps bit for bit; a node update moves
-// ((CX + 2) / CX x 72 + 72) / 2 bytes of HBM traffic instead of 144.
+// result equals K launches of K2 bit for bit; a node update moves about
+// ((CX + 2(K - 1)) / CX x 72 + 72) / K bytes of HBM traffic instead of 144.
 // ---------------------------------------------------------------------------
-template <int CX>
-__device__ __forceinline__ void pressure2_block(const StepArgs& a, int blk, double* lds2, double (*s_rc)[CX + 2]) {
-  constexpr int W = CX + 2;
+template <int CX, int K>
+constexpr int pressure_tile_w() {
+  return CX + 2 * (K - 1);
+}
+
+// One step of a K2e workgroup: step k of K (LDS columns k - 1 .. W - k),
+// gathered from HBM (the first step) or from LDS, kept in LDS or stored to
+// HBM (the last).
+template <int CX, int K>
+__device__ __forceinline__ void pressurek_step(const StepArgs& a, int blk, double* lds,
+                                               double (*s_rc)[pressure_tile_w<CX, K>()],
+                                               double (*s_rate)[pressure_tile_w<CX, K>()], int k) {
+  constexpr int W = pressure_tile_w<CX, K>();
   const int nx = a.g.nx, ny = a.g.ny;
-  double* s1 = lds2;                   // [9][ny][W]: first-step populations
-  double* gh = lds2 + 9 * ny * W;      // [2][9][ny]: ghost columns (first, then second step)
-  const int x0 = blk * CX - 1;         // global column of LDS column 0
-  const int lx = threadIdx.x, ty = threadIdx.y;
-  const int tid = ty * W + lx, nthreads = W * ny;
+  double* s1 = lds;                    // [9][ny][W]: the latest step kept
+  double* gh = lds + 9 * ny * W;       // [2][9][ny]: ghost columns of the current step
+  const int x0 = blk * CX - (K - 1);   // global column of LDS column 0
+  int lx = threadIdx.x, ty = threadIdx.y;
+  // Opaque copies per step: the compiler would otherwise compute the LDS
+  // addresses of every step's gather up front and hold them (spilled to
+  // scratch) across the steps.
+  asm volatile("" : "+v"(lx), "+v"(ty));
   const int x = x0 + lx;
+  const double omr = 1.0 - a.r;
+  // step k covers global columns lo .. hi that exist
+  const int lo = x0 + (k - 1), hi = x0 + W - k;
+  const bool need_in = lo <= 0 && hi >= 0, need_out = lo <= nx - 1 && hi >= nx - 1;
+  const bool valid = lx >= k - 1 && lx <= W - k && x >= 0 && x < nx;
+  const TileView tv{s1, x0, 0, W, ny, nx, ny};
+  if (need_in || need_out) {
+    const int tid = ty * W + lx, nthreads = W * ny;
+    if (k == 1)
+      fill_ghosts(View{a.src, a.g}, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
+    else
+      fill_ghosts(tv, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
+    __syncthreads();
+  }
   const int yc = ny / 2;
   const bool even = (ny & 1) == 0;
-  const double omr = 1.0 - a.r;
-  // first step: columns x0 .. x0 + CX + 1 that exist
-  {
-    const bool in1 = x0 <= 0, out1 = x0 + W - 1 >= nx - 1;   // the region holds column 0 / nx - 1
-    const bool valid = x >= 0 && x < nx;
-    double f[9];
-    if (in1 || out1) {
+  double f[9];
+  if (valid) {
+    if (k == 1) {
       const View v{a.src, a.g};
-      fill_ghosts(v, a.rho_in, a.rho_out, in1, out1, gh, gh + 9 * ny, tid, nthreads);
-      __syncthreads();
-      if (valid) gather_node(Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}, x, ty, f);
+      if (need_in || need_out)
+        gather_node(Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}, x, ty, f);
+      else
+        gather_node(Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, x, ty, f);
     } else {
-      gather_node(Gather<3, View>{{a.src, a.g}, a.r, omr, a.shift, a.rho_in, a.rho_out}, x, ty, f);
-    }
-    if (valid) {
-      if (ty == yc) s_rc[0][lx] = sum9(f);
-      if (even && ty == yc - 1) s_rc[1][lx] = sum9(f);
-    }
-    __syncthreads();
-    if (valid) {
-      const double rc = even ? 0.5 * (s_rc[1][lx] + s_rc[0][lx]) : s_rc[0][lx];
-      double snu, sq;
-      local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
-      collide<false>(f, 0.0, 0.0, Rates{a.s3, snu, sq, a.s8});
-#pragma unroll
-      for (int i = 0; i < 9; ++i) s1[(i * ny + ty) * W + lx] = f[i];
-    }
-  }
-  __syncthreads();
-  // second step: columns x0 + 1 .. x0 + CX
-  {
-    const TileView tv{s1, x0, 0, W, ny, nx, ny};
-    const bool in2 = x0 + 1 == 0, out2 = x0 + CX >= nx - 1;   // the outputs hold column 0 / nx - 1
-    const bool out = lx >= 1 && lx <= CX && x < nx;
-    if (in2 || out2) {
-      fill_ghosts(tv, a.rho_in, a.rho_out, in2, out2, gh, gh + 9 * ny, tid, nthreads);
-      __syncthreads();
-    }
-    double f[9];
-    if (out) {
-      if (in2 || out2)
+      if (need_in || need_out)
         Gather<2, TileView>{tv, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}(x, ty, f);
       else
         Gather<3, TileView>{tv, a.r, omr, a.shift, a.rho_in, a.rho_out}(x, ty, f);
-      if (ty == yc) s_rc[0][lx] = sum9(f);
-      if (even && ty == yc - 1) s_rc[1][lx] = sum9(f);
     }
-    __syncthreads();
-    if (out) {
-      const double rc = even ? 0.5 * (s_rc[1][lx] + s_rc[0][lx]) : s_rc[0][lx];
-      double snu, sq;
-      local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, snu, sq);
-      collide<false>(f, 0.0, 0.0, Rates{a.s3, snu, sq, a.s8});
+    if (ty == yc) s_rc[0][lx] = sum9(f);
+    if (even && ty == yc - 1) s_rc[1][lx] = sum9(f);
+  }
+  __syncthreads();   // centre densities published; every read of step k - 1 done
+  // the column's rates, once per column (the same arithmetic as every node
+  // of the column evaluating them)
+  if (valid && ty == 0) {
+    const double rc = even ? 0.5 * (s_rc[1][lx] + s_rc[0][lx]) : s_rc[0][lx];
+    local_rates(a.kn, a.rho_out, rc, a.c_tau, a.a, a.A2, a.tq_den, s_rate[0][lx], s_rate[1][lx]);
+  }
+  __syncthreads();
+  if (valid) {
+    collide<false>(f, 0.0, 0.0, Rates{a.s3, s_rate[0][lx], s_rate[1][lx], a.s8});
+    if (k < K) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s1[(i * ny + ty) * W + lx] = f[i];
+    } else {
       store9(a.dst, a.g, x, ty, f);
     }
   }
 }
 
-template <int CX>
-__global__ __launch_bounds__(1024) void k_step2_pressure(StepArgs a) {
-  extern __shared__ double lds2[];   // [9][ny][CX + 2] + [2][9][ny]
-  __shared__ double s_rc[2][CX + 2];
-  pressure2_block<CX>(a, logical_block(a.xcd_remap), lds2, s_rc);
+// s_rc: [2][W] centre-row densities, s_rate: [2][W] the columns' s_nu, s_q.
+template <int CX, int K>
+__device__ __forceinline__ void pressurek_block(const StepArgs& a, int blk, double* lds,
+                                                double (*s_rc)[pressure_tile_w<CX, K>()],
+                                                double (*s_rate)[pressure_tile_w<CX, K>()]) {
+  pressurek_step<CX, K>(a, blk, lds, s_rc, s_rate, 1);
+#pragma unroll 1
+  for (int k = 2; k <= K; ++k) {
+    __syncthreads();   // step k - 1 is in LDS
+    pressurek_step<CX, K>(a, blk, lds, s_rc, s_rate, k);
+  }
+}
+
+template <int CX, int K>
+__global__ __launch_bounds__(1024) void k_stepk_pressure(StepArgs a) {
+  extern __shared__ double lds[];   // [9][ny][W] + [2][9][ny]
+  __shared__ double s_rc[2][pressure_tile_w<CX, K>()], s_rate[2][pressure_tile_w<CX, K>()];
+  pressurek_block<CX, K>(a, logical_block(a.xcd_remap), lds, s_rc, s_rate);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,16 +466,16 @@ __global__ __launch_bounds__((column_threads<CX, ONE>())) void k_pbatch_step(PBa
   pressure_block<CX, ONE>(channel_args(p, c), b - k * p.nblk, p.nblk, s_rc, s_ghost);
 }
 
-// Two steps of every running channel in one launch (K2e per channel).
-template <int CX>
-__global__ __launch_bounds__(1024) void k_pbatch_step2(PBatchArgs p) {
-  extern __shared__ double lds2[];
-  __shared__ double s_rc[2][CX + 2];
+// K steps of every running channel in one launch (K2e per channel).
+template <int CX, int K>
+__global__ __launch_bounds__(1024) void k_pbatch_stepk(PBatchArgs p) {
+  extern __shared__ double lds[];
+  __shared__ double s_rc[2][pressure_tile_w<CX, K>()], s_rate[2][pressure_tile_w<CX, K>()];
   const int b = logical_block(p.xcd_remap);
   const int k = b / p.nblk;
   const int c = p.live[k];
   if (!p.state[c].active) return;
-  pressure2_block<CX>(channel_args(p, c), b - k * p.nblk, lds2, s_rc);
+  pressurek_block<CX, K>(channel_args(p, c), b - k * p.nblk, lds, s_rc, s_rate);
 }
 
 // ---------------------------------------------------------------------------
@@ -842,12 +860,16 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
   return hipGetLastError();
 }
 
-// Two-step pressure launches: channels of at most kPressureTwoStepRows rows
+// Multi-step pressure launches: channels of at most kPressureTwoStepRows rows
 // on the column kernel's path (grids that take the row kernel step one at a
-// time).  Measured, us per step one / two steps per launch: 2000 x 20
-// 4.35 / 3.48, 4000 x 40 6.37 / 4.99, 8192 x 40 11.75 / 8.74, 32768 x 16
+// time).  Measured with two steps per launch, us per step one / two: 2000 x
+// 20 4.35 / 3.48, 4000 x 40 6.37 / 4.99, 8192 x 40 11.75 / 8.74, 32768 x 16
 // 15.45 / 14.65, but 16384 x 64 33.0 / 34.1 (8-column tiles: the halo
-// columns cost more than the second launch saves).
+// columns cost more than the second launch saves).  With the column rates
+// evaluated once per column, 4000 x 40 takes 4.68 / 4.48 / 4.14 us per step
+// at two / three / four steps per launch (16-column tiles; 8-column tiles
+// 5.04 / 4.75 / 6.07), the batch of 16 channels of 2000 x 20 15.4 / 13.9 /
+// 12.4 us (32-column tiles).
 constexpr int kPressureTwoStepRows = 48;
 
 bool pressure_two_step_ok(const StepArgs& a) {
@@ -856,28 +878,61 @@ bool pressure_two_step_ok(const StepArgs& a) {
   return a.mode == 1 && a.g.ny <= kPressureTwoStepRows && !rows;
 }
 
-// Width of K2e: the widest of 32, 16, 8 columns with (CX + 2) ny <= 1024 that
-// leaves about one workgroup per CU over nch channels, else 8.
-int step2_pressure_cx(const Geo& g, int nch, int cus) {
+// Width of K2e: the widest of 32, 16, 8 columns with (CX + 2(k - 1)) ny <=
+// 1024 that leaves about one workgroup per CU over nch channels, else 8
+// (which fits every k <= 4 up to 48 rows).
+int stepk_pressure_cx(const Geo& g, int nch, int cus, int k) {
   const long enough = cus > 0 ? cus - cus / 10 : 230;
   for (const int cand : {32, 16}) {
-    if ((cand + 2) * g.ny > 1024) continue;
+    if ((cand + 2 * (k - 1)) * g.ny > 1024) continue;
     if ((long)nch * ((g.nx + cand - 1) / cand) >= enough) return cand;
   }
   return 8;
 }
 
-hipError_t launch_step2_pressure(const StepArgs& a, hipStream_t st) {
+size_t stepk_pressure_lds(const Geo& g, int cx, int k) {
+  return (9 * (size_t)g.ny * (cx + 2 * (k - 1)) + 18 * (size_t)g.ny) * sizeof(double);
+}
+
+// LDS of a K2e workgroup at most: (CX + 2(k - 1)) ny <= 1024 nodes of 9
+// doubles plus two ghost columns of at most 48 rows.
+constexpr int kStepKPressureLdsMax = (9 * 1024 + 18 * kPressureTwoStepRows) * (int)sizeof(double);
+
+template <int CX, int K>
+hipError_t pressure_allow() {
+  for (const void* f : {(const void*)k_stepk_pressure<CX, K>, (const void*)k_pbatch_stepk<CX, K>}) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kStepKPressureLdsMax);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Launch LAUNCH(CX, K) for the K2e instance of width cx and k steps.
+#define CLB_STEPK_PRESSURE_DISPATCH(cx, k, LAUNCH) \
+  do {                                             \
+    if ((cx) == 32) {                              \
+      if ((k) == 4) LAUNCH(32, 4);                 \
+      else if ((k) == 3) LAUNCH(32, 3);            \
+      else LAUNCH(32, 2);                          \
+    } else if ((cx) == 16) {                       \
+      if ((k) == 4) LAUNCH(16, 4);                 \
+      else if ((k) == 3) LAUNCH(16, 3);            \
+      else LAUNCH(16, 2);                          \
+    } else {                                       \
+      if ((k) == 4) LAUNCH(8, 4);                  \
+      else if ((k) == 3) LAUNCH(8, 3);             \
+      else LAUNCH(8, 2);                           \
+    }                                              \
+  } while (0)
+
+hipError_t launch_stepk_pressure(const StepArgs& a, int k, hipStream_t st) {
   const int ny = a.g.ny;
-  const int cx = step2_pressure_cx(a.g, 1, a.cus);
-  const dim3 grid((unsigned)((a.g.nx + cx - 1) / cx)), block(cx + 2, ny);
-  const size_t lds = (9 * (size_t)ny * (cx + 2) + 18 * (size_t)ny) * sizeof(double);
-  if (cx == 32)
-    k_step2_pressure<32><<<grid, block, lds, st>>>(a);
-  else if (cx == 16)
-    k_step2_pressure<16><<<grid, block, lds, st>>>(a);
-  else
-    k_step2_pressure<8><<<grid, block, lds, st>>>(a);
+  const int cx = stepk_pressure_cx(a.g, 1, a.cus, k);
+  const dim3 grid((unsigned)((a.g.nx + cx - 1) / cx)), block(cx + 2 * (k - 1), ny);
+  const size_t lds = stepk_pressure_lds(a.g, cx, k);
+#define CLB_LAUNCH(CXV, KV) k_stepk_pressure<CXV, KV><<<grid, block, lds, st>>>(a)
+  CLB_STEPK_PRESSURE_DISPATCH(cx, k, CLB_LAUNCH);
+#undef CLB_LAUNCH
   return hipGetLastError();
 }
 
@@ -887,19 +942,16 @@ bool pbatch_two_step_ok(const PBatchArgs& a) {
   return a.g.ny <= kPressureTwoStepRows && !rows;
 }
 
-hipError_t launch_pbatch_step2(const PBatchArgs& a, hipStream_t st) {
+hipError_t launch_pbatch_stepk(const PBatchArgs& a, int k, hipStream_t st) {
   const int ny = a.g.ny;
-  const int cx = step2_pressure_cx(a.g, a.nch, a.cus);
+  const int cx = stepk_pressure_cx(a.g, a.nch, a.cus, k);
   PBatchArgs b = a;
   b.nblk = (a.g.nx + cx - 1) / cx;
-  const dim3 grid((unsigned)((size_t)b.nblk * a.nch)), block(cx + 2, ny);
-  const size_t lds = (9 * (size_t)ny * (cx + 2) + 18 * (size_t)ny) * sizeof(double);
-  if (cx == 32)
-    k_pbatch_step2<32><<<grid, block, lds, st>>>(b);
-  else if (cx == 16)
-    k_pbatch_step2<16><<<grid, block, lds, st>>>(b);
-  else
-    k_pbatch_step2<8><<<grid, block, lds, st>>>(b);
+  const dim3 grid((unsigned)((size_t)b.nblk * a.nch)), block(cx + 2 * (k - 1), ny);
+  const size_t lds = stepk_pressure_lds(a.g, cx, k);
+#define CLB_LAUNCH(CXV, KV) k_pbatch_stepk<CXV, KV><<<grid, block, lds, st>>>(b)
+  CLB_STEPK_PRESSURE_DISPATCH(cx, k, CLB_LAUNCH);
+#undef CLB_LAUNCH
   return hipGetLastError();
 }
 
@@ -978,6 +1030,15 @@ hipError_t stepk_setup() {
   hipError_t e = stepk_allow<2>();
   if (e == hipSuccess) e = stepk_allow<3>();
   if (e == hipSuccess) e = stepk_allow<4>();
+  if (e == hipSuccess) e = pressure_allow<32, 2>();
+  if (e == hipSuccess) e = pressure_allow<32, 3>();
+  if (e == hipSuccess) e = pressure_allow<32, 4>();
+  if (e == hipSuccess) e = pressure_allow<16, 2>();
+  if (e == hipSuccess) e = pressure_allow<16, 3>();
+  if (e == hipSuccess) e = pressure_allow<16, 4>();
+  if (e == hipSuccess) e = pressure_allow<8, 2>();
+  if (e == hipSuccess) e = pressure_allow<8, 3>();
+  if (e == hipSuccess) e = pressure_allow<8, 4>();
   return e;
 }
 

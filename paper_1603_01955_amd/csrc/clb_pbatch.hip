@@ -152,7 +152,7 @@ struct clb_pbatch {
   int32_t n_live;
   int64_t t;                               // steps taken by the channels still running
   int32_t par;                             // buffer holding their current state
-  int32_t steps_per_launch;                // 2: two-step launches where they apply, 1: one step
+  int32_t steps_per_launch;                // 2-4: multi-step launches where they apply, 1: one step
   hipStream_t stream;                      // caller's stream: all work runs here
   hipStream_t capture;                     // private stream, used only to record graphs
   size_t step_lds;                         // LDS reserved per row-kernel workgroup (occupancy cap)
@@ -177,18 +177,20 @@ void drop_graphs(clb_pbatch* b) {
   }
 }
 
-// n steps of the running channels from buffer *par (updated) -- two per
-// launch where the two-step kernel applies -- then the count (and with check
-// the convergence test) on stream st.
+// n steps of the running channels from buffer *par (updated) --
+// steps_per_launch per launch where the multi-step kernel applies, a shorter
+// remainder in one launch -- then the count (and with check the
+// convergence test) on stream st.
 clb_status enqueue_chunk(clb_pbatch* b, hipStream_t st, int* par, int64_t n, int check, double tol) {
   clb::PBatchArgs a = b->args;
   a.nch = b->n_live;
-  const bool two = b->steps_per_launch >= 2 && b->n_live > 0 && clb::pbatch_two_step_ok(a);
+  const int k = b->n_live > 0 && clb::pbatch_two_step_ok(a) ? b->steps_per_launch : 1;
   for (int64_t left = n; left > 0 && b->n_live > 0;) {
     a.par = *par;
-    if (two && left >= 2) {
-      PBATCH_HIP(clb::launch_pbatch_step2(a, st));
-      left -= 2;
+    const int m = left < k ? (int)left : k;
+    if (m >= 2) {
+      PBATCH_HIP(clb::launch_pbatch_stepk(a, m, st));
+      left -= m;
     } else {
       PBATCH_HIP(clb::launch_pbatch_step(a, st, b->step_lds));
       left -= 1;
@@ -359,7 +361,7 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   b->h_m.assign(nch, 0.0);
   b->t = 0;
   b->par = 0;
-  b->steps_per_launch = 2;
+  b->steps_per_launch = 4;
   b->stream = static_cast<hipStream_t>(hip_stream);
 
   auto fail_init = [b](hipError_t e, const char* where) {
@@ -372,6 +374,7 @@ clb_status clb_pbatch_init(int32_t nch, const clb_params* params, void* d_worksp
   hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
   if (e != hipSuccess) return fail_init(e, "hipStreamCreateWithFlags");
   e = clb::periodic_step_lds(1024, &b->step_lds);
+  if (e == hipSuccess) e = clb::stepk_setup();
   if (e != hipSuccess) return fail_init(e, "device attributes");
   e = hipMemcpyAsync(d_ch, b->chan.data(), nch * sizeof(clb::PChan), hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return fail_init(e, "upload channel table");
@@ -468,7 +471,7 @@ clb_status clb_pbatch_run(clb_pbatch* b, int64_t max_steps, int32_t check_every,
 
 clb_status clb_pbatch_set_steps_per_launch(clb_pbatch* b, int32_t steps) {
   if (!b) return clb::perr(CLB_EINVAL, "batch: NULL");
-  if (steps != 1 && steps != 2) return clb::perr(CLB_EINVAL, "steps: must be 1 or 2");
+  if (steps < 1 || steps > 4) return clb::perr(CLB_EINVAL, "steps: must be 1, 2, 3 or 4");
   if (steps != b->steps_per_launch) {
     PBATCH_HIP(hipStreamSynchronize(b->stream));
     drop_graphs(b);

@@ -115,13 +115,14 @@ def test_bench_workload_matches_reference():
 
 @pytest.mark.parametrize("nx,ny,nch", [(149, 12, 4), (1030, 40, 5), (50, 70, 2), (2, 3, 3), (2000, 20, 3)])
 def test_row_and_column_kernels_agree_bitwise(nx, ny, nch):
-    """Row and column kernels, one or two steps per launch (odd chunks, so
-    both launch kinds and both buffers occur): the same populations."""
+    """Row and column kernels, one to four steps per launch (odd chunks, so
+    every launch kind, shorter remainders and both buffers occur): the same
+    populations."""
     PressureBatch, _, clb = _mods()
     params = [_gpu_params(clb, nx, ny, s) for s in _specs(nch)]
     out = []
     for path in (1, 2):
-        for spl in (1, 2):
+        for spl in ((1, 2, 3, 4) if path == 1 else (1, 2)):
             pb = PressureBatch(params)
             pb.set_path(path)
             pb.set_steps_per_launch(spl)
