@@ -77,8 +77,9 @@ void clb3_params_default(clb3_params* p);
  * N = ny).  Host only.  CLB_EINVAL names the first invalid field. */
 clb_status clb3_derive(const clb3_params* p, clb_derived* out);
 
-/* Device workspace in bytes: two population buffers (216 bytes per node)
- * plus reduction scratch. */
+/* Device workspace in bytes: two population buffers (216 bytes per node,
+ * rows padded to whole segments of the device layout) plus reduction
+ * scratch. */
 clb_status clb3_workspace_size(const clb3_params* p, size_t* bytes);
 
 /* Create a context over the caller's workspace (device memory, 8-byte
@@ -101,8 +102,9 @@ clb_status clb3_moments(clb3_ctx* c, double* d_rho, double* d_ux, double* d_uy, 
  * channel the 2-D Q).  Needs gx != 0.  Synchronises. */
 clb_status clb3_flow_rate(clb3_ctx* c, double* h_Q);
 
-/* Copy the post-collision populations out / in ([27][nz][ny][nx], device).
- * Setting them resets the step counter. */
+/* Copy the post-collision populations out / in ([27][nz][ny][nx], device;
+ * converted from / to the library's own device layout).  Setting them
+ * resets the step counter. */
 clb_status clb3_get_populations(clb3_ctx* c, double* d_out);
 clb_status clb3_set_populations(clb3_ctx* c, const double* d_in);
 

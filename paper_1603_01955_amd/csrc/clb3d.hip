@@ -7,6 +7,14 @@
 // duct walls, then the cascaded collision (Eqs. 6-9, 13) in central-moment
 // form.  One kernel per step: gather, collide, store -- 216 B read and
 // 216 B written per node update.
+//
+// Device layout: each (y, z) row is cut into segments of L = min(1024, the
+// next power of two >= nx) columns, and a segment stores its 27 directions
+// one after the other, L values each: [nz][ny][segment][27][L].  A
+// wavefront's loads of one direction are one contiguous 512-byte piece, and
+// the 27 pieces of a row segment lie together (216 L bytes) instead of in 27
+// planes far apart.  clb3_get_populations / clb3_set_populations convert
+// from / to the ABI layout [27][nz][ny][nx].
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,10 +31,11 @@ namespace clb3 {
 namespace {
 
 struct Args {
-  const double* src;    // post-collision populations at t - 1, [27][nz][ny][nx]
+  const double* src;    // post-collision populations at t - 1 (device layout)
   double* dst;          // post-collision populations at t
   int nx, ny, nz;
-  size_t plane;         // nx * ny * nz
+  int lshift, nseg;     // L = 2^lshift columns per row segment, nseg segments per row
+  size_t plane;         // nx * ny * nz (logical nodes)
   int zwalls;           // 1: walls in z (duct), 0: z periodic (channel)
   int shift;            // Eq. (20) specular source displaced along the walls
   double r, omr;        // bounce-back fraction and 1 - r
@@ -34,8 +43,16 @@ struct Args {
   double sb, snu, sq, s8;
 };
 
+// Logical node number (the ABI order, x fastest).
 __device__ __forceinline__ size_t node_index(const Args& a, int x, int y, int z) {
   return ((size_t)z * (size_t)a.ny + (size_t)y) * (size_t)a.nx + (size_t)x;
+}
+
+// Device-layout offset of direction 0 of node (x, y, z); direction i lies
+// i << lshift further.
+__device__ __forceinline__ size_t dev_index(const Args& a, int x, int y, int z) {
+  const size_t seg = ((size_t)z * (size_t)a.ny + (size_t)y) * (size_t)a.nseg + (size_t)(x >> a.lshift);
+  return ((seg * 27) << a.lshift) + (size_t)(x & ((1 << a.lshift) - 1));
 }
 
 // Pre-collision populations of node (x, y, z): pull streaming (Eq. 5), x
@@ -47,7 +64,7 @@ __device__ __forceinline__ size_t node_index(const Args& a, int x, int y, int z)
 __device__ __forceinline__ void gather(const Args& a, int x, int y, int z, double f[27]) {
 #pragma clang fp contract(off)
   const double* __restrict__ P = a.src;
-  const size_t self = node_index(a, x, y, z);
+  const size_t self = dev_index(a, x, y, z);
 #pragma unroll
   for (int c = -1; c <= 1; ++c) {
 #pragma unroll
@@ -66,12 +83,12 @@ __device__ __forceinline__ void gather(const Args& a, int x, int y, int z, doubl
         else
           zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
         if (!oy && !oz) {
-          f[i] = P[(size_t)i * a.plane + node_index(a, xs, ys, zs)];
+          f[i] = P[((size_t)i << a.lshift) + dev_index(a, xs, ys, zs)];
         } else {
           const int i2 = (e + 1) + 3 * ((oy ? -b : b) + 1) + 9 * ((oz ? -c : c) + 1);
-          const double bb = P[(size_t)(26 - i) * a.plane + self];
-          const size_t sn = a.shift ? node_index(a, xs, oy ? y : ys, oz ? z : zs) : self;
-          const double sp = P[(size_t)i2 * a.plane + sn];
+          const double bb = P[((size_t)(26 - i) << a.lshift) + self];
+          const size_t sn = a.shift ? dev_index(a, xs, oy ? y : ys, oz ? z : zs) : self;
+          const double sp = P[((size_t)i2 << a.lshift) + sn];
           f[i] = a.r * bb + a.omr * sp;
         }
       }
@@ -193,9 +210,9 @@ __global__ __launch_bounds__(kBX * kBY) void k3_step(Args a) {
   double f[27];
   gather(a, x, y, z, f);
   collide<FORCE>(f, a);
-  const size_t n = node_index(a, x, y, z);
+  const size_t n = dev_index(a, x, y, z);
 #pragma unroll
-  for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(f[i], a.dst + (size_t)i * a.plane + n);
+  for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(f[i], a.dst + ((size_t)i << a.lshift) + n);
 }
 
 // Macroscopic fields of the pre-collision state (Eqs. 12-13).
@@ -240,14 +257,23 @@ __global__ __launch_bounds__(256) void k3_ux_partial(Args a, double* partial) {
   if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-// Count of non-finite values among all populations, per workgroup.
-__global__ __launch_bounds__(256) void k3_nonfinite_partial(const double* __restrict__ p, size_t n,
+// Count of non-finite values among all populations (logical nodes only: the
+// padding lanes of a last row segment are never written), per workgroup.
+__global__ __launch_bounds__(256) void k3_nonfinite_partial(const double* __restrict__ p, Args a,
                                                             double* partial) {
   __shared__ double s[4];
   double cnt = 0.0;
-  for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
-    const double v = p[k];
-    cnt += (v - v == 0.0) ? 0.0 : 1.0;
+  for (size_t n = blockIdx.x * (size_t)256 + threadIdx.x; n < a.plane; n += (size_t)gridDim.x * 256) {
+    const int x = (int)(n % (size_t)a.nx);
+    const size_t rest = n / (size_t)a.nx;
+    const int y = (int)(rest % (size_t)a.ny);
+    const int z = (int)(rest / (size_t)a.ny);
+    const size_t d = dev_index(a, x, y, z);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const double v = p[((size_t)i << a.lshift) + d];
+      cnt += (v - v == 0.0) ? 0.0 : 1.0;   // inf - inf and NaN - NaN are NaN
+    }
   }
   cnt = clb::wave_sum(cnt);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = cnt;
@@ -268,8 +294,13 @@ __global__ __launch_bounds__(256) void k3_sum(const double* __restrict__ v, int 
 
 // Start: f^eq(rho0, 0) (product of the one-axis factors 2/3, 1/6, 1/6) plus
 // the seeded perturbation.
-__global__ void k3_init(double* dst, size_t plane, double rho0, int perturbed, double amp, uint64_t seed) {
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < plane; n += (size_t)gridDim.x * blockDim.x) {
+__global__ void k3_init(double* dst, Args a, double rho0, int perturbed, double amp, uint64_t seed) {
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < a.plane; n += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(n % (size_t)a.nx);
+    const size_t rest = n / (size_t)a.nx;
+    const int y = (int)(rest % (size_t)a.ny);
+    const int z = (int)(rest / (size_t)a.ny);
+    const size_t d = dev_index(a, x, y, z);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
       const int e0 = i % 3 - 1, e1 = (i / 3) % 3 - 1, e2 = i / 9 - 1;
@@ -281,8 +312,27 @@ __global__ void k3_init(double* dst, size_t plane, double rho0, int perturbed, d
         const double U = (double)(clb::splitmix64_first(key) >> 11) * (1.0 / 9007199254740992.0);
         v += amp * (2.0 * U - 1.0);
       }
-      dst[(size_t)i * plane + n] = v;
+      dst[((size_t)i << a.lshift) + d] = v;
     }
+  }
+}
+
+// ABI layout [27][nz][ny][nx] <-> device layout.
+template <bool EXPORT>
+__global__ void k3_convert(const double* __restrict__ src, Args a, double* __restrict__ dst) {
+  const size_t n = 27 * a.plane;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(k / a.plane);
+    const size_t node = k - (size_t)i * a.plane;
+    const int x = (int)(node % (size_t)a.nx);
+    const size_t rest = node / (size_t)a.nx;
+    const int y = (int)(rest % (size_t)a.ny);
+    const int z = (int)(rest / (size_t)a.ny);
+    const size_t d = ((size_t)i << a.lshift) + dev_index(a, x, y, z);
+    if (EXPORT)
+      dst[k] = src[d];
+    else
+      dst[d] = src[k];
   }
 }
 
@@ -372,7 +422,20 @@ clb_status validate3(const clb3_params* p, clb_derived* d) {
 
 size_t plane_of(const clb3_params* p) { return (size_t)p->nx * (size_t)p->ny * (size_t)p->nz; }
 
-size_t buffer_bytes(const clb3_params* p) { return clb3::align256(27 * plane_of(p) * sizeof(double)); }
+// log2 of the row segment length L = min(1024, next power of two >= nx).
+int lshift_of(const clb3_params* p) {
+  int ls = 0;
+  while ((1 << ls) < p->nx && ls < 10) ++ls;
+  return ls;
+}
+
+int nseg_of(const clb3_params* p) { return (p->nx + (1 << lshift_of(p)) - 1) >> lshift_of(p); }
+
+// One population buffer in the device layout (padded row segments).
+size_t buffer_bytes(const clb3_params* p) {
+  return clb3::align256((27 * (size_t)p->nz * (size_t)p->ny * (size_t)nseg_of(p) * sizeof(double))
+                        << lshift_of(p));
+}
 
 size_t total_bytes(const clb3_params* p) {
   return 2 * buffer_bytes(p) + clb3::align256(clb3::kPartials * sizeof(double)) + clb3::align256(32 * sizeof(double));
@@ -385,6 +448,8 @@ clb3::Args args_of(const clb3_ctx* c) {
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.nz = c->p.nz;
+  a.lshift = lshift_of(&c->p);
+  a.nseg = nseg_of(&c->p);
   a.plane = plane_of(&c->p);
   a.zwalls = c->p.zbc == CLB3_Z_WALLS;
   a.shift = c->p.cbbsr_shift;
@@ -471,7 +536,7 @@ clb_status clb3_init(const clb3_params* p, void* d_workspace, size_t bytes, void
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   const size_t plane = plane_of(p);
-  clb3::k3_init<<<clb3::blocks_for(plane) * 16, 256, 0, c->stream>>>(c->buf[0], plane, p->rho0,
+  clb3::k3_init<<<clb3::blocks_for(plane) * 16, 256, 0, c->stream>>>(c->buf[0], args_of(c), p->rho0,
                                                                      p->init == CLB_INIT_PERTURBED, p->init_amp, p->seed);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -543,7 +608,9 @@ clb_status clb3_get_populations(clb3_ctx* c, double* d_out) {
   const size_t bytes = 27 * plane_of(&c->p) * sizeof(double);
   clb_status st = clb::check_device_ptr(d_out, bytes, "d_out");
   if (st != CLB_OK) return st;
-  CLB3_HIP(hipMemcpyAsync(d_out, c->buf[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+  clb3::k3_convert<true><<<clb3::blocks_for(27 * plane_of(&c->p)) * 16, 256, 0, c->stream>>>(c->buf[c->cur],
+                                                                                            args_of(c), d_out);
+  CLB3_HIP(hipGetLastError());
   return CLB_OK;
 }
 
@@ -552,7 +619,9 @@ clb_status clb3_set_populations(clb3_ctx* c, const double* d_in) {
   const size_t bytes = 27 * plane_of(&c->p) * sizeof(double);
   clb_status st = clb::check_device_ptr(d_in, bytes, "d_in");
   if (st != CLB_OK) return st;
-  CLB3_HIP(hipMemcpyAsync(c->buf[c->cur], d_in, bytes, hipMemcpyDeviceToDevice, c->stream));
+  clb3::k3_convert<false><<<clb3::blocks_for(27 * plane_of(&c->p)) * 16, 256, 0, c->stream>>>(d_in, args_of(c),
+                                                                                             c->buf[c->cur]);
+  CLB3_HIP(hipGetLastError());
   c->steps = 0;
   return CLB_OK;
 }
@@ -560,9 +629,8 @@ clb_status clb3_set_populations(clb3_ctx* c, const double* d_in) {
 clb_status clb3_check_finite(clb3_ctx* c, int32_t* h_ok) {
   if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
   if (!h_ok) return fail3(CLB_EINVAL, "h_ok: NULL");
-  const size_t n = 27 * plane_of(&c->p);
-  const unsigned nb = clb3::blocks_for(n);
-  clb3::k3_nonfinite_partial<<<nb, 256, 0, c->stream>>>(c->buf[c->cur], n, c->partial);
+  const unsigned nb = clb3::blocks_for(plane_of(&c->p));
+  clb3::k3_nonfinite_partial<<<nb, 256, 0, c->stream>>>(c->buf[c->cur], args_of(c), c->partial);
   clb3::k3_sum<<<1, 256, 0, c->stream>>>(c->partial, (int)nb, c->result);
   CLB3_HIP(hipGetLastError());
   double bad = 0;
