@@ -201,11 +201,42 @@ __device__ __forceinline__ void collide(double f[27], const Args& a) {
 
 constexpr int kBX = 64, kBY = 4;
 
+// Order of the step's workgroups.  The hardware deals consecutive
+// workgroups to the eight XCDs in turn; logical block l = (b mod 8) per +
+// b / 8 gives each XCD one contiguous range of l, which walks chunks of
+// kChunkRows block rows (kChunkRows kBY rows of y): in a chunk z by z, in a
+// plane block row by block row, in a block row x by x.  The x and y
+// neighbours a workgroup pulls from then run on the same XCD at about the
+// same time, and its z neighbours kChunkRows nbx workgroups before or after
+// it, so the rows they share stay in that XCD's L2.
+constexpr int kChunkRows = 8;
+
+__device__ __forceinline__ void step_block(const Args& a, int& bx, int& by, int& z) {
+  int l = (int)blockIdx.x;
+  const int per = (int)gridDim.x >> 3;
+  if (l < (per << 3)) l = (l & 7) * per + (l >> 3);
+  const int nbx = (a.nx + kBX - 1) / kBX, nby = (a.ny + kBY - 1) / kBY;
+  const int full = nby / kChunkRows;
+  const int per_chunk = a.nz * kChunkRows * nbx;
+  int chunk = l / per_chunk, h = kChunkRows;
+  int rem = l - chunk * per_chunk;
+  if (chunk >= full) {   // the last, shorter chunk
+    chunk = full;
+    rem = l - full * per_chunk;
+    h = nby - full * kChunkRows;
+  }
+  z = rem / (h * nbx);
+  const int r2 = rem - z * (h * nbx);
+  by = chunk * kChunkRows + r2 / nbx;
+  bx = r2 - (r2 / nbx) * nbx;
+}
+
 template <bool FORCE>
 __global__ __launch_bounds__(kBX * kBY) void k3_step(Args a) {
-  const int x = blockIdx.x * kBX + (threadIdx.x & (kBX - 1));
-  const int y = blockIdx.y * kBY + (int)(threadIdx.x / kBX);
-  const int z = blockIdx.z;
+  int bx, by, z;
+  step_block(a, bx, by, z);
+  const int x = bx * kBX + (threadIdx.x & (kBX - 1));
+  const int y = by * kBY + (int)(threadIdx.x / kBX);
   if (x >= a.nx || y >= a.ny) return;
   double f[27];
   gather(a, x, y, z, f);
@@ -387,6 +418,8 @@ clb_status validate3(const clb3_params* p, clb_derived* d) {
   if (p->ny < 1) return fail3(CLB_EINVAL, "ny: must be >= 1 (got %d)", p->ny);
   if (p->nz < 1 || p->nz > 65535) return fail3(CLB_EINVAL, "nz: must lie in [1, 65535] (got %d)", p->nz);
   if ((p->ny + 3) / 4 > 65535) return fail3(CLB_EINVAL, "ny: at most 262140 rows");
+  if ((size_t)((p->nx + 63) / 64) * (size_t)((p->ny + 3) / 4) * (size_t)p->nz >= ((size_t)1 << 31))
+    return fail3(CLB_EINVAL, "nx*ny*nz: grid too large for one launch");
   if (p->zbc != CLB3_Z_WALLS && p->zbc != CLB3_Z_PERIODIC) return fail3(CLB_EINVAL, "zbc: unknown kind %d", p->zbc);
   if (p->init != CLB_INIT_UNIFORM && p->init != CLB_INIT_PERTURBED)
     return fail3(CLB_EINVAL, "init: must be CLB_INIT_UNIFORM or CLB_INIT_PERTURBED");
@@ -551,7 +584,8 @@ clb_status clb3_step(clb3_ctx* c, int64_t nsteps) {
   const clb::TraceRange trace("clb3_step");
   if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
   if (nsteps < 0) return fail3(CLB_EINVAL, "nsteps: must be >= 0");
-  const dim3 grid = node_grid(&c->p);
+  const dim3 g3 = node_grid(&c->p);
+  const dim3 grid(g3.x * g3.y * g3.z);   // k3_step orders its workgroups itself
   const bool force = c->p.gx != 0.0 || c->p.gy != 0.0 || c->p.gz != 0.0;
   for (int64_t n = 0; n < nsteps; ++n) {
     const clb3::Args a = args_of(c);
