@@ -189,6 +189,9 @@ __global__ __launch_bounds__(MAXT) void k_batch(BatchArgs a) {
   const bool mine = (int)threadIdx.x < n;
   NodeSources q{};
   if (one && mine) q = node_sources(d, threadIdx.x);
+  // steps to the next convergence check (at multiples of check_every of the
+  // channel's step count); a countdown instead of a 64-bit remainder per step
+  int64_t to_check = a.check_every > 0 ? a.check_every - st.steps % a.check_every : 0;
   while (!st.converged && taken < a.max_steps) {
     if (one) {
       if (mine) {
@@ -212,7 +215,8 @@ __global__ __launch_bounds__(MAXT) void k_batch(BatchArgs a) {
     A = B;
     B = t;
     ++taken;
-    if (a.check_every > 0 && (st.steps + taken) % a.check_every == 0) {
+    if (a.check_every > 0 && --to_check == 0) {
+      to_check = a.check_every;
       const double S = channel_sum_ux(d, A, n, red);
       st.checks += 1;
       if (fabs(S - st.S) <= a.tol * fabs(S)) st.converged = 1;   // first check: S is NaN
