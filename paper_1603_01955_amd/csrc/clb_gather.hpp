@@ -100,8 +100,21 @@ __device__ __forceinline__ double eq_factor(int e, double u) {
   return e == 0 ? 2.0 / 3.0 - u * u : (e > 0 ? 0.5 * (1.0 / 3.0 + u * u + u) : 0.5 * (1.0 / 3.0 + u * u - u));
 }
 
-// Population i of the ghost column at row y, evaluated inline: the same
-// arithmetic as ghost_row for that one direction (bitwise the same value).
+// Ghost population i from the density and velocity of the two adjacent
+// columns (rho1, u1 next to the boundary, u2 one further in) and the
+// adjacent column's own population f1i: ghost_row's arithmetic for that one
+// direction (bitwise the same value).
+__device__ __forceinline__ double ghost_from(int i, double rho_b, double rho1, double ux1, double uy1, double ux2,
+                                             double uy2, double f1i) {
+#pragma clang fp contract(off)
+  const int ex = (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+  const int ey = (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+  const double eg = (2.0 * rho_b - rho1) * eq_factor(ex, 2.0 * ux1 - ux2) * eq_factor(ey, 2.0 * uy1 - uy2);
+  const double e1 = rho1 * eq_factor(ex, ux1) * eq_factor(ey, uy1);
+  return eg + (f1i - e1);
+}
+
+// Population i of the ghost column at row y, evaluated inline.
 template <class V>
 __device__ __forceinline__ double ghost_value(const V& v, bool inlet, int y, double rho_b, int i) {
 #pragma clang fp contract(off)
@@ -116,14 +129,10 @@ __device__ __forceinline__ double ghost_value(const V& v, bool inlet, int y, dou
   double rho1, ux1, uy1, rho2, ux2, uy2;
   rho_u(f1, rho1, ux1, uy1);
   rho_u(f2, rho2, ux2, uy2);
-  const int ex = (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
-  const int ey = (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
   double f1i = f1[0];
 #pragma unroll
   for (int k = 1; k < 9; ++k) f1i = k == i ? f1[k] : f1i;
-  const double eg = (2.0 * rho_b - rho1) * eq_factor(ex, 2.0 * ux1 - ux2) * eq_factor(ey, 2.0 * uy1 - uy2);
-  const double e1 = rho1 * eq_factor(ex, ux1) * eq_factor(ey, uy1);
-  return eg + (f1i - e1);
+  return ghost_from(i, rho_b, rho1, ux1, uy1, ux2, uy2, f1i);
 }
 
 // Largest ny whose two ghost columns ([2][9][ny] doubles) are staged in LDS.
@@ -147,6 +156,34 @@ __device__ __forceinline__ void fill_ghosts(const V& v, double rho_in, double rh
 #pragma unroll
       for (int k = 0; k < 9; ++k) s_out[k * ny + y] = g[k];
     }
+  }
+}
+
+// fill_ghosts with a smaller register footprint, for kernels that keep
+// many waves in flight: one thread per row takes the velocity of the second
+// column, then the first column's populations and moments, and writes the
+// nine ghost populations one by one (bitwise ghost_row's values).  No
+// barrier: the caller synchronises before the ghosts are read.
+template <class V>
+__device__ __forceinline__ void fill_ghosts_lean(const V& v, double rho_in, double rho_out, bool need_in,
+                                                 bool need_out, double* s_in, double* s_out, int tid, int nthreads) {
+  const int ny = v.ny(), nx = v.nx();
+  for (int j = tid; j < 2 * ny; j += nthreads) {
+    const bool inlet = j < ny;
+    if (inlet ? !need_in : !need_out) continue;
+    const int y = inlet ? j : j - ny;
+    const int c1 = inlet ? 0 : nx - 1, c2 = inlet ? 1 : nx - 2;
+    double f[9], rho1, ux1, uy1, rho2, ux2, uy2;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f[k] = v.at(k, c2, y);
+    rho_u(f, rho2, ux2, uy2);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f[k] = v.at(k, c1, y);
+    rho_u(f, rho1, ux1, uy1);
+    double* out = inlet ? s_in : s_out;
+    const double rho_b = inlet ? rho_in : rho_out;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i * ny + y] = ghost_from(i, rho_b, rho1, ux1, uy1, ux2, uy2, f[i]);
   }
 }
 

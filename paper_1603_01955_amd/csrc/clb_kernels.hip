@@ -354,12 +354,12 @@ __device__ __forceinline__ void pressurek_step(const StepArgs& a, int blk, doubl
   const bool need_in = lo <= 0 && hi >= 0, need_out = lo <= nx - 1 && hi >= nx - 1;
   const bool valid = lx >= k - 1 && lx <= W - k && x >= 0 && x < nx;
   const TileView tv{s1, x0, 0, W, ny, nx, ny};
-  if (need_in || need_out) {
+  if (need_in || need_out) {   // uniform across the workgroup
     const int tid = ty * W + lx, nthreads = W * ny;
     if (k == 1)
-      fill_ghosts(View{a.src, a.g}, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
+      fill_ghosts_lean(View{a.src, a.g}, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
     else
-      fill_ghosts(tv, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
+      fill_ghosts_lean(tv, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
     __syncthreads();
   }
   const int yc = ny / 2;
@@ -369,9 +369,9 @@ __device__ __forceinline__ void pressurek_step(const StepArgs& a, int blk, doubl
     if (k == 1) {
       const View v{a.src, a.g};
       if (need_in || need_out)
-        gather_node(Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}, x, ty, f);
+        Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}(x, ty, f);
       else
-        gather_node(Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}, x, ty, f);
+        Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}(x, ty, f);
     } else {
       if (need_in || need_out)
         Gather<2, TileView>{tv, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}(x, ty, f);
@@ -406,7 +406,7 @@ __device__ __forceinline__ void pressurek_block(const StepArgs& a, int blk, doub
                                                 double (*s_rc)[pressure_tile_w<CX, K>()],
                                                 double (*s_rate)[pressure_tile_w<CX, K>()]) {
   pressurek_step<CX, K>(a, blk, lds, s_rc, s_rate, 1);
-#pragma unroll 1
+#pragma unroll
   for (int k = 2; k <= K; ++k) {
     __syncthreads();   // step k - 1 is in LDS
     pressurek_step<CX, K>(a, blk, lds, s_rc, s_rate, k);
@@ -890,6 +890,7 @@ int stepk_pressure_cx(const Geo& g, int nch, int cus, int k) {
   return 8;
 }
 
+// [9][ny][W] populations and [2][9][ny] ghost columns.
 size_t stepk_pressure_lds(const Geo& g, int cx, int k) {
   return (9 * (size_t)g.ny * (cx + 2 * (k - 1)) + 18 * (size_t)g.ny) * sizeof(double);
 }
