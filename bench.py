@@ -527,7 +527,9 @@ def main():
                "mlups": round(nodes / (ms2 * 1e-3) / 1e6, 1),
                "achieved": round(BYTES_PER_NODE * nodes / (2 * ms2 * 1e-3) / 1e9, 1),
                "frac": round(BYTES_PER_NODE * nodes / (2 * ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    launch_s = ms * 1e-3 * k                          # average duration of one k-step launch
+    # average duration of one k-step launch (steps % k of the timed steps run
+    # in one shorter launch at the end: one launch in 334 at 1000 steps, k = 3)
+    launch_s = ms * 1e-3 * k
     # Algorithmic bytes of one k-step launch: every population read once and
     # written once (72 B + 72 B per node); the steps before the last stay in LDS.
     alg = BYTES_PER_NODE * nodes
