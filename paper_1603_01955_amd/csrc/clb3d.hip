@@ -217,7 +217,8 @@ __device__ __forceinline__ void step_block(const Args& a, int& bx, int& by, int&
   if (l < (per << 3)) l = (l & 7) * per + (l >> 3);
   const int nbx = (a.nx + kBX - 1) / kBX, nby = (a.ny + kBY - 1) / kBY;
   const int full = nby / kChunkRows;
-  const int per_chunk = a.nz * kChunkRows * nbx;
+  // workgroups of a full chunk; no more than the grid (below 2^31) holds
+  const int per_chunk = a.nz * (nby < kChunkRows ? nby : kChunkRows) * nbx;
   int chunk = l / per_chunk, h = kChunkRows;
   int rem = l - chunk * per_chunk;
   if (chunk >= full) {   // the last, shorter chunk

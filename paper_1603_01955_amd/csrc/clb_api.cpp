@@ -648,6 +648,7 @@ clb_status clb_hbm_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_
   if (((uintptr_t)d_src & 15) != 0 || ((uintptr_t)d_dst & 15) != 0)
     return fail(CLB_EINVAL, "d_src / d_dst: must be 16-byte aligned");
   if (bytes == 0) return CLB_OK;
+  if (bytes / 16 / 256 >= ((size_t)1 << 31)) return fail(CLB_EINVAL, "bytes: %zu too large for one launch", bytes);
   clb_status st = check_device_range(d_src, bytes, "d_src");
   if (st != CLB_OK) return st;
   if ((st = check_device_range(d_dst, bytes, "d_dst")) != CLB_OK) return st;
