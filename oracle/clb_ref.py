@@ -141,6 +141,19 @@ def init_perturbed(prm, seed, amp):
     return P
 
 
+def init_perturbed_rows(prm, seed, amp, y0, y1):
+    """Rows y0 .. y1 - 1 (full width) of init_perturbed: the same generator
+    keyed by the same node numbers, evaluated for those rows only (grids too
+    large to hold whole)."""
+    P = init_uniform(dataclasses.replace(prm, ny=y1 - y0))
+    node = (np.arange(y0, y1, dtype=np.uint64)[:, None] * np.uint64(prm.nx)
+            + np.arange(prm.nx, dtype=np.uint64)[None, :])
+    for i in range(9):
+        U = uniform01(seed, np.uint64(9) * node + np.uint64(i))
+        P[i] += amp * (2.0 * U - 1.0)
+    return P
+
+
 # ---------------------------------------------------------------------------
 # Macroscopic quantities, Eqs. (12)-(13): rho = sum f, rho u = sum e f + rho F/2.
 # ---------------------------------------------------------------------------
@@ -398,6 +411,23 @@ def run(P, prm, nsteps, callback=None):
         P = step(P, prm)
         if callback is not None:
             callback(n + 1, P)
+    return P
+
+
+def run_rows(P, prm, nsteps):
+    """nsteps periodic steps of a band of full-width rows P (9, rows, nx) cut
+    out of the channel prm: the rates of Eqs. (18), (21) use the channel's
+    N = prm.ny, and both edges of the band are stepped as walls (Eq. 20).
+    Where the band ends at a channel wall that is the channel's own rule; at
+    a cut edge it is not, and after nsteps the rows within nsteps of a cut
+    edge no longer hold the channel's values (the others do)."""
+    if prm.xbc != "periodic":
+        raise ValueError("run_rows supports periodic x only")
+    _, r = resolved(prm)
+    band = dataclasses.replace(prm, ny=P.shape[1])
+    s_nu, s_q = rate_nu(prm.kn, prm.ny, prm.a), rate_q(prm.kn, prm.ny, prm.a, prm.A2, prm.tq_den)
+    for _ in range(nsteps):
+        P = collide(stream_bc(P, band, r), prm.gx, prm.gy, prm.s3, s_nu, s_q, prm.s8, prm.forcing)
     return P
 
 

@@ -188,3 +188,35 @@ def test_perturbed_start_counter_layout():
     assert np.array_equal(a, big[:, :3, :])
     w = C.init_uniform(prm)
     assert np.max(np.abs(a - w)) <= 1e-4 and np.max(np.abs(a - w)) > 5e-5
+
+
+def test_perturbed_rows_are_rows_of_the_start():
+    """init_perturbed_rows gives exactly the rows of the whole seeded start."""
+    prm = C.Params(nx=9, ny=11)
+    whole = C.init_perturbed(prm, 1234, 1e-3)
+    for y0, y1 in ((0, 4), (3, 10), (8, 11), (5, 6)):
+        assert np.array_equal(C.init_perturbed_rows(prm, 1234, 1e-3, y0, y1), whole[:, y0:y1])
+
+
+@pytest.mark.parametrize("shift", [1, 0])
+def test_row_bands_reproduce_the_channel(shift):
+    """Bands of rows stepped on their own (rates from the channel's height)
+    equal the whole channel's run on every row more than n steps away from a
+    cut edge: the band reaching each wall, and interior bands."""
+    nx, ny, n = 13, 17, 3
+    prm = C.Params(nx=nx, ny=ny, kn=0.7, gx=2e-4, gy=-3e-5, cbbsr_shift=shift, forcing=1)
+    P0 = C.init_perturbed(prm, 77, 1e-3)
+    whole = C.run(P0, prm, n)
+    # bottom band: rows 0 .. 2n, valid rows 0 .. n
+    got = C.run_rows(P0[:, :2 * n + 1].copy(), prm, n)
+    assert np.array_equal(got[:, :n + 1], whole[:, :n + 1])
+    # top band: rows ny - 2n - 1 .. ny - 1, valid rows ny - n - 1 .. ny - 1
+    got = C.run_rows(P0[:, ny - 2 * n - 1:].copy(), prm, n)
+    assert np.array_equal(got[:, n:], whole[:, ny - n - 1:])
+    # interior bands: only the middle row is valid
+    for yc in (n, 8, ny - n - 1):
+        got = C.run_rows(P0[:, yc - n:yc + n + 1].copy(), prm, n)
+        assert np.array_equal(got[:, n], whole[:, yc])
+    # and a cut row is not the channel's (the band edges are not walls there)
+    got = C.run_rows(P0[:, 8 - n:8 + n + 1].copy(), prm, n)
+    assert not np.array_equal(got[:, 0], whole[:, 8 - n])
