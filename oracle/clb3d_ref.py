@@ -261,6 +261,40 @@ def init_perturbed(prm, seed, amp):
     return P
 
 
+def init_perturbed_window(prm, seed, amp, y0, y1, z0, z1):
+    """Rows y0 .. y1 - 1 of layers z0 .. z1 - 1 (full width) of
+    init_perturbed: the same generator keyed by the same node numbers,
+    evaluated for that window only (ducts too large to hold whole)."""
+    P = init_uniform(dataclasses.replace(prm, ny=y1 - y0, nz=z1 - z0))
+    zz = np.arange(z0, z1, dtype=np.uint64)[:, None, None]
+    yy = np.arange(y0, y1, dtype=np.uint64)[None, :, None]
+    xx = np.arange(prm.nx, dtype=np.uint64)[None, None, :]
+    node = (zz * np.uint64(prm.ny) + yy) * np.uint64(prm.nx) + xx
+    for i in range(Q3):
+        U = uniform01(seed, np.uint64(27) * node + np.uint64(i))
+        P[i] += amp * (2.0 * U - 1.0)
+    return P
+
+
+def run_window(P, prm, nsteps):
+    """nsteps steps of a window of full-width rows P (27, layers, rows, nx)
+    cut out of the duct prm: the rates of Eqs. (18), (21) use the duct's
+    N = prm.ny, and every face of the window is stepped as a wall (Eq. 20 in
+    3-D).  Where the window ends at a duct wall that is the duct's own rule;
+    at a cut face it is not, and after nsteps the rows and layers within
+    nsteps of a cut face no longer hold the duct's values (the others do).
+    A z-periodic channel keeps its periodic z only in a window of all its
+    layers."""
+    _, r = resolved(prm)
+    zbc = prm.zbc if P.shape[1] == prm.nz else "walls"
+    win = dataclasses.replace(prm, ny=P.shape[2], nz=P.shape[1], zbc=zbc)
+    rt = rates(prm)
+    g = (prm.gx, prm.gy, prm.gz)
+    for _ in range(nsteps):
+        P = collide(stream_bc(P, win, r), g, *rt)
+    return P
+
+
 def moments(P, prm):
     """rho (nz, ny, nx) and u (3, nz, ny, nx) of the pre-collision state."""
     return macroscopic(stream_bc(P, prm), (prm.gx, prm.gy, prm.gz))

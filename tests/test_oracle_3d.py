@@ -267,3 +267,47 @@ def test_duct_flow_rate_converges_to_continuum_poiseuille():
         errs.append(u[0].mean() / _duct_mean_velocity(n, n, 1e-6, nu) - 1)
     assert abs(errs[1]) < 0.008
     assert abs(errs[1]) < abs(errs[0]) / 3.5
+
+
+def test_perturbed_window_is_part_of_the_start():
+    prm = D.Params3D(nx=5, ny=7, nz=6)
+    whole = D.init_perturbed(prm, 321, 1e-3)
+    for y0, y1, z0, z1 in ((0, 3, 0, 3), (2, 7, 1, 4), (4, 5, 5, 6)):
+        assert np.array_equal(D.init_perturbed_window(prm, 321, 1e-3, y0, y1, z0, z1), whole[:, z0:z1, y0:y1])
+
+
+def _close(a, b):
+    # the reference's back-transform solves a batch of linear systems, whose
+    # last bits depend on the batch: agreement to rounding, not bit for bit
+    return np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("zbc", ["walls", "periodic"])
+def test_windows_reproduce_the_duct(zbc):
+    """Windows of full-width rows stepped on their own (rates from the duct's
+    height) equal the whole duct's run on every row and layer more than n
+    steps from a cut face: corner, edge and interior windows; a row next to a
+    cut face does not."""
+    nx, ny, nz, n = 6, 9, 8, 2
+    prm = D.Params3D(nx=nx, ny=ny, nz=nz, zbc=zbc, kn=0.4, gx=1e-4, gy=2e-5, gz=-1e-5)
+    P0 = D.init_perturbed(prm, 55, 1e-3)
+    whole = D.run(P0, prm, n)
+    w = 2 * n + 1
+    # corner at y = 0, z = 0 (both walls in a duct): rows and layers 0 .. n
+    got = D.run_window(P0[:, :w, :w].copy(), prm, n)
+    if zbc == "walls":
+        assert _close(got[:, :n + 1, :n + 1], whole[:, :n + 1, :n + 1])
+    # top edge y = ny - 1 at interior layer zc: rows ny - n - 1 .. ny - 1 of layer zc
+    zc = 4
+    got = D.run_window(P0[:, zc - n:zc + n + 1, ny - w:].copy(), prm, n)
+    assert _close(got[:, n, n:], whole[:, zc, ny - n - 1:])
+    assert not _close(got[:, n, 0], whole[:, zc, ny - w])
+    # interior: the middle row of the middle layer
+    yc = 4
+    got = D.run_window(P0[:, zc - n:zc + n + 1, yc - n:yc + n + 1].copy(), prm, n)
+    assert _close(got[:, n, n], whole[:, zc, yc])
+    assert not _close(got[:, 0, n], whole[:, zc - n, yc])
+    # all layers of a z-periodic channel: z stays periodic, rows 0 .. n valid
+    if zbc == "periodic":
+        got = D.run_window(P0[:, :, :w].copy(), prm, n)
+        assert _close(got[:, :, :n + 1], whole[:, :, :n + 1])
