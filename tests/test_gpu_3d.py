@@ -72,6 +72,38 @@ def test_larger_duct_parity():
     s.close()
 
 
+def test_full_size_duct_windows():
+    """The benchmarked duct itself (512 x 256 x 256, Kn = 0.5, g = 1e-6,
+    seeded perturbed start), two steps on the GPU, against the reference
+    stepped from the same seeded start on windows of full-width rows: two
+    opposite duct edges (corners of the cross-section), a wall face and the
+    interior, every node of their valid rows.  The reference takes its input
+    from the seeded generator only."""
+    from clb_inputs import WORKLOADS
+    w = dict(WORKLOADS["duct_512x256x256"])
+    s = _duct(**w)
+    n = 2
+    s.step(n)
+    P = s.populations()
+    prm = _oracle_params(w)
+    ny, nz, k = prm.ny, prm.nz, 2 * n + 1
+    # (y0, z0) of each k x k window and the valid (row, layer) slices in it
+    windows = [
+        (0, 0, slice(0, n + 1), slice(0, n + 1)),                       # corner y = 0, z = 0
+        (ny - k, nz - k, slice(n, k), slice(n, k)),                     # corner y = ny - 1, z = nz - 1
+        (0, 128 - n, slice(0, n + 1), slice(n, n + 1)),                 # bottom wall face, layer 128
+        (97 - n, nz - k, slice(n, n + 1), slice(n, k)),                 # side wall face, row 97
+        (128 - n, 77 - n, slice(n, n + 1), slice(n, n + 1)),            # interior node row
+    ]
+    for y0, z0, vy, vz in windows:
+        ref = D.run_window(D.init_perturbed_window(prm, w["seed"], w["init_amp"], y0, y0 + k, z0, z0 + k),
+                           prm, n)[:, vz, vy]
+        got = P[:, z0:z0 + k, y0:y0 + k][:, vz, vy].cpu().numpy()
+        assert _rel(got, ref) <= TOL, (y0, z0)
+    del P
+    s.close()
+
+
 @pytest.mark.parametrize("init", ["uniform", "perturbed"])
 def test_start_states(init):
     kw = dict(nx=6, ny=5, nz=4, kn=0.2, rho0=1.1, init=init, init_amp=1e-3, seed=11)
