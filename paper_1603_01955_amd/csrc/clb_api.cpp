@@ -372,7 +372,7 @@ hipError_t enqueue_steps(const clb_ctx* c, int64_t n, hipStream_t st, int* cur) 
   const bool periodic = c->p.xbc == CLB_X_PERIODIC;
   int k = c->steps_per_launch;
   if (periodic && !clb::periodic_multi_step_ok(step_args(c))) k = 1;
-  if (!periodic && !clb::pressure_two_step_ok(step_args(c))) k = 1;
+  if (!periodic && !clb::pressure_multi_step_ok(step_args(c))) k = 1;
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {
     clb::StepArgs a = step_args(c);

@@ -146,9 +146,9 @@ constexpr size_t kPBatchRowNodes = (size_t)1 << 21;
 // as for launch_step (row kernel only).
 hipError_t launch_pbatch_step(const PBatchArgs& a, hipStream_t st, size_t lds_reserve = 0);
 // k = 2..4 steps of every active channel in one launch, where
-// pbatch_two_step_ok holds (ny <= 48, column-kernel path for the running
+// pbatch_multi_step_ok holds (ny <= 48, column-kernel path for the running
 // channels); needs stepk_setup.
-bool pbatch_two_step_ok(const PBatchArgs& a);
+bool pbatch_multi_step_ok(const PBatchArgs& a);
 hipError_t launch_pbatch_stepk(const PBatchArgs& a, int k, hipStream_t st);
 // k = 2, 3 or 4 periodic or pressure-driven steps in one launch (a.src ->
 // a.dst, the steps before the last kept in LDS); stepk_setup allows their
@@ -156,9 +156,9 @@ hipError_t launch_pbatch_stepk(const PBatchArgs& a, int k, hipStream_t st);
 hipError_t stepk_setup();
 hipError_t launch_stepk(const StepArgs& a, int k, hipStream_t st);
 bool periodic_multi_step_ok(const StepArgs& a);   // nx >= 64
-// Pressure-driven form; only where pressure_two_step_ok holds (ny <= 48,
+// Pressure-driven form; only where pressure_multi_step_ok holds (ny <= 48,
 // column-kernel path).
-bool pressure_two_step_ok(const StepArgs& a);
+bool pressure_multi_step_ok(const StepArgs& a);
 hipError_t launch_stepk_pressure(const StepArgs& a, int k, hipStream_t st);
 hipError_t launch_init(const InitArgs& a, hipStream_t st);
 // Plain copy of n16 16-byte words (HBM ceiling probe).

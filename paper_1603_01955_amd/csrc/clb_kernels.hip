@@ -860,7 +860,7 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
   return hipGetLastError();
 }
 
-// Multi-step pressure launches: channels of at most kPressureTwoStepRows rows
+// Multi-step pressure launches: channels of at most kPressureMultiStepRows rows
 // on the column kernel's path (grids that take the row kernel step one at a
 // time).  Measured with two steps per launch, us per step one / two: 2000 x
 // 20 4.35 / 3.48, 4000 x 40 6.37 / 4.99, 8192 x 40 11.75 / 8.74, 32768 x 16
@@ -870,12 +870,12 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
 // at two / three / four steps per launch (16-column tiles; 8-column tiles
 // 5.04 / 4.75 / 6.07), the batch of 16 channels of 2000 x 20 15.4 / 13.9 /
 // 12.4 us (32-column tiles).
-constexpr int kPressureTwoStepRows = 48;
+constexpr int kPressureMultiStepRows = 48;
 
-bool pressure_two_step_ok(const StepArgs& a) {
+bool pressure_multi_step_ok(const StepArgs& a) {
   const bool rows = a.col_rates && a.ghosts &&
                     (a.pressure_path == 2 || (a.pressure_path == 0 && (size_t)a.g.nx * a.g.ny >= kPressureRowNodes));
-  return a.mode == 1 && a.g.ny <= kPressureTwoStepRows && !rows;
+  return a.mode == 1 && a.g.ny <= kPressureMultiStepRows && !rows;
 }
 
 // Width of K2e: the widest of 32, 16, 8 columns with (CX + 2(k - 1)) ny <=
@@ -897,7 +897,7 @@ size_t stepk_pressure_lds(const Geo& g, int cx, int k) {
 
 // LDS of a K2e workgroup at most: (CX + 2(k - 1)) ny <= 1024 nodes of 9
 // doubles plus two ghost columns of at most 48 rows.
-constexpr int kStepKPressureLdsMax = (9 * 1024 + 18 * kPressureTwoStepRows) * (int)sizeof(double);
+constexpr int kStepKPressureLdsMax = (9 * 1024 + 18 * kPressureMultiStepRows) * (int)sizeof(double);
 
 template <int CX, int K>
 hipError_t pressure_allow() {
@@ -937,10 +937,10 @@ hipError_t launch_stepk_pressure(const StepArgs& a, int k, hipStream_t st) {
   return hipGetLastError();
 }
 
-bool pbatch_two_step_ok(const PBatchArgs& a) {
+bool pbatch_multi_step_ok(const PBatchArgs& a) {
   const bool rows = a.col_rates && a.ghosts &&
                     (a.path == 2 || (a.path == 0 && (size_t)a.nch * a.g.nx * a.g.ny >= kPBatchRowNodes));
-  return a.g.ny <= kPressureTwoStepRows && !rows;
+  return a.g.ny <= kPressureMultiStepRows && !rows;
 }
 
 hipError_t launch_pbatch_stepk(const PBatchArgs& a, int k, hipStream_t st) {

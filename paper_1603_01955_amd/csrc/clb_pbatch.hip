@@ -184,7 +184,7 @@ void drop_graphs(clb_pbatch* b) {
 clb_status enqueue_chunk(clb_pbatch* b, hipStream_t st, int* par, int64_t n, int check, double tol) {
   clb::PBatchArgs a = b->args;
   a.nch = b->n_live;
-  const int k = b->n_live > 0 && clb::pbatch_two_step_ok(a) ? b->steps_per_launch : 1;
+  const int k = b->n_live > 0 && clb::pbatch_multi_step_ok(a) ? b->steps_per_launch : 1;
   for (int64_t left = n; left > 0 && b->n_live > 0;) {
     a.par = *par;
     const int m = left < k ? (int)left : k;
