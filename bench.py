@@ -539,7 +539,15 @@ def main():
         prof.get("steps_per_launch", 0)) == k else None
     fp64 = float(prof["fp64_valu_insts_per_launch"]) if "fp64_valu_insts_per_launch" in prof and int(
         prof.get("steps_per_launch", 0)) == k else None
+    valu = float(prof["valu_insts_per_launch"]) if "valu_insts_per_launch" in prof and int(
+        prof.get("steps_per_launch", 0)) == k else None
     copy_gbs = copy_bandwidth()
+    # Lower bounds on the launch time: its counted HBM bytes at the copy rate
+    # measured above, and its counted VALU instructions at one wave
+    # instruction per CU per clock.  The larger one over the measured time is
+    # how close the launch runs to what binds it.
+    t_hbm = traffic / (copy_gbs * 1e9) if traffic else None
+    t_valu = valu / FP64_WAVE_INSTS_PER_S if valu else None
     rec = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -576,7 +584,10 @@ def main():
                      "fp64_issue_frac": round(fp64 / launch_s / FP64_WAVE_INSTS_PER_S, 4) if fp64 else None,
                      # node updates x 144 B over the time: the bandwidth a one-step kernel would need
                      "effective_gbs": round(BYTES_PER_NODE * nodes * k / launch_s / 1e9, 1),
-                     "two_steps_per_launch": alt},
+                     "two_steps_per_launch": alt,
+                     "bound_us": {"hbm_at_copy_rate": round(t_hbm * 1e6, 1) if t_hbm else None,
+                                  "valu_issue": round(t_valu * 1e6, 1) if t_valu else None},
+                     "bound_time_frac": round(max(t_hbm, t_valu) / launch_s, 4) if t_hbm and t_valu else None},
     }
     s.close()
     del s
