@@ -179,7 +179,22 @@ def kn_sweep(max_steps=400000, check_every=1000, tol=1e-12, baselines=True, forc
         "batched_s": round(t_batch, 4), "loop_s": round(t_loop, 4), "graph_loop_s": round(t_graph, 4),
         "speedup_vs_loop": round(t_loop / t_batch, 2), "speedup_vs_graph_loop": round(t_graph / t_batch, 2),
         "tuned": {"threads": threads, "longest_first": longest, "tune_s": round(t_tune, 3)},
+        "cpu_oracle": kn_sweep_oracle(heights, kns, forcing),
     }
+
+
+def kn_sweep_oracle(heights, kns, forcing):
+    """The CPU reference on the sweep's tallest channel, the one that sets
+    the batch's time (the reference steps channels one at a time)."""
+    import numpy as np
+    from oracle import clb_ref as C
+    j = int(np.argmax(heights))
+    prm = C.Params(nx=4, ny=int(heights[j]), kn=float(kns[j]), gx=1e-6, forcing=forcing)
+    st = {"P": C.init_uniform(prm)}
+
+    def step():
+        st["P"] = C.step(st["P"], prm)
+    return oracle_rate(step, prm.nx * prm.ny, "the 4 x %d channel at Kn = %.3g" % (prm.ny, prm.kn), budget_s=2.0)
 
 
 def kn_minimum(ny=64, count=48, kn_lo=0.3, kn_hi=3.0, forcing=0, max_steps=400000, check_every=1000,
@@ -246,10 +261,27 @@ def adjoint_calibration(T=2000, K=45, repeats=3):
         tb.append(t2 - t1)
     adj.close()
     f, b = min(tf), min(tb)
+    from threadpoolctl import threadpool_limits
+    from oracle import adjoint_ref as AR
+    from oracle import clb_ref as C
+    prm = C.Params(nx=2000, ny=20, xbc="pressure", kn=0.1, p_ratio=2.0, a=theta0[0], A1=theta0[1], A2=theta0[2],
+                   r=theta0[3])
+    Tc = 3
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        AR.complex_step_grad(prm, Tc, np.zeros(2000), 1.0)
+        tc = time.perf_counter() - t0
     return {"workload": "long_2000x20", "T": T, "K": K, "loss": loss,
             "grad": {"a": g[0], "A1": g[1], "A2": g[2], "r": g[3]},
             "forward_s": round(f, 4), "backward_s": round(b, 4),
-            "backward_over_forward": round(b / f, 3)}
+            "backward_over_forward": round(b / f, 3),
+            # gradient steps per second: steps of a run whose full gradient
+            # (all four parameters) is had per second of forward + backward
+            "gradient_steps_per_s": round(T / (f + b), 1),
+            "cpu_oracle": {"value": round(Tc / tc, 3), "unit": "gradient steps per s", "cores": 1,
+                           "kind": "oracle",
+                           "sample": "complex-step gradient (four complex128 runs) of %d steps of the same "
+                                     "channel, NumPy, one thread, %.1f s" % (Tc, tc)}}
 
 
 def pressure_step(nx=4000, ny=40, steps=200000, spl=None):
@@ -286,7 +318,19 @@ def pressure_step(nx=4000, ny=40, steps=200000, spl=None):
             "dp_max": round(float(dp[k]), 6), "x_over_L_at_dp_max": round((k + 0.5) / nx, 4),
             "dp_profile": {"x_over_L": at, "dp": [round(float(dp[min(nx - 1, int(a * nx))]), 6) for a in at]},
             "massflow_mean": float(m),
-            "massflow_spread": float((m_col.max() - m_col.min()) / abs(m))}
+            "massflow_spread": float((m_col.max() - m_col.min()) / abs(m)),
+            "cpu_oracle": pressure_oracle(nx, ny)}
+
+
+def pressure_oracle(nx, ny):
+    """The CPU reference on the same channel from the same start."""
+    from oracle import clb_ref as C
+    prm = C.Params(nx=nx, ny=ny, xbc="pressure", kn=0.1, p_ratio=2.0)
+    st = {"P": C.init_linear_rho(prm)}
+
+    def step():
+        st["P"] = C.step(st["P"], prm)
+    return oracle_rate(step, nx * ny, "the %dx%d channel" % (nx, ny))
 
 
 def duct3d(steps=100, warmup=5):
@@ -314,7 +358,15 @@ def duct3d(steps=100, warmup=5):
     del s
     torch.cuda.empty_cache()
     gbs = 432.0 * nodes / (ms * 1e-3) / 1e9
+    from oracle import clb3d_ref as D
+    prm = D.Params3D(nx=w["nx"], ny=w["ny"], nz=w["nz"], kn=w["kn"], gx=w["gx"])
+    win = {"P": D.init_perturbed_window(prm, w["seed"], w["init_amp"], 0, 8, 0, 8)}
+
+    def step():
+        win["P"] = D.run_window(win["P"], prm, 1)
+    cpu = oracle_rate(step, w["nx"] * 64, "a 512 x 8 x 8 corner window of the same duct (the duct's rates)")
     return {"workload": "duct_512x256x256", "steps": steps, "ms_per_step": round(ms, 4), "finite": ok,
+            "cpu_oracle": cpu,
             "mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "unit_bytes": "432 B per node update"}}
@@ -407,6 +459,14 @@ def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2
            "batched_to_steady_s": round(t_batch, 3),
            "batched_step_us": round(us_batch, 3), "batched_mlups": round(nodes / us_batch, 1),
            "batched_algorithmic_gbs": round(BYTES_PER_NODE * nodes / us_batch / 1e3, 1)}
+    from oracle import clb_ref as C
+    prm0 = C.Params(nx=w["nx"], ny=w["ny"], xbc="pressure", kn=kns[0], p_ratio=w["p_ratio"], sigma=w["sigma"])
+    st = {"P": C.init_linear_rho(prm0)}
+
+    def ostep():
+        st["P"] = C.step(st["P"], prm0)
+    out["cpu_oracle"] = oracle_rate(ostep, w["nx"] * w["ny"], "one channel of the batch (the first; the reference "
+                                    "steps channels one at a time)")
     if not baselines:
         return out
     s = single(params[0])
@@ -436,6 +496,25 @@ def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2
     out["loop_steps_match"] = bool((np.array(steps_l) == steps_b).all())
     out["speedup_vs_graph_loop"] = round(t_loop / t_batch, 2)
     return out
+
+
+def oracle_rate(step, nodes, sample, budget_s=3.0):
+    """The CPU reference as it stands, one thread, timed beside a GPU row:
+    step() advances its state by one step of `nodes` node updates; steps
+    are taken (after one warm-up step) until budget_s has passed."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        step()
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            step()
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget_s:
+                break
+    return {"value": round(nodes * n / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "%d steps of %s, NumPy FP64, one thread, %.1f s" % (n, sample, dt)}
 
 
 def cpu_baseline():
