@@ -28,7 +28,9 @@ definitions allow; every point below is a reading, not a printed formula:
     Knudsen number of the height); r from Eq. (21), the same on every wall.
   * Walls: half-way planes below row y = 0 and above y = ny - 1 and, for a
     duct, below layer z = 0 and above z = nz - 1 (or z periodic: a channel).
-    x is periodic (force-driven, Section 3.1).  Eq. (20) in 3-D: when the
+    x is periodic (force-driven, Section 3.1) or, for a pressure-driven duct
+    (Section 3.2 carried to 3-D), bounded by ghost planes x = -1 and x = nx
+    (below).  Eq. (20) in 3-D: when the
     pull source n - e of direction e at node n lies behind the wall planes of
     a set S of axes (one axis, or both y and z at a duct edge),
         pre_e(n) = r P_{-e}(n) + (1 - r) P_{e'}(n - e_t),
@@ -41,6 +43,19 @@ definitions allow; every point below is a reading, not a printed formula:
     reflects a population leaving across one wall into a direction that
     crosses both), so ducts take cbbsr_shift = 1; the same-node variant is
     kept for z-periodic channels.
+  * Pressure-driven ducts: the 2-D inlet/outlet reading applied row by row
+    of each cross-section: for every (y, z) the ghost population is
+    f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1), rho_1, u_1
+    from the column next to the plane and u_2 from the one after it
+    (rho_b = p_ratio rho_out at the inlet, rho_out at the outlet), no force;
+    a pull or specular source beyond x = 0 or x = nx - 1 takes the ghost
+    value.  The local Knudsen number of column x is Kn_out rho_out /
+    rho_c(x), rho_c the mean pre-collision density of the central node(s) of
+    the cross-section (the middle row, or the mean of the two middle rows,
+    of the middle layer(s)) at the same step; s_nu(x) and s_q(x) follow from
+    Eqs. (18) and (21) with N = ny; the bulk rate stays s_b.  The start is
+    f^eq(rho(x), 0) with rho falling linearly from rho_in at the inlet plane
+    to rho_out at the outlet (x_i = i + 1/2, L = nx).
 
 Parity with the paper: unpinned (no 3-D scheme or number is printed).  The
 reference is pinned instead by mathematics (tests/test_oracle_3d.py):
@@ -101,12 +116,19 @@ class Params3D:
     rho0: float = 1.0
     tq_den: float = 16.0          # Eq. (21) denominator
     cbbsr_shift: int = 1
+    xbc: str = "periodic"         # "periodic" (force-driven) or "pressure" (Section 3.2 carried to 3-D)
+    p_ratio: float = 2.0          # p_in / p_out (pressure mode)
+    rho_out: float = 1.0
 
 
 def resolved(prm):
     A1 = prm.A1 if prm.A1 is not None else slip_A1(prm.sigma)
     r = prm.r if prm.r is not None else bounce_fraction(A1)
     return A1, r
+
+
+def rho_in(prm):
+    return prm.p_ratio * prm.rho_out
 
 
 def rates(prm):
@@ -190,15 +212,36 @@ def collide(pre, g, s_b, s_nu, s_q, s8):
 # ---------------------------------------------------------------------------
 # Streaming (Eq. 5) with the walls (Eq. 20 in 3-D) -> pre-collision state.
 # ---------------------------------------------------------------------------
+def ghost_planes(P, prm):
+    """Ghost planes x = -1 (inlet) and x = nx (outlet) of a pressure-driven
+    duct, (27, nz, ny) each, by the reading in the module docstring."""
+    def plane(c1, c2, rho_b):
+        f1, f2 = P[:, :, :, c1], P[:, :, :, c2]
+        rho1, u1 = macroscopic(f1)
+        _, u2 = macroscopic(f2)
+        n = rho1.size
+        eq_g = equilibrium((2.0 * rho_b - rho1).ravel(), (2.0 * u1 - u2).reshape(3, n)).reshape(f1.shape)
+        eq_1 = equilibrium(rho1.ravel(), u1.reshape(3, n)).reshape(f1.shape)
+        return eq_g + (f1 - eq_1)
+    nx = P.shape[3]
+    return plane(0, 1, rho_in(prm)), plane(nx - 1, nx - 2, prm.rho_out)
+
+
 def stream_bc(P, prm, r=None):
     if r is None:
         r = resolved(prm)[1]
     _, nz, ny, nx = P.shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     zwalls = prm.zbc == "walls"
-    pre = np.empty_like(P)
+    pressure = prm.xbc == "pressure"
+    if pressure:
+        # x index shifted by one: 0 is the inlet ghost plane, nx + 1 the outlet one
+        g_in, g_out = ghost_planes(P, prm)
+        P = np.concatenate([g_in[..., None], P, g_out[..., None]], axis=3)
+        x = x + 1
+    pre = np.empty((Q3, nz, ny, nx))
     for i, (a, b, c) in enumerate(E3):
-        xs = (x - a) % nx
+        xs = x - a if pressure else (x - a) % nx
         ys = y - b
         zs = z - c
         out_y = (ys < 0) | (ys >= ny)
@@ -229,9 +272,35 @@ def stream_bc(P, prm, r=None):
     return pre
 
 
+def central(n):
+    """Index of the middle row (odd n) or of the two middle rows (even n)."""
+    return [n // 2] if n % 2 else [n // 2 - 1, n // 2]
+
+
+def centre_density(rho):
+    """rho_c(x): mean density of the central node(s) of each cross-section,
+    rho of shape (nz, ny, nx)."""
+    nz, ny, _ = rho.shape
+    return rho[central(nz)][:, central(ny)].mean(axis=(0, 1))
+
+
+def local_rates(pre, prm):
+    """s_nu(x), s_q(x) of a pressure-driven duct from the local Knudsen
+    number Kn_out rho_out / rho_c(x) of the pre-collision state (Eqs. 18, 21,
+    N = ny)."""
+    rho, _ = macroscopic(pre)
+    kn = prm.kn * prm.rho_out / centre_density(rho)
+    return rate_nu(kn, prm.ny, prm.a), rate_q(kn, prm.ny, prm.a, prm.A2, prm.tq_den)
+
+
 def step(P, prm):
     _, r = resolved(prm)
     pre = stream_bc(P, prm, r)
+    if prm.xbc == "pressure":
+        s_nu, s_q = local_rates(pre, prm)
+        shape = (prm.nz, prm.ny, prm.nx)
+        return collide(pre, (0.0, 0.0, 0.0), prm.s_b, np.broadcast_to(s_nu, shape).ravel(),
+                       np.broadcast_to(s_q, shape).ravel(), prm.s8)
     return collide(pre, (prm.gx, prm.gy, prm.gz), *rates(prm))
 
 
@@ -248,6 +317,16 @@ def init_uniform(prm):
     n = prm.nx * prm.ny * prm.nz
     feq = equilibrium(np.full(n, prm.rho0), np.zeros((3, n)))
     return feq.reshape(Q3, prm.nz, prm.ny, prm.nx)
+
+
+def init_linear_rho(prm):
+    """f^eq(rho(x), 0), rho falling linearly from rho_in at the inlet plane
+    x = 0 to rho_out at the outlet plane x = nx (node centres x_i = i + 1/2)."""
+    x = np.arange(prm.nx, dtype=np.float64) + 0.5
+    rho = rho_in(prm) - (rho_in(prm) - prm.rho_out) * x / prm.nx
+    rho3 = np.broadcast_to(rho, (prm.nz, prm.ny, prm.nx)).ravel()
+    n = rho3.size
+    return equilibrium(rho3, np.zeros((3, n))).reshape(Q3, prm.nz, prm.ny, prm.nx)
 
 
 def init_perturbed(prm, seed, amp):
@@ -298,6 +377,23 @@ def run_window(P, prm, nsteps):
 def moments(P, prm):
     """rho (nz, ny, nx) and u (3, nz, ny, nx) of the pre-collision state."""
     return macroscopic(stream_bc(P, prm), (prm.gx, prm.gy, prm.gz))
+
+
+def mass_flow(P, prm):
+    """m(x) = sum_{y,z} rho u_x of the pre-collision state (a pressure-driven
+    duct's mass flow through each cross-section)."""
+    rho, u = moments(P, prm)
+    return (rho * u[0]).sum(axis=(0, 1))
+
+
+def pressure_deviation(P, prm):
+    """delta p(x) = (p_c(x) - p_l(x)) / p_out along the duct's centre line,
+    p = rho/3, p_l linear from p_in at x = 0 to p_out at x = L = nx."""
+    rho, _ = moments(P, prm)
+    p_out, p_in = prm.rho_out / 3.0, rho_in(prm) / 3.0
+    x = np.arange(prm.nx, dtype=np.float64) + 0.5
+    p_l = p_in - (p_in - p_out) * x / prm.nx
+    return (centre_density(rho) / 3.0 - p_l) / p_out
 
 
 def flow_rate_Q(P, prm):

@@ -8,6 +8,8 @@ of square ducts, the discrete slip channel of the 2-D analysis, and the
 continuum Poiseuille flow rate of a rectangular duct."""
 from math import pi, tanh
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -311,3 +313,113 @@ def test_windows_reproduce_the_duct(zbc):
     if zbc == "periodic":
         got = D.run_window(P0[:, :, :w].copy(), prm, n)
         assert _close(got[:, :, :n + 1], whole[:, :, :n + 1])
+
+
+# ---------------------------------------------------------------------------
+# Pressure-driven ducts (the 2-D inlet/outlet reading carried to 3-D).
+# ---------------------------------------------------------------------------
+def _pduct(**kw):
+    base = dict(nx=9, ny=5, nz=4, xbc="pressure", kn=0.2, p_ratio=1.8)
+    base.update(kw)
+    return D.Params3D(**base)
+
+
+def _opp_y(P):
+    """Mirror y -> ny - 1 - y of populations (27, nz, ny, nx), directions b -> -b."""
+    idx = [D.direction(a, -b, c) for a, b, c in D.E3]
+    return P[idx][:, :, ::-1]
+
+
+def _opp_z(P):
+    idx = [D.direction(a, b, -c) for a, b, c in D.E3]
+    return P[idx][:, ::-1]
+
+
+def test_pressure_rest_state_is_steady():
+    """Equal inlet and outlet pressure: the rest state is a fixed point."""
+    prm = _pduct(p_ratio=1.0)
+    P0 = D.init_linear_rho(prm)
+    P = D.run(P0, prm, 5)
+    assert np.max(np.abs(P - P0)) <= 1e-15
+
+
+def test_pressure_linear_start_pull():
+    """From the linear-density rest start the pull gives, at every column
+    including the two next to the ghost planes, the node's own density and
+    the momentum -(1/3) d rho/dx of the profile (interior rows and layers;
+    the ghost density extrapolation makes the profile linear through the
+    planes)."""
+    prm = _pduct(nx=7, ny=5, nz=5, p_ratio=1.6)
+    P = D.init_linear_rho(prm)
+    pre = D.stream_bc(P, prm)
+    rho, j = pre.sum(axis=0), np.tensordot(D.E3.T.astype(float), pre, (1, 0))
+    x = np.arange(prm.nx) + 0.5
+    rho_x = D.rho_in(prm) - (D.rho_in(prm) - prm.rho_out) * x / prm.nx
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.max(np.abs(rho[inner] - rho_x)) <= 1e-14
+    jx = (D.rho_in(prm) - prm.rho_out) / (3.0 * prm.nx)
+    assert np.max(np.abs(j[0][inner] - jx)) <= 1e-14
+    assert np.max(np.abs(j[1][inner])) <= 1e-14 and np.max(np.abs(j[2][inner])) <= 1e-14
+
+
+def test_pressure_ghost_plane_moments():
+    """Each ghost population row carries density 2 rho_b - rho_1 and
+    velocity 2 u_1 - u_2 (moments computed from the populations), and its
+    departure from its own equilibrium is that of the column next to it."""
+    from clb_inputs import uniform_populations_3d
+    prm = _pduct(nx=6, ny=4, nz=3, p_ratio=1.7, rho_out=1.1)
+    P = uniform_populations_3d(6, 4, 3, seed=19) * 1.2
+    g_in, g_out = D.ghost_planes(P, prm)
+    for g, c1, c2, rb in ((g_in, 0, 1, D.rho_in(prm)), (g_out, 5, 4, prm.rho_out)):
+        rho1, u1 = D.macroscopic(P[..., c1])
+        _, u2 = D.macroscopic(P[..., c2])
+        rg, ug = D.macroscopic(g)
+        assert np.max(np.abs(rg - (2.0 * rb - rho1))) <= 1e-13
+        assert np.max(np.abs(ug - (2.0 * u1 - u2))) <= 1e-12
+        n = rho1.size
+        eq_g = D.equilibrium(rg.ravel(), ug.reshape(3, n)).reshape(g.shape)
+        eq_1 = D.equilibrium(rho1.ravel(), u1.reshape(3, n)).reshape(g.shape)
+        assert np.max(np.abs((g - eq_g) - (P[..., c1] - eq_1))) <= 1e-13
+
+
+def test_pressure_interior_equals_periodic_step_at_local_kn():
+    """A state uniform along x: away from the ghost planes the pressure step
+    equals the periodic duct's step at Kn = Kn_out rho_out / rho_c, rho_c the
+    pre-collision density at the central nodes of the cross-section (odd and
+    even heights and widths)."""
+    from clb_inputs import uniform_populations_3d
+    for ny, nz in ((5, 4), (4, 5), (6, 6), (3, 3)):
+        prm = _pduct(nx=6, ny=ny, nz=nz, kn=0.3, p_ratio=1.5, rho_out=0.9)
+        col = uniform_populations_3d(1, ny, nz, seed=3 + ny)        # (27, nz, ny, 1)
+        P = np.repeat(col, prm.nx, axis=3)
+        got = D.step(P, prm)
+        per = D.Params3D(nx=prm.nx, ny=ny, nz=nz, kn=prm.kn)
+        rho, _ = D.macroscopic(D.stream_bc(P, per))
+        mid = {3: [1], 4: [1, 2], 5: [2], 6: [2, 3]}      # middle row(s) of 3 .. 6
+        rho_c = rho[mid[nz]][:, mid[ny], 0].mean()
+        per = dataclasses.replace(per, kn=prm.kn * prm.rho_out / rho_c)
+        ref = D.step(P, per)
+        assert np.max(np.abs(got[..., 1:-1] - ref[..., 1:-1])) <= 1e-14 * np.max(np.abs(ref)), (ny, nz)
+
+
+def test_pressure_symmetry_and_z_uniformity():
+    """The linear start of a duct stays mirror-symmetric in y and in z; that
+    of a z-periodic channel stays uniform along z."""
+    prm = _pduct(nx=8, ny=5, nz=4, p_ratio=1.9)
+    P = D.run(D.init_linear_rho(prm), prm, 4)
+    assert np.max(np.abs(P - _opp_y(P))) <= 1e-14
+    assert np.max(np.abs(P - _opp_z(P))) <= 1e-14
+    ch = _pduct(nx=8, ny=5, nz=3, zbc="periodic", p_ratio=1.9)
+    P = D.run(D.init_linear_rho(ch), ch, 4)
+    assert np.max(np.abs(P - P[:, :1])) <= 1e-15
+
+
+def test_pressure_duct_reaches_uniform_mass_flow():
+    """A short duct run from the linear start: the mass flow through every
+    cross-section becomes the same (steady state), positive, from the inlet
+    to the outlet."""
+    prm = _pduct(nx=20, ny=4, nz=4, kn=0.1, p_ratio=1.5)
+    P = D.run(D.init_linear_rho(prm), prm, 400)
+    m = D.mass_flow(P, prm)
+    assert m.min() > 0
+    assert (m.max() - m.min()) / m.mean() <= 1e-6
