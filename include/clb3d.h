@@ -1,6 +1,7 @@
 /*
  * clb3d.h -- C ABI of the 3-D cascaded lattice Boltzmann step for
- * force-driven gas flow in a rectangular microduct (MI355X, gfx950).
+ * force-driven or pressure-driven gas flow in a rectangular microduct
+ * (MI355X, gfx950).
  *
  * The paper (Liu & He, arXiv:1603.01955) develops its cascaded scheme in 2-D
  * and names the extension to rectangular ducts as future work (Section 4).
@@ -11,8 +12,24 @@
  * at s8, first order shifted by rho F as by the source of Eq. 9); the
  * combined bounce-back / specular wall of Eq. (20) on the duct walls, with
  * the reflected population taken from the node displaced along the walls
- * (at a duct edge the reflection reverses both normal components); x
- * periodic (force driven, Section 3.1).
+ * (at a duct edge the reflection reverses both normal components).  Two
+ * kinds of duct:
+ *  - force driven (xbc = CLB_X_PERIODIC, Section 3.1): x periodic, body
+ *    acceleration (gx, gy, gz), the rates of Eqs. (18), (21) at Kn;
+ *  - pressure driven (xbc = CLB_X_PRESSURE, Section 3.2): no force; ghost
+ *    planes x = -1 and x = nx hold, for every row (y, z) of the
+ *    cross-section, f^eq(2 rho_b - rho_1, 2 u_1 - u_2) + f_1 - f^eq(rho_1, u_1)
+ *    (rho_1, u_1, f_1 of the column next to the plane, u_2 of the one after
+ *    it, rho_b = p_ratio rho_out at the inlet, rho_out at the outlet; the
+ *    2-D inlet/outlet rule row by row), and a pull or displaced specular
+ *    source beyond the inlet or outlet takes the ghost value; the rates of
+ *    cross-section x follow from the local Knudsen number
+ *    Kn rho_out / rho_c(x), rho_c the pre-collision density at the centre of
+ *    the cross-section (the mean over the middle row, or the two middle
+ *    rows, of the middle layer, or the two middle layers), with N = ny in
+ *    Eq. (18); the bulk rate stays s_b.
+ * The D3Q27 equilibrium is the product over the axes of 2/3 - u^2 (e = 0)
+ * and (1/3 + u^2 + e u) / 2 (e = +-1), times rho.
  *
  * Conventions (as in clb.h): lattice units, FP64, the caller owns device
  * memory and the stream, every call returns a clb_status and enqueues its
@@ -45,7 +62,8 @@ typedef enum clb3_zbc {
 } clb3_zbc;
 
 /* Problem statement; clb3_params_default fills the values of Section 3
- * (a = 2, sigma = 1, B2 = 0.55, bulk rate 1.1, s8 = 1.2). */
+ * (a = 2, sigma = 1, B2 = 0.55, bulk rate 1.1, s8 = 1.2; force driven;
+ * p_ratio = 2, rho_out = 1 for a pressure-driven duct). */
 typedef struct clb3_params {
   int32_t nx, ny, nz;    /* fluid nodes along the duct, across its height, across its width (>= 1) */
   int32_t zbc;           /* clb3_zbc                                                        */
@@ -55,7 +73,13 @@ typedef struct clb3_params {
   int32_t cbbsr_shift;   /* Eq. 20 specular source: 1 = displaced along the walls (default);
                             0 = the node itself, z-periodic channels only (at duct edges it
                             does not conserve mass)                                         */
-  double kn;             /* Knudsen number of the height H = ny, > 0          Eq. 18         */
+  int32_t xbc;           /* clb_xbc: CLB_X_PERIODIC (force driven, default) or CLB_X_PRESSURE
+                            (pressure driven: nx >= 2, gx = gy = gz = 0; the init kind may
+                            also be CLB_INIT_LINEAR_RHO, f^eq(rho(x), 0) with rho falling
+                            linearly from p_ratio rho_out at x = 0 to rho_out at x = nx,
+                            node centres at x + 1/2)                                        */
+  double kn;             /* Knudsen number of the height H = ny (outlet Kn_out when pressure
+                            driven), > 0                                      Eq. 18         */
   double a;              /* Bosanquet rarefaction factor, >= 0                Eq. 16         */
   double sigma;          /* TMAC in (0, 2]; A1 = (1 - 0.1817 sigma)(2 - sigma)/sigma if A1 NaN */
   double A1;             /* first-order slip coefficient; NaN -> from sigma                   */
@@ -67,6 +91,8 @@ typedef struct clb3_params {
   double init_amp;       /* perturbation amplitude (CLB_INIT_PERTURBED), >= 0                   */
   uint64_t seed;         /* perturbation seed                                                   */
   double tq_den;         /* denominator of Eq. 21 (16 as printed)                               */
+  double p_ratio;        /* p_in / p_out (pressure driven), > 0               Sec. 3.2       */
+  double rho_out;        /* outlet density (pressure driven), > 0; p = rho / 3                  */
 } clb3_params;
 
 typedef struct clb3_ctx clb3_ctx;
@@ -78,8 +104,9 @@ void clb3_params_default(clb3_params* p);
 clb_status clb3_derive(const clb3_params* p, clb_derived* out);
 
 /* Device workspace in bytes: two population buffers (216 bytes per node,
- * rows padded to whole segments of the device layout) plus reduction
- * scratch. */
+ * rows padded to whole segments of the device layout), reduction scratch,
+ * three doubles per column and, for a pressure-driven duct, the two ghost
+ * planes (432 bytes per row of the cross-section). */
 clb_status clb3_workspace_size(const clb3_params* p, size_t* bytes);
 
 /* Create a context over the caller's workspace (device memory, 8-byte
@@ -87,7 +114,9 @@ clb_status clb3_workspace_size(const clb3_params* p, size_t* bytes);
  * hip_stream. */
 clb_status clb3_init(const clb3_params* p, void* d_workspace, size_t bytes, void* hip_stream, clb3_ctx** out);
 
-/* Advance nsteps >= 0 steps (Eqs. 5, 20 carried to 3-D, then the collision). */
+/* Advance nsteps >= 0 steps (Eqs. 5, 20 carried to 3-D, then the collision;
+ * a pressure-driven duct first builds the ghost planes and the rates of
+ * every cross-section from the state, three launches per step). */
 clb_status clb3_step(clb3_ctx* c, int64_t nsteps);
 
 /* Steps taken since clb3_init / the last clb3_set_populations. */
@@ -96,6 +125,21 @@ clb_status clb3_steps_done(const clb3_ctx* c, int64_t* h_steps);
 /* Density and velocity (rho u = sum e f + rho F / 2, Eqs. 12-13) of the
  * current pre-collision state, device arrays [nz][ny][nx]; any may be NULL. */
 clb_status clb3_moments(clb3_ctx* c, double* d_rho, double* d_ux, double* d_uy, double* d_uz);
+
+/* Mass flow through each cross-section (Section 3.2 carried to the duct):
+ * m(x) = sum_{y,z} rho u_x of the current pre-collision state
+ * (rho u_x = sum e_x f + rho gx / 2).  Optional per-column d_m_col[nx]
+ * (device); *h_m_mean (host, may be NULL) receives the mean over x and then
+ * the call synchronises.  Fixed summation order. */
+clb_status clb3_massflow(clb3_ctx* c, double* d_m_col, double* h_m_mean);
+
+/* Pressure deviation along the duct's centre line (Section 3.2):
+ * d_dp[x] = (p_c(x) - p_l(x)) / p_out, p_c = rho_c / 3 at the centre of the
+ * cross-section (as for the local Knudsen number), p_l falling linearly from
+ * p_in at x = 0 to p_out at x = nx (node centres x + 1/2); optional
+ * d_rho_c[x].  Device arrays of nx doubles, either may be NULL.
+ * Pressure-driven ducts only (CLB_ESTATE otherwise). */
+clb_status clb3_pressure_deviation(clb3_ctx* c, double* d_dp, double* d_rho_c);
 
 /* Dimensionless flow rate of Section 3.1 carried to the duct:
  * Q = sqrt(6) sum_{y,z} u_x / (3 gx H^2 W), averaged over x (for a z-periodic

@@ -15,12 +15,13 @@ class clb3_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("zbc", ctypes.c_int32), ("init", ctypes.c_int32), ("cbbsr_shift", ctypes.c_int32),
+        ("xbc", ctypes.c_int32),
         ("kn", ctypes.c_double), ("a", ctypes.c_double), ("sigma", ctypes.c_double),
         ("A1", ctypes.c_double), ("A2", ctypes.c_double), ("r", ctypes.c_double),
         ("s_b", ctypes.c_double), ("s8", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
         ("rho0", ctypes.c_double), ("init_amp", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("tq_den", ctypes.c_double),
+        ("tq_den", ctypes.c_double), ("p_ratio", ctypes.c_double), ("rho_out", ctypes.c_double),
     ]
 
 
@@ -34,6 +35,8 @@ _SIGNATURES3 = {
     "clb3_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "clb3_steps_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "clb3_moments": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "clb3_massflow": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "clb3_pressure_deviation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "clb3_flow_rate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "clb3_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "clb3_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -54,13 +57,15 @@ def lib():
 
 def make_params3(nx, ny, nz, zbc="walls", kn=0.1, a=2.0, sigma=1.0, A1=None, A2=0.55, r=None, s_b=1.1, s8=1.2,
                  gx=0.0, gy=0.0, gz=0.0, rho0=1.0, init="uniform", init_amp=0.0, seed=0, tq_den=16.0,
-                 cbbsr_shift=1):
+                 cbbsr_shift=1, xbc="periodic", p_ratio=2.0, rho_out=1.0):
     p = clb3_params()
     lib().clb3_params_default(ctypes.byref(p))
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.zbc = {"walls": CLB3_Z_WALLS, "periodic": CLB3_Z_PERIODIC}[zbc] if isinstance(zbc, str) else int(zbc)
-    p.init = {"uniform": clb.INIT_UNIFORM, "perturbed": clb.INIT_PERTURBED}[init] if isinstance(init, str) \
-        else int(init)
+    p.init = {"uniform": clb.INIT_UNIFORM, "perturbed": clb.INIT_PERTURBED,
+              "linear_rho": clb.INIT_LINEAR_RHO}[init] if isinstance(init, str) else int(init)
+    p.xbc = {"periodic": clb.X_PERIODIC, "pressure": clb.X_PRESSURE}[xbc] if isinstance(xbc, str) else int(xbc)
+    p.p_ratio, p.rho_out = float(p_ratio), float(rho_out)
     p.cbbsr_shift = int(cbbsr_shift)
     p.kn, p.a, p.sigma = float(kn), float(a), float(sigma)
     p.A1 = math.nan if A1 is None else float(A1)
@@ -86,8 +91,8 @@ def workspace_size3(params):
 
 
 class Duct:
-    """Force-driven flow in a rectangular microduct (or a z-periodic
-    channel), D3Q27 cascaded step; populations live in a torch-allocated
+    """Force-driven or pressure-driven flow in a rectangular microduct (or a
+    z-periodic channel), D3Q27 cascaded step; populations live in a torch-allocated
     device workspace, every call enqueues on the current torch stream."""
 
     def __init__(self, params=None, device="cuda", stream=None, **kw):
@@ -133,6 +138,19 @@ class Duct:
         rho, ux, uy, uz = (self._empty(self.nz, self.ny, self.nx) for _ in range(4))
         clb.check(lib().clb3_moments(self._ctx, clb._ptr(rho), clb._ptr(ux), clb._ptr(uy), clb._ptr(uz)))
         return rho, ux, uy, uz
+
+    def massflow(self):
+        """(m(x) per cross-section, device tensor [nx]; its mean over x)."""
+        m = self._empty(self.nx)
+        mean = ctypes.c_double()
+        clb.check(lib().clb3_massflow(self._ctx, clb._ptr(m), ctypes.byref(mean)))
+        return m, mean.value
+
+    def pressure_deviation(self):
+        """(dp(x), rho_c(x)) along the centre line, device tensors [nx]."""
+        dp, rc = self._empty(self.nx), self._empty(self.nx)
+        clb.check(lib().clb3_pressure_deviation(self._ctx, clb._ptr(dp), clb._ptr(rc)))
+        return dp, rc
 
     def flow_rate(self):
         q = ctypes.c_double()

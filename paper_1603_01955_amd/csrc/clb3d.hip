@@ -1,12 +1,17 @@
-// 3-D cascaded LB step for force-driven gas flow in a rectangular microduct
-// (D3Q27, FP64), declared in include/clb3d.h.
+// 3-D cascaded LB step for gas flow in a rectangular microduct (D3Q27, FP64),
+// force-driven or pressure-driven, declared in include/clb3d.h.
 //
 // Method: the 2-D scheme of Liu & He (arXiv:1603.01955) carried to 3-D, the
 // extension the paper names as future work (Section 4): pull streaming
 // (Eq. 5) with the combined bounce-back / specular wall of Eq. (20) on the
 // duct walls, then the cascaded collision (Eqs. 6-9, 13) in central-moment
-// form.  One kernel per step: gather, collide, store -- 216 B read and
-// 216 B written per node update.
+// form.  Force-driven ducts (x periodic, Section 3.1): one kernel per step,
+// gather, collide, store -- 216 B read and 216 B written per node update.
+// Pressure-driven ducts (Section 3.2 carried to 3-D): per step the two ghost
+// planes x = -1, x = nx (k3_ghosts), the relaxation rates of every
+// cross-section from the local Knudsen number at its centre (k3_rates),
+// then the step, which pulls across the inlet and outlet from the ghost
+// planes.
 //
 // Device layout: each (y, z) row is cut into segments of L = min(1024, the
 // next power of two >= nx) columns, and a segment stores its 27 directions
@@ -41,7 +46,18 @@ struct Args {
   double r, omr;        // bounce-back fraction and 1 - r
   double gx, gy, gz;
   double sb, snu, sq, s8;
+  // pressure-driven ducts (pressure = 1)
+  int pressure;
+  double rho_in, rho_out;   // boundary densities, p = rho / 3
+  double kn, ab, A2, tq_den, c_tau;   // Kn_out, Eq. (18) a, B2, Eq. (21) denominator, sqrt(6/pi) ny
+  double* ghosts;           // [2][27][nz][ny]: inlet plane x = -1, outlet plane x = nx
+  double* col_rates;        // [2][nx]: s_nu(x), then s_q(x)
 };
+
+// Ghost population i of side (0 inlet, 1 outlet) at row y, layer z.
+__device__ __forceinline__ double ghost(const Args& a, int side, int i, int y, int z) {
+  return a.ghosts[((size_t)(side * 27 + i) * (size_t)a.nz + (size_t)z) * (size_t)a.ny + (size_t)y];
+}
 
 // Logical node number (the ABI order, x fastest).
 __device__ __forceinline__ size_t node_index(const Args& a, int x, int y, int z) {
@@ -56,11 +72,15 @@ __device__ __forceinline__ size_t dev_index(const Args& a, int x, int y, int z) 
 }
 
 // Pre-collision populations of node (x, y, z): pull streaming (Eq. 5), x
-// periodic, z periodic or walled; where the source n - e lies behind the
-// wall planes of a set S of axes, Eq. (20) carried to 3-D:
+// periodic (PRESSURE false) or open at the inlet and outlet with the source
+// taken from the ghost planes (PRESSURE true), z periodic or walled; where
+// the source n - e lies behind the wall planes of a set S of axes, Eq. (20)
+// carried to 3-D:
 //   pre_e(n) = r P_{-e}(n) + (1 - r) P_{e'}(n - e_t),
 // e' = e with its components along S reversed, e_t = e without them (the
-// node itself when shift = 0).
+// node itself when shift = 0); a displaced source beyond the inlet or the
+// outlet is a ghost value.
+template <bool PRESSURE>
 __device__ __forceinline__ void gather(const Args& a, int x, int y, int z, double f[27]) {
 #pragma clang fp contract(off)
   const double* __restrict__ P = a.src;
@@ -73,7 +93,9 @@ __device__ __forceinline__ void gather(const Args& a, int x, int y, int z, doubl
       for (int e = -1; e <= 1; ++e) {
         const int i = (e + 1) + 3 * (b + 1) + 9 * (c + 1);
         int xs = x - e;
-        xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+        if (!PRESSURE) xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+        const bool gh = PRESSURE && (xs < 0 || xs >= a.nx);   // the source lies on a ghost plane
+        const int side = xs < 0 ? 0 : 1;
         const int ys = y - b;
         int zs = z - c;
         const bool oy = ys < 0 || ys >= a.ny;
@@ -83,17 +105,31 @@ __device__ __forceinline__ void gather(const Args& a, int x, int y, int z, doubl
         else
           zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
         if (!oy && !oz) {
-          f[i] = P[((size_t)i << a.lshift) + dev_index(a, xs, ys, zs)];
+          f[i] = gh ? ghost(a, side, i, ys, zs) : P[((size_t)i << a.lshift) + dev_index(a, xs, ys, zs)];
         } else {
           const int i2 = (e + 1) + 3 * ((oy ? -b : b) + 1) + 9 * ((oz ? -c : c) + 1);
           const double bb = P[((size_t)(26 - i) << a.lshift) + self];
-          const size_t sn = a.shift ? dev_index(a, xs, oy ? y : ys, oz ? z : zs) : self;
-          const double sp = P[((size_t)i2 << a.lshift) + sn];
+          const int sy = oy ? y : ys, sz = oz ? z : zs;
+          double sp;
+          if (gh && a.shift) {
+            sp = ghost(a, side, i2, sy, sz);
+          } else {
+            const size_t sn = a.shift ? dev_index(a, xs, sy, sz) : self;
+            sp = P[((size_t)i2 << a.lshift) + sn];
+          }
           f[i] = a.r * bb + a.omr * sp;
         }
       }
     }
   }
+}
+
+// gather for the mode of a (the diagnostics' kernels serve both).
+__device__ __forceinline__ void gather_any(const Args& a, int x, int y, int z, double f[27]) {
+  if (a.pressure)
+    gather<true>(a, x, y, z, f);
+  else
+    gather<false>(a, x, y, z, f);
 }
 
 // Density and momentum of the populations (x, y, z components).
@@ -118,7 +154,7 @@ __device__ __forceinline__ void rho_j(const double f[27], double& rho, double& j
 // s_nu, third order at s_q, orders 4-6 at s8 towards rho c_p c_q c_r with
 // c = (1, 0, 1/3), first order + rho F); three passes back.
 template <bool FORCE>
-__device__ __forceinline__ void collide(double f[27], const Args& a) {
+__device__ __forceinline__ void collide(double f[27], const Args& a, double snu, double sq) {
 #pragma clang fp contract(off)
   using clb::detail::axis_central;
   using clb::detail::axis_populations;
@@ -153,7 +189,7 @@ __device__ __forceinline__ void collide(double f[27], const Args& a) {
   const double third = 1.0 / 3.0;
   const double tr = (f[2] + f[6]) + f[18];
   const double tr1 = tr - a.sb * (tr - rho);
-  const double onu = 1.0 - a.snu;
+  const double onu = 1.0 - snu;
   const double mean = tr * third, mean1 = tr1 * third;
   f[2] = mean1 + onu * (f[2] - mean);
   f[6] = mean1 + onu * (f[6] - mean);
@@ -161,7 +197,7 @@ __device__ __forceinline__ void collide(double f[27], const Args& a) {
   f[4] = onu * f[4];     // k110
   f[10] = onu * f[10];   // k101
   f[12] = onu * f[12];   // k011
-  const double oq = 1.0 - a.sq;
+  const double oq = 1.0 - sq;
   // third order: k210 k120 k201 k021 k102 k012 k111
   f[5] = oq * f[5];
   f[7] = oq * f[7];
@@ -232,7 +268,7 @@ __device__ __forceinline__ void step_block(const Args& a, int& bx, int& by, int&
   bx = r2 - (r2 / nbx) * nbx;
 }
 
-template <bool FORCE>
+template <bool FORCE, bool PRESSURE>
 __global__ __launch_bounds__(kBX * kBY) void k3_step(Args a) {
   int bx, by, z;
   step_block(a, bx, by, z);
@@ -240,8 +276,11 @@ __global__ __launch_bounds__(kBX * kBY) void k3_step(Args a) {
   const int y = by * kBY + (int)(threadIdx.x / kBX);
   if (x >= a.nx || y >= a.ny) return;
   double f[27];
-  gather(a, x, y, z, f);
-  collide<FORCE>(f, a);
+  gather<PRESSURE>(a, x, y, z, f);
+  if (PRESSURE)
+    collide<FORCE>(f, a, a.col_rates[x], a.col_rates[a.nx + x]);
+  else
+    collide<FORCE>(f, a, a.snu, a.sq);
   const size_t n = dev_index(a, x, y, z);
 #pragma unroll
   for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(f[i], a.dst + ((size_t)i << a.lshift) + n);
@@ -255,7 +294,7 @@ __global__ __launch_bounds__(kBX * kBY) void k3_moments(Args a, double* rho, dou
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
   double f[27];
-  gather(a, x, y, z, f);
+  gather_any(a, x, y, z, f);
   double r, jx, jy, jz;
   rho_j(f, r, jx, jy, jz);
   const size_t n = node_index(a, x, y, z);
@@ -278,7 +317,7 @@ __global__ __launch_bounds__(256) void k3_ux_partial(Args a, double* partial) {
     const int y = (int)(rest % (size_t)a.ny);
     const int z = (int)(rest / (size_t)a.ny);
     double f[27];
-    gather(a, x, y, z, f);
+    gather<false>(a, x, y, z, f);   // force-driven ducts only
     double r, jx, jy, jz;
     rho_j(f, r, jx, jy, jz);
     acc += jx / r + 0.5 * a.gx;
@@ -287,6 +326,131 @@ __global__ __launch_bounds__(256) void k3_ux_partial(Args a, double* partial) {
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// One axis factor of the D3Q27 equilibrium f^eq_i(rho, u) = rho prod_axes
+// w(e, u): w(0, u) = 2/3 - u^2, w(+-1, u) = (1/3 + u^2 +- u) / 2.  Along each
+// axis the three factors have zeroth, first and second central moments 1, 0,
+// 1/3, so the product has the equilibrium central moments rho c_p c_q c_r,
+// c = (1, 0, 1/3), of the collision.
+__device__ __forceinline__ double eq_axis(int e, double u) {
+#pragma clang fp contract(off)
+  return e == 0 ? 2.0 / 3.0 - u * u : 0.5 * ((1.0 / 3.0 + u * u) + (double)e * u);
+}
+
+// Ghost planes of a pressure-driven duct, one thread per (side, y, z): the
+// inlet/outlet rule of Section 3.2 applied to every row of the cross-section,
+//   ghost_i = f^eq_i(2 rho_b - rho_1, 2 u_1 - u_2) + P_i(c1) - f^eq_i(rho_1, u_1),
+// rho_1, u_1 the density and velocity of the post-collision populations of
+// the column next to the plane (c1 = 0 at the inlet, nx - 1 at the outlet),
+// u_2 those of the column after it, rho_b = rho_in at the inlet, rho_out at
+// the outlet.
+__global__ __launch_bounds__(256) void k3_ghosts(Args a) {
+#pragma clang fp contract(off)
+  const size_t cs = (size_t)a.ny * (size_t)a.nz;
+  for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < 2 * cs; k += (size_t)gridDim.x * 256) {
+    const int side = k >= cs ? 1 : 0;
+    const size_t yz = k - (side ? cs : 0);
+    const int y = (int)(yz % (size_t)a.ny), z = (int)(yz / (size_t)a.ny);
+    const int c1 = side ? a.nx - 1 : 0, c2 = side ? a.nx - 2 : 1;
+    const double rho_b = side ? a.rho_out : a.rho_in;
+    double f[27];
+    const size_t d2 = dev_index(a, c2, y, z);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] = a.src[((size_t)i << a.lshift) + d2];
+    double r2, jx, jy, jz;
+    rho_j(f, r2, jx, jy, jz);
+    const double u2x = jx / r2, u2y = jy / r2, u2z = jz / r2;
+    const size_t d1 = dev_index(a, c1, y, z);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] = a.src[((size_t)i << a.lshift) + d1];
+    double r1;
+    rho_j(f, r1, jx, jy, jz);
+    const double u1x = jx / r1, u1y = jy / r1, u1z = jz / r1;
+    const double rg = 2.0 * rho_b - r1;
+    const double ugx = 2.0 * u1x - u2x, ugy = 2.0 * u1y - u2y, ugz = 2.0 * u1z - u2z;
+    double* out = a.ghosts + (size_t)side * 27 * cs + yz;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const int ex = i % 3 - 1, ey = (i / 3) % 3 - 1, ez = i / 9 - 1;
+      const double eg = rg * eq_axis(ex, ugx) * eq_axis(ey, ugy) * eq_axis(ez, ugz);
+      const double e1 = r1 * eq_axis(ex, u1x) * eq_axis(ey, u1y) * eq_axis(ez, u1z);
+      out[(size_t)i * cs] = eg + (f[i] - e1);
+    }
+  }
+}
+
+// Pre-collision density at the centre of cross-section x: the mean over the
+// middle row (odd ny) or the two middle rows (even ny) of the middle layer
+// or the two middle layers (nz alike).  Needs the ghost planes of the state.
+__device__ __forceinline__ double centre_density(const Args& a, int x) {
+#pragma clang fp contract(off)
+  const int y0 = (a.ny - 1) / 2, y1 = a.ny / 2;
+  const int z0 = (a.nz - 1) / 2, z1 = a.nz / 2;
+  double sum = 0.0;
+  int cnt = 0;
+  for (int z = z0; z <= z1; ++z)
+    for (int y = y0; y <= y1; ++y) {
+      double f[27];
+      gather<true>(a, x, y, z, f);
+      double r, jx, jy, jz;
+      rho_j(f, r, jx, jy, jz);
+      sum += r;
+      ++cnt;
+    }
+  return sum / (double)cnt;
+}
+
+// Relaxation rates of cross-section x of a pressure-driven duct (one thread
+// per x): Kn(x) = Kn_out rho_out / rho_c(x), s_nu(x) by Eq. (18) with
+// N = ny, s_q(x) by Eq. (21); the bulk rate stays s_b.
+__global__ __launch_bounds__(256) void k3_rates(Args a) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= a.nx) return;
+  double snu, sq;
+  clb::local_rates(a.kn, a.rho_out, centre_density(a, x), a.c_tau, a.ab, a.A2, a.tq_den, snu, sq);
+  a.col_rates[x] = snu;
+  a.col_rates[a.nx + x] = sq;
+}
+
+// Cross-section sums of the pre-collision state, one workgroup per x:
+// m[x] = sum_{y,z} rho u_x (rho u_x = j_x + rho F_x / 2, Eq. 13) and, for a
+// pressure-driven duct, rhoc[x] = rho_c(x).  Fixed summation order:
+// strided per-thread sums, wavefront butterflies, the four wavefront totals
+// in order.  Either output may be NULL.
+__global__ __launch_bounds__(256) void k3_sections(Args a, double* m, double* rhoc) {
+#pragma clang fp contract(off)
+  __shared__ double s[4];
+  const int x = blockIdx.x;
+  if (m) {
+    const size_t cs = (size_t)a.ny * (size_t)a.nz;
+    double acc = 0.0;
+    for (size_t k = threadIdx.x; k < cs; k += 256) {
+      const int y = (int)(k % (size_t)a.ny), z = (int)(k / (size_t)a.ny);
+      double f[27];
+      gather_any(a, x, y, z, f);
+      double r, jx, jy, jz;
+      rho_j(f, r, jx, jy, jz);
+      acc += jx + 0.5 * r * a.gx;
+    }
+    acc = clb::wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) m[x] = (s[0] + s[1]) + (s[2] + s[3]);
+  }
+  if (rhoc && threadIdx.x == 0) rhoc[x] = centre_density(a, x);
+}
+
+// Pressure deviation along the centre line (Section 3.2), one thread per x:
+// dp[x] = (p_c(x) - p_l(x)) / p_out, p = rho / 3, p_l linear from p_in at
+// x = 0 to p_out at x = nx, node centres at x + 1/2.
+__global__ __launch_bounds__(256) void k3_pressure_dev(Args a, const double* __restrict__ rhoc, double* dp) {
+#pragma clang fp contract(off)
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= a.nx) return;
+  const double p_out = a.rho_out / 3.0, p_in = a.rho_in / 3.0;
+  const double p_l = p_in - (p_in - p_out) * ((double)x + 0.5) / (double)a.nx;
+  dp[x] = (rhoc[x] / 3.0 - p_l) / p_out;
 }
 
 // Count of non-finite values among all populations (logical nodes only: the
@@ -324,21 +488,28 @@ __global__ __launch_bounds__(256) void k3_sum(const double* __restrict__ v, int 
   if (threadIdx.x == 0) out[0] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-// Start: f^eq(rho0, 0) (product of the one-axis factors 2/3, 1/6, 1/6) plus
-// the seeded perturbation.
-__global__ void k3_init(double* dst, Args a, double rho0, int perturbed, double amp, uint64_t seed) {
+// Start: f^eq(rho, 0) (product of the one-axis factors 2/3, 1/6, 1/6) with
+// rho = rho0, or falling linearly from rho_in at the inlet plane x = 0 to
+// rho_out at the outlet plane x = nx (node centres x + 1/2; kind
+// CLB_INIT_LINEAR_RHO), plus the seeded perturbation (CLB_INIT_PERTURBED).
+__global__ void k3_init(double* dst, Args a, double rho0, int kind, double amp, uint64_t seed) {
+#pragma clang fp contract(off)
+  const bool perturbed = kind == CLB_INIT_PERTURBED;
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < a.plane; n += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(n % (size_t)a.nx);
     const size_t rest = n / (size_t)a.nx;
     const int y = (int)(rest % (size_t)a.ny);
     const int z = (int)(rest / (size_t)a.ny);
     const size_t d = dev_index(a, x, y, z);
+    const double rho = kind == CLB_INIT_LINEAR_RHO
+                           ? a.rho_in - (a.rho_in - a.rho_out) * ((double)x + 0.5) / (double)a.nx
+                           : rho0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
       const int e0 = i % 3 - 1, e1 = (i / 3) % 3 - 1, e2 = i / 9 - 1;
       const double w0 = e0 == 0 ? 2.0 / 3.0 : 1.0 / 6.0, w1 = e1 == 0 ? 2.0 / 3.0 : 1.0 / 6.0,
                    w2 = e2 == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
-      double v = rho0 * w0 * w1 * w2;
+      double v = rho * w0 * w1 * w2;
       if (perturbed) {
         const uint64_t key = seed ^ (27ull * (uint64_t)n + (uint64_t)i);
         const double U = (double)(clb::splitmix64_first(key) >> 11) * (1.0 / 9007199254740992.0);
@@ -388,6 +559,8 @@ struct clb3_ctx {
   int cur;
   double* partial;
   double* result;
+  double* cols;     // [3][nx]: s_nu(x), s_q(x) of a pressure-driven duct, then per-x scratch
+  double* ghosts;   // [2][27][nz][ny] ghost planes (pressure-driven ducts; NULL otherwise)
   hipStream_t stream;
   int64_t steps;
 };
@@ -422,8 +595,20 @@ clb_status validate3(const clb3_params* p, clb_derived* d) {
   if ((size_t)((p->nx + 63) / 64) * (size_t)((p->ny + 3) / 4) * (size_t)p->nz >= ((size_t)1 << 31))
     return fail3(CLB_EINVAL, "nx*ny*nz: grid too large for one launch");
   if (p->zbc != CLB3_Z_WALLS && p->zbc != CLB3_Z_PERIODIC) return fail3(CLB_EINVAL, "zbc: unknown kind %d", p->zbc);
-  if (p->init != CLB_INIT_UNIFORM && p->init != CLB_INIT_PERTURBED)
-    return fail3(CLB_EINVAL, "init: must be CLB_INIT_UNIFORM or CLB_INIT_PERTURBED");
+  if (p->xbc != CLB_X_PERIODIC && p->xbc != CLB_X_PRESSURE) return fail3(CLB_EINVAL, "xbc: unknown kind %d", p->xbc);
+  const bool pressure = p->xbc == CLB_X_PRESSURE;
+  if (p->init != CLB_INIT_UNIFORM && p->init != CLB_INIT_PERTURBED && p->init != CLB_INIT_LINEAR_RHO)
+    return fail3(CLB_EINVAL, "init: unknown kind %d", p->init);
+  if (p->init == CLB_INIT_LINEAR_RHO && !pressure)
+    return fail3(CLB_EINVAL, "init: CLB_INIT_LINEAR_RHO needs xbc = CLB_X_PRESSURE");
+  if (pressure) {
+    if (p->nx < 2) return fail3(CLB_EINVAL, "nx: pressure-driven ducts need nx >= 2 (got %d)", p->nx);
+    if (p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0)
+      return fail3(CLB_EINVAL, "gx/gy/gz: must be 0 for a pressure-driven duct");
+    if (!(finite(p->p_ratio) && p->p_ratio > 0)) return fail3(CLB_EINVAL, "p_ratio: must be finite and > 0");
+    if (!(finite(p->rho_out) && p->rho_out > 0)) return fail3(CLB_EINVAL, "rho_out: must be finite and > 0");
+    if (!finite(p->p_ratio * p->rho_out)) return fail3(CLB_EINVAL, "p_ratio * rho_out: must be finite");
+  }
   if (p->cbbsr_shift != 0 && p->cbbsr_shift != 1) return fail3(CLB_EINVAL, "cbbsr_shift: must be 0 or 1");
   if (p->cbbsr_shift == 0 && p->zbc == CLB3_Z_WALLS)
     return fail3(CLB_EINVAL, "cbbsr_shift: the same-node specular source does not conserve mass at duct edges; "
@@ -471,8 +656,15 @@ size_t buffer_bytes(const clb3_params* p) {
                         << lshift_of(p));
 }
 
+size_t cols_bytes(const clb3_params* p) { return clb3::align256(3 * (size_t)p->nx * sizeof(double)); }
+
+size_t ghost_bytes(const clb3_params* p) {
+  return p->xbc == CLB_X_PRESSURE ? clb3::align256(2 * 27 * (size_t)p->ny * (size_t)p->nz * sizeof(double)) : 0;
+}
+
 size_t total_bytes(const clb3_params* p) {
-  return 2 * buffer_bytes(p) + clb3::align256(clb3::kPartials * sizeof(double)) + clb3::align256(32 * sizeof(double));
+  return 2 * buffer_bytes(p) + clb3::align256(clb3::kPartials * sizeof(double)) + clb3::align256(32 * sizeof(double)) +
+         cols_bytes(p) + ghost_bytes(p);
 }
 
 clb3::Args args_of(const clb3_ctx* c) {
@@ -496,7 +688,27 @@ clb3::Args args_of(const clb3_ctx* c) {
   a.snu = c->d.s_nu;
   a.sq = c->d.s_q;
   a.s8 = c->p.s8;
+  a.pressure = c->p.xbc == CLB_X_PRESSURE;
+  a.rho_out = c->p.rho_out;
+  a.rho_in = c->p.p_ratio * c->p.rho_out;
+  a.kn = c->p.kn;
+  a.ab = c->p.a;
+  a.A2 = c->p.A2;
+  a.tq_den = c->p.tq_den;
+  a.c_tau = std::sqrt(6.0 / kPi) * (double)c->p.ny;
+  a.ghosts = c->ghosts;
+  a.col_rates = c->cols;
   return a;
+}
+
+// The ghost planes of the current state (pressure-driven ducts): the step,
+// and every diagnostic that gathers, reads them.
+clb_status refresh_ghosts(clb3_ctx* c, const clb3::Args& a) {
+  if (!a.pressure) return CLB_OK;
+  const size_t n = 2 * (size_t)c->p.ny * (size_t)c->p.nz;
+  clb3::k3_ghosts<<<clb3::blocks_for(n) * 4, 256, 0, c->stream>>>(a);
+  CLB3_HIP(hipGetLastError());
+  return CLB_OK;
 }
 
 dim3 node_grid(const clb3_params* p) {
@@ -531,6 +743,9 @@ void clb3_params_default(clb3_params* p) {
   p->s8 = 1.2;      // Section 3
   p->rho0 = 1.0;
   p->tq_den = 16.0;
+  p->xbc = CLB_X_PERIODIC;
+  p->p_ratio = 2.0;   // Section 3.2
+  p->rho_out = 1.0;
 }
 
 clb_status clb3_derive(const clb3_params* p, clb_derived* out) {
@@ -566,12 +781,16 @@ clb_status clb3_init(const clb3_params* p, void* d_workspace, size_t bytes, void
   c->buf[1] = reinterpret_cast<double*>(base + buffer_bytes(p));
   c->partial = reinterpret_cast<double*>(base + 2 * buffer_bytes(p));
   c->result = c->partial + clb3::kPartials;
+  char* tail = base + 2 * buffer_bytes(p) + clb3::align256(clb3::kPartials * sizeof(double)) +
+               clb3::align256(32 * sizeof(double));
+  c->cols = reinterpret_cast<double*>(tail);
+  c->ghosts = p->xbc == CLB_X_PRESSURE ? reinterpret_cast<double*>(tail + cols_bytes(p)) : nullptr;
   c->cur = 0;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   const size_t plane = plane_of(p);
-  clb3::k3_init<<<clb3::blocks_for(plane) * 16, 256, 0, c->stream>>>(c->buf[0], args_of(c), p->rho0,
-                                                                     p->init == CLB_INIT_PERTURBED, p->init_amp, p->seed);
+  clb3::k3_init<<<clb3::blocks_for(plane) * 16, 256, 0, c->stream>>>(c->buf[0], args_of(c), p->rho0, p->init,
+                                                                     p->init_amp, p->seed);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     delete c;
@@ -588,12 +807,19 @@ clb_status clb3_step(clb3_ctx* c, int64_t nsteps) {
   const dim3 g3 = node_grid(&c->p);
   const dim3 grid(g3.x * g3.y * g3.z);   // k3_step orders its workgroups itself
   const bool force = c->p.gx != 0.0 || c->p.gy != 0.0 || c->p.gz != 0.0;
+  const bool pressure = c->p.xbc == CLB_X_PRESSURE;
   for (int64_t n = 0; n < nsteps; ++n) {
     const clb3::Args a = args_of(c);
-    if (force)
-      clb3::k3_step<true><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
-    else
-      clb3::k3_step<false><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
+    if (pressure) {   // ghost planes, then the rates of every cross-section, then the step
+      clb_status st = refresh_ghosts(c, a);
+      if (st != CLB_OK) return st;
+      clb3::k3_rates<<<(unsigned)((c->p.nx + 255) / 256), 256, 0, c->stream>>>(a);
+      clb3::k3_step<false, true><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
+    } else if (force) {
+      clb3::k3_step<true, false><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
+    } else {
+      clb3::k3_step<false, false><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
+    }
     CLB3_HIP(hipGetLastError());
     c->cur ^= 1;
     c->steps += 1;
@@ -617,7 +843,46 @@ clb_status clb3_moments(clb3_ctx* c, double* d_rho, double* d_ux, double* d_uy, 
   if (d_uy && (st = clb::check_device_ptr(d_uy, bytes, "d_uy")) != CLB_OK) return st;
   if (d_uz && (st = clb::check_device_ptr(d_uz, bytes, "d_uz")) != CLB_OK) return st;
   if (!d_rho && !d_ux && !d_uy && !d_uz) return CLB_OK;
-  clb3::k3_moments<<<node_grid(&c->p), clb3::kBX * clb3::kBY, 0, c->stream>>>(args_of(c), d_rho, d_ux, d_uy, d_uz);
+  const clb3::Args a = args_of(c);
+  if ((st = refresh_ghosts(c, a)) != CLB_OK) return st;
+  clb3::k3_moments<<<node_grid(&c->p), clb3::kBX * clb3::kBY, 0, c->stream>>>(a, d_rho, d_ux, d_uy, d_uz);
+  CLB3_HIP(hipGetLastError());
+  return CLB_OK;
+}
+
+clb_status clb3_massflow(clb3_ctx* c, double* d_m_col, double* h_m_mean) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  clb_status st;
+  if (d_m_col && (st = clb::check_device_ptr(d_m_col, (size_t)c->p.nx * sizeof(double), "d_m_col")) != CLB_OK)
+    return st;
+  if (!d_m_col && !h_m_mean) return CLB_OK;
+  const clb3::Args a = args_of(c);
+  if ((st = refresh_ghosts(c, a)) != CLB_OK) return st;
+  double* m = d_m_col ? d_m_col : c->cols + 2 * (size_t)c->p.nx;
+  clb3::k3_sections<<<(unsigned)c->p.nx, 256, 0, c->stream>>>(a, m, nullptr);
+  CLB3_HIP(hipGetLastError());
+  if (!h_m_mean) return CLB_OK;
+  clb3::k3_sum<<<1, 256, 0, c->stream>>>(m, c->p.nx, c->result);
+  CLB3_HIP(hipGetLastError());
+  double sum = 0;
+  if ((st = read_result3(c, &sum)) != CLB_OK) return st;
+  *h_m_mean = sum / (double)c->p.nx;
+  return CLB_OK;
+}
+
+clb_status clb3_pressure_deviation(clb3_ctx* c, double* d_dp, double* d_rho_c) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  if (c->p.xbc != CLB_X_PRESSURE) return fail3(CLB_ESTATE, "clb3_pressure_deviation: pressure-driven ducts only");
+  const size_t bytes = (size_t)c->p.nx * sizeof(double);
+  clb_status st;
+  if (d_dp && (st = clb::check_device_ptr(d_dp, bytes, "d_dp")) != CLB_OK) return st;
+  if (d_rho_c && (st = clb::check_device_ptr(d_rho_c, bytes, "d_rho_c")) != CLB_OK) return st;
+  if (!d_dp && !d_rho_c) return CLB_OK;
+  const clb3::Args a = args_of(c);
+  if ((st = refresh_ghosts(c, a)) != CLB_OK) return st;
+  double* rc = d_rho_c ? d_rho_c : c->cols + 2 * (size_t)c->p.nx;
+  clb3::k3_sections<<<(unsigned)c->p.nx, 64, 0, c->stream>>>(a, nullptr, rc);
+  if (d_dp) clb3::k3_pressure_dev<<<(unsigned)((c->p.nx + 255) / 256), 256, 0, c->stream>>>(a, rc, d_dp);
   CLB3_HIP(hipGetLastError());
   return CLB_OK;
 }

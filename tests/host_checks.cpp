@@ -133,11 +133,42 @@ int main() {
     b3 = q3;
     b3.kn = -1.0;
     EXPECT(clb3_workspace_size(&b3, &n) == CLB_EINVAL);
+    // pressure-driven ducts: the ghost planes add 2 * 27 doubles per row of the cross-section
+    size_t n_force = 0, n_press = 0;
+    EXPECT(clb3_workspace_size(&q3, &n_force) == CLB_OK);
+    b3 = q3;
+    b3.xbc = CLB_X_PRESSURE;
+    EXPECT(clb3_derive(&b3, &d) == CLB_OK);
+    EXPECT(clb3_workspace_size(&b3, &n_press) == CLB_OK && n_press >= n_force + 2 * 27 * 8 * 12 * 10);
+    b3.init = CLB_INIT_LINEAR_RHO;
+    EXPECT(clb3_derive(&b3, &d) == CLB_OK);
+    b3.nx = 1;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3.nx = 2;
+    EXPECT(clb3_derive(&b3, &d) == CLB_OK);
+    b3.gx = 1e-5;   // no body force in a pressure-driven duct
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3.gx = 0.0;
+    b3.gz = 1e-5;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3.gz = 0.0;
+    b3.p_ratio = 0.0;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3.p_ratio = NAN;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
+    b3.p_ratio = 2.0;
+    b3.rho_out = -1.0;
+    EXPECT(clb3_workspace_size(&b3, &n) == CLB_EINVAL);
+    b3.rho_out = 1.0;
+    b3.xbc = 7;
+    EXPECT(clb3_derive(&b3, &d) == CLB_EINVAL);
   }
   EXPECT(clb3_derive(nullptr, &d) == CLB_EINVAL);
   EXPECT(clb3_derive(&q3, nullptr) == CLB_EINVAL);
   EXPECT(clb3_step(nullptr, 1) == CLB_EINVAL);
   EXPECT(clb3_flow_rate(nullptr, nullptr) == CLB_EINVAL);
+  EXPECT(clb3_massflow(nullptr, nullptr, nullptr) == CLB_EINVAL);
+  EXPECT(clb3_pressure_deviation(nullptr, nullptr, nullptr) == CLB_EINVAL);
   EXPECT(clb3_destroy(nullptr) == CLB_EINVAL);
   clb3_ctx* c3 = nullptr;
   EXPECT(clb3_init(&q3, nullptr, n, nullptr, &c3) == CLB_EINVAL && c3 == nullptr);
