@@ -33,9 +33,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched Kn-sweep comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
-    ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "msweep", "adjoint", "duct"), default="all",
-                    help="run one part alone (step: the periodic step only; sweep / pressure / msweep / adjoint: "
-                         "that measurement only, printed as its own JSON line) -- for profiling runs")
+    ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "msweep", "adjoint", "duct", "pduct"),
+                    default="all",
+                    help="run one part alone (step: the periodic step only; sweep / pressure / msweep / adjoint / "
+                         "duct (force-driven 3-D duct) / pduct (pressure-driven 3-D duct): that measurement only, "
+                         "printed as its own JSON line) -- for profiling runs")
     ap.add_argument("--no-loop-baseline", action="store_true",
                     help="sweep / msweep: skip the loop-of-solvers baselines (profiling the batched kernel)")
     ap.add_argument("--no-msweep", action="store_true", help="skip the pressure-driven mass-flow sweep")
@@ -372,6 +374,52 @@ def duct3d(steps=100, warmup=5):
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "unit_bytes": "432 B per node update"}}
 
 
+def duct3d_pressure(steps=200, warmup=5):
+    """The pressure-driven 3-D duct (4000 x 40 x 40, L/H = 100,
+    p_in/p_out = 2, Kn_out = 0.1, linear start): time per step with HIP
+    events on the solver's stream.  A step is three launches: the two ghost
+    planes, the rates of every cross-section, the step itself; the roofline
+    unit is the step's 432 B per node update plus the ghost planes (54 values
+    read and 27 written per row of each plane)."""
+    import torch
+    from clb_inputs import WORKLOADS
+    from paper_1603_01955_amd import Duct
+    w = dict(WORKLOADS["duct_pressure_4000x40x40"])
+    s = Duct(**w)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nodes = s.nx * s.ny * s.nz
+    ok = s.check_finite()
+    _, m_mean = s.massflow()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    step_bytes = 432.0 * nodes + 2 * (54 + 27) * 8.0 * w["ny"] * w["nz"]
+    gbs = step_bytes / (ms * 1e-3) / 1e9
+    from oracle import clb3d_ref as D
+    small = dict(nx=w["nx"], ny=4, nz=4, kn=w["kn"], xbc="pressure", p_ratio=w["p_ratio"])
+    prm = D.Params3D(**small)
+    st = {"P": D.init_linear_rho(prm)}
+
+    def step():
+        st["P"] = D.step(st["P"], prm)
+    cpu = oracle_rate(step, w["nx"] * 16, "a 4000 x 4 x 4 pressure-driven duct (the same length, Kn_out and "
+                                          "pressure ratio, the cross-section cut to 4 x 4)")
+    return {"workload": "duct_pressure_4000x40x40", "steps": steps, "ms_per_step": round(ms, 4), "finite": ok,
+            "mass_flow_mean": m_mean, "cpu_oracle": cpu,
+            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "unit_bytes": "432 B per node update + 648 B per row of each ghost plane"}}
+
+
 def forcing_variant(steps=200, warmup=10):
     """The source with third-order force moments (clb_params.forcing = 1):
     the periodic step's throughput on the benchmark grid, and the batched Kn
@@ -569,6 +617,9 @@ def main():
     if args.part == "duct":
         print(json.dumps({"duct3d": duct3d()}), flush=True)
         return
+    if args.part == "pduct":
+        print(json.dumps({"duct3d_pressure": duct3d_pressure()}), flush=True)
+        return
     import torch
     from paper_1603_01955_amd import Solver
 
@@ -685,6 +736,7 @@ def main():
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_calibration()
     rec["duct3d"] = duct3d()
+    rec["duct3d_pressure"] = duct3d_pressure()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec), flush=True)

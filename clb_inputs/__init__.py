@@ -88,6 +88,10 @@ WORKLOADS = {
     # Rectangular microduct (3-D extension): square cross-section, force driven.
     "duct_512x256x256": dict(nx=512, ny=256, nz=256, kn=0.5, gx=1e-6, init="perturbed", init_amp=1e-4,
                              seed=2468),
+    # Long pressure-driven microduct (3-D extension of the long channel): square
+    # 40 x 40 cross-section, L/H = 100, p_in/p_out = 2, Kn_out = 0.1.
+    "duct_pressure_4000x40x40": dict(nx=4000, ny=40, nz=40, xbc="pressure", kn=0.1, p_ratio=2.0,
+                                     init="linear_rho"),
     # Mass-flow sweep: 16 long channels, L/H = 100, Kn_out 0.01 .. 1.
     "mass_flow_sweep_16x2000x20": dict(nx=2000, ny=20, xbc="pressure", p_ratio=MASS_FLOW_P_RATIO,
                                        sigma=MASS_FLOW_SIGMA, channels=16, kn_lo=0.01, kn_hi=1.0),

@@ -50,13 +50,18 @@ struct Args {
   int pressure;
   double rho_in, rho_out;   // boundary densities, p = rho / 3
   double kn, ab, A2, tq_den, c_tau;   // Kn_out, Eq. (18) a, B2, Eq. (21) denominator, sqrt(6/pi) ny
-  double* ghosts;           // [2][27][nz][ny]: inlet plane x = -1, outlet plane x = nx
+  double* ghosts;           // [2][nz][ny][27]: inlet plane x = -1, outlet plane x = nx
   double* col_rates;        // [2][nx]: s_nu(x), then s_q(x)
 };
 
-// Ghost population i of side (0 inlet, 1 outlet) at row y, layer z.
+// Ghost population i of side (0 inlet, 1 outlet) at row y, layer z; the 27
+// values of one row lie together.
+__device__ __forceinline__ size_t ghost_row(const Args& a, int side, int y, int z) {
+  return (((size_t)side * (size_t)a.nz + (size_t)z) * (size_t)a.ny + (size_t)y) * 27;
+}
+
 __device__ __forceinline__ double ghost(const Args& a, int side, int i, int y, int z) {
-  return a.ghosts[((size_t)(side * 27 + i) * (size_t)a.nz + (size_t)z) * (size_t)a.ny + (size_t)y];
+  return a.ghosts[ghost_row(a, side, y, z) + (size_t)i];
 }
 
 // Logical node number (the ABI order, x fastest).
@@ -80,6 +85,49 @@ __device__ __forceinline__ size_t dev_index(const Args& a, int x, int y, int z) 
 // e' = e with its components along S reversed, e_t = e without them (the
 // node itself when shift = 0); a displaced source beyond the inlet or the
 // outlet is a ghost value.
+// Pre-collision population of one direction (e, b, c), given at run time,
+// at node (x, y, z), self = dev_index of the node: the rule of gather below
+// for that direction alone (the rates kernel spreads the directions of a
+// node over lanes).
+template <bool PRESSURE>
+__device__ __forceinline__ double pull(const Args& a, int x, int y, int z, size_t self, int e, int b, int c) {
+#pragma clang fp contract(off)
+  const double* __restrict__ P = a.src;
+  const int i = (e + 1) + 3 * (b + 1) + 9 * (c + 1);
+  int xs = x - e;
+  if (!PRESSURE) xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+  const bool gh = PRESSURE && (xs < 0 || xs >= a.nx);   // the source lies on a ghost plane
+  const int side = xs < 0 ? 0 : 1;
+  const int ys = y - b;
+  int zs = z - c;
+  const bool oy = ys < 0 || ys >= a.ny;
+  bool oz = false;
+  if (a.zwalls)
+    oz = zs < 0 || zs >= a.nz;
+  else
+    zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
+  double v;
+  if (!oy && !oz) {
+    v = gh ? ghost(a, side, i, ys, zs) : P[((size_t)i << a.lshift) + dev_index(a, xs, ys, zs)];
+  } else {
+    const int i2 = (e + 1) + 3 * ((oy ? -b : b) + 1) + 9 * ((oz ? -c : c) + 1);
+    const double bb = P[((size_t)(26 - i) << a.lshift) + self];
+    const int sy = oy ? y : ys, sz = oz ? z : zs;
+    double sp;
+    if (gh && a.shift) {
+      sp = ghost(a, side, i2, sy, sz);
+    } else {
+      const size_t sn = a.shift ? dev_index(a, xs, sy, sz) : self;
+      sp = P[((size_t)i2 << a.lshift) + sn];
+    }
+    v = a.r * bb + a.omr * sp;
+  }
+  return v;
+}
+
+// The 27 pre-collision populations of node (x, y, z): pull for every
+// direction, written out in full (the step's hot loop; the compiler keeps
+// the wall and ghost tests of each direction apart).
 template <bool PRESSURE>
 __device__ __forceinline__ void gather(const Args& a, int x, int y, int z, double f[27]) {
 #pragma clang fp contract(off)
@@ -338,44 +386,52 @@ __device__ __forceinline__ double eq_axis(int e, double u) {
   return e == 0 ? 2.0 / 3.0 - u * u : 0.5 * ((1.0 / 3.0 + u * u) + (double)e * u);
 }
 
-// Ghost planes of a pressure-driven duct, one thread per (side, y, z): the
-// inlet/outlet rule of Section 3.2 applied to every row of the cross-section,
+// Sum over the 32 lanes of a half-wavefront, the same value (bitwise) in
+// every lane: butterfly of fixed order.
+__device__ __forceinline__ double group32_sum(double v) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int d = 16; d > 0; d >>= 1) v += __shfl_xor(v, d, 32);
+  return v;
+}
+
+// Ghost planes of a pressure-driven duct, 32 lanes per (side, y, z), lane
+// i < 27 for direction i: the inlet/outlet rule of Section 3.2 applied to
+// every row of the cross-section,
 //   ghost_i = f^eq_i(2 rho_b - rho_1, 2 u_1 - u_2) + P_i(c1) - f^eq_i(rho_1, u_1),
 // rho_1, u_1 the density and velocity of the post-collision populations of
 // the column next to the plane (c1 = 0 at the inlet, nx - 1 at the outlet),
 // u_2 those of the column after it, rho_b = rho_in at the inlet, rho_out at
-// the outlet.
+// the outlet.  The moments are lane sums over the group.
 __global__ __launch_bounds__(256) void k3_ghosts(Args a) {
 #pragma clang fp contract(off)
   const size_t cs = (size_t)a.ny * (size_t)a.nz;
-  for (size_t k = blockIdx.x * (size_t)256 + threadIdx.x; k < 2 * cs; k += (size_t)gridDim.x * 256) {
-    const int side = k >= cs ? 1 : 0;
-    const size_t yz = k - (side ? cs : 0);
+  const int i = (int)(threadIdx.x & 31);
+  const int ex = i % 3 - 1, ey = (i / 3) % 3 - 1, ez = i / 9 - 1;
+  // whole 32-lane groups stay together through the loop and the shuffles
+  for (size_t g = (blockIdx.x * (size_t)256 + threadIdx.x) >> 5; g < 2 * cs; g += (size_t)gridDim.x * 8) {
+    const int side = g >= cs ? 1 : 0;
+    const size_t yz = g - (side ? cs : 0);
     const int y = (int)(yz % (size_t)a.ny), z = (int)(yz / (size_t)a.ny);
     const int c1 = side ? a.nx - 1 : 0, c2 = side ? a.nx - 2 : 1;
     const double rho_b = side ? a.rho_out : a.rho_in;
-    double f[27];
-    const size_t d2 = dev_index(a, c2, y, z);
-#pragma unroll
-    for (int i = 0; i < 27; ++i) f[i] = a.src[((size_t)i << a.lshift) + d2];
-    double r2, jx, jy, jz;
-    rho_j(f, r2, jx, jy, jz);
-    const double u2x = jx / r2, u2y = jy / r2, u2z = jz / r2;
-    const size_t d1 = dev_index(a, c1, y, z);
-#pragma unroll
-    for (int i = 0; i < 27; ++i) f[i] = a.src[((size_t)i << a.lshift) + d1];
-    double r1;
-    rho_j(f, r1, jx, jy, jz);
-    const double u1x = jx / r1, u1y = jy / r1, u1z = jz / r1;
-    const double rg = 2.0 * rho_b - r1;
-    const double ugx = 2.0 * u1x - u2x, ugy = 2.0 * u1y - u2y, ugz = 2.0 * u1z - u2z;
-    double* out = a.ghosts + (size_t)side * 27 * cs + yz;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const int ex = i % 3 - 1, ey = (i / 3) % 3 - 1, ez = i / 9 - 1;
-      const double eg = rg * eq_axis(ex, ugx) * eq_axis(ey, ugy) * eq_axis(ez, ugz);
+    double f1 = 0.0, f2 = 0.0;
+    if (i < 27) {
+      f1 = a.src[((size_t)i << a.lshift) + dev_index(a, c1, y, z)];
+      f2 = a.src[((size_t)i << a.lshift) + dev_index(a, c2, y, z)];
+    }
+    const double r1 = group32_sum(f1), r2 = group32_sum(f2);
+    const double jx1 = group32_sum((double)ex * f1), jy1 = group32_sum((double)ey * f1),
+                 jz1 = group32_sum((double)ez * f1);
+    const double jx2 = group32_sum((double)ex * f2), jy2 = group32_sum((double)ey * f2),
+                 jz2 = group32_sum((double)ez * f2);
+    const double u1x = jx1 / r1, u1y = jy1 / r1, u1z = jz1 / r1;
+    const double u2x = jx2 / r2, u2y = jy2 / r2, u2z = jz2 / r2;
+    if (i < 27) {
+      const double rg = 2.0 * rho_b - r1;
+      const double eg = rg * eq_axis(ex, 2.0 * u1x - u2x) * eq_axis(ey, 2.0 * u1y - u2y) * eq_axis(ez, 2.0 * u1z - u2z);
       const double e1 = r1 * eq_axis(ex, u1x) * eq_axis(ey, u1y) * eq_axis(ez, u1z);
-      out[(size_t)i * cs] = eg + (f[i] - e1);
+      a.ghosts[ghost_row(a, side, y, z) + (size_t)i] = eg + (f1 - e1);
     }
   }
 }
@@ -401,16 +457,31 @@ __device__ __forceinline__ double centre_density(const Args& a, int x) {
   return sum / (double)cnt;
 }
 
-// Relaxation rates of cross-section x of a pressure-driven duct (one thread
-// per x): Kn(x) = Kn_out rho_out / rho_c(x), s_nu(x) by Eq. (18) with
-// N = ny, s_q(x) by Eq. (21); the bulk rate stays s_b.
+// Relaxation rates of cross-section x of a pressure-driven duct, 32 lanes
+// per x, lane i < 27 pulling direction i at the central node(s):
+// Kn(x) = Kn_out rho_out / rho_c(x), s_nu(x) by Eq. (18) with N = ny, s_q(x)
+// by Eq. (21); the bulk rate stays s_b.  Needs the ghost planes of the state.
 __global__ __launch_bounds__(256) void k3_rates(Args a) {
-  const int x = blockIdx.x * 256 + threadIdx.x;
-  if (x >= a.nx) return;
-  double snu, sq;
-  clb::local_rates(a.kn, a.rho_out, centre_density(a, x), a.c_tau, a.ab, a.A2, a.tq_den, snu, sq);
-  a.col_rates[x] = snu;
-  a.col_rates[a.nx + x] = sq;
+#pragma clang fp contract(off)
+  const int i = (int)(threadIdx.x & 31);
+  const int e = i % 3 - 1, b = (i / 3) % 3 - 1, c = i / 9 - 1;
+  const int y0 = (a.ny - 1) / 2, y1 = a.ny / 2;
+  const int z0 = (a.nz - 1) / 2, z1 = a.nz / 2;
+  const double cnt = (double)((y1 - y0 + 1) * (z1 - z0 + 1));
+  for (size_t g = (blockIdx.x * (size_t)256 + threadIdx.x) >> 5; g < (size_t)a.nx; g += (size_t)gridDim.x * 8) {
+    const int x = (int)g;
+    double acc = 0.0;
+    if (i < 27)
+      for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y) acc += pull<true>(a, x, y, z, dev_index(a, x, y, z), e, b, c);
+    const double rc = group32_sum(acc) / cnt;
+    if (i == 0) {
+      double snu, sq;
+      clb::local_rates(a.kn, a.rho_out, rc, a.c_tau, a.ab, a.A2, a.tq_den, snu, sq);
+      a.col_rates[x] = snu;
+      a.col_rates[a.nx + x] = sq;
+    }
+  }
 }
 
 // Cross-section sums of the pre-collision state, one workgroup per x:
@@ -543,6 +614,14 @@ constexpr int kPartials = 1024;
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Workgroups of 256 threads for n groups of 32 lanes (eight per workgroup),
+// at most 65536 (the kernels loop over the rest).
+unsigned group_blocks(size_t n) {
+  size_t b = (n + 7) / 8;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b == 0 ? 1 : b);
+}
+
 unsigned blocks_for(size_t n) {
   size_t b = (n + 255) / 256;
   if (b > (size_t)kPartials) b = kPartials;
@@ -560,7 +639,7 @@ struct clb3_ctx {
   double* partial;
   double* result;
   double* cols;     // [3][nx]: s_nu(x), s_q(x) of a pressure-driven duct, then per-x scratch
-  double* ghosts;   // [2][27][nz][ny] ghost planes (pressure-driven ducts; NULL otherwise)
+  double* ghosts;   // [2][nz][ny][27] ghost planes (pressure-driven ducts; NULL otherwise)
   hipStream_t stream;
   int64_t steps;
 };
@@ -705,8 +784,7 @@ clb3::Args args_of(const clb3_ctx* c) {
 // and every diagnostic that gathers, reads them.
 clb_status refresh_ghosts(clb3_ctx* c, const clb3::Args& a) {
   if (!a.pressure) return CLB_OK;
-  const size_t n = 2 * (size_t)c->p.ny * (size_t)c->p.nz;
-  clb3::k3_ghosts<<<clb3::blocks_for(n) * 4, 256, 0, c->stream>>>(a);
+  clb3::k3_ghosts<<<clb3::group_blocks(2 * (size_t)c->p.ny * (size_t)c->p.nz), 256, 0, c->stream>>>(a);
   CLB3_HIP(hipGetLastError());
   return CLB_OK;
 }
@@ -813,7 +891,7 @@ clb_status clb3_step(clb3_ctx* c, int64_t nsteps) {
     if (pressure) {   // ghost planes, then the rates of every cross-section, then the step
       clb_status st = refresh_ghosts(c, a);
       if (st != CLB_OK) return st;
-      clb3::k3_rates<<<(unsigned)((c->p.nx + 255) / 256), 256, 0, c->stream>>>(a);
+      clb3::k3_rates<<<clb3::group_blocks((size_t)c->p.nx), 256, 0, c->stream>>>(a);
       clb3::k3_step<false, true><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
     } else if (force) {
       clb3::k3_step<true, false><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);

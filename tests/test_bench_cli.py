@@ -23,5 +23,5 @@ def test_more_than_one_gpu_is_refused():
 def test_help_lists_the_parts():
     res = _bench("--help")
     assert res.returncode == 0
-    for part in ("step", "sweep", "pressure", "msweep", "adjoint", "duct"):
+    for part in ("step", "sweep", "pressure", "msweep", "adjoint", "duct", "pduct"):
         assert part in res.stdout
