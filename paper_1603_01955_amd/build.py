@@ -53,6 +53,13 @@ def hipcc():
 # Sources that define the single-channel step kernels (ties recorded
 # profile data to the kernel version it was measured on).
 STEP_SOURCES = ["clb_device.hpp", "clb_gather.hpp", "clb_internal.hpp", "clb_kernels.hip"]
+# Sources of the 3-D duct kernels (clb3d.hip and the headers it includes).
+DUCT_SOURCES = ["clb3d.hip", "clb_device.hpp", "clb_internal.hpp", "clb_trace.hpp"]
+
+
+def sources_2d():
+    """Every csrc/ file but the 3-D duct's own source."""
+    return sorted(f for f in os.listdir(CSRC) if f != "clb3d.hip")
 
 
 def source_hash(names=STEP_SOURCES):
