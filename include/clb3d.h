@@ -105,7 +105,7 @@ clb_status clb3_derive(const clb3_params* p, clb_derived* out);
 
 /* Device workspace in bytes: two population buffers (216 bytes per node,
  * rows padded to whole segments of the device layout), reduction scratch,
- * three doubles per column and, for a pressure-driven duct, the two ghost
+ * 67 doubles per column and, for a pressure-driven duct, the two ghost
  * planes (432 bytes per row of the cross-section). */
 clb_status clb3_workspace_size(const clb3_params* p, size_t* bytes);
 

@@ -484,32 +484,48 @@ __global__ __launch_bounds__(256) void k3_rates(Args a) {
   }
 }
 
-// Cross-section sums of the pre-collision state, one workgroup per x:
-// m[x] = sum_{y,z} rho u_x (rho u_x = j_x + rho F_x / 2, Eq. 13) and, for a
-// pressure-driven duct, rhoc[x] = rho_c(x).  Fixed summation order:
-// strided per-thread sums, wavefront butterflies, the four wavefront totals
-// in order.  Either output may be NULL.
-__global__ __launch_bounds__(256) void k3_sections(Args a, double* m, double* rhoc) {
+// Mass flow through the cross-sections, first pass: the rows of each
+// cross-section are cut into kRowParts contiguous parts; wavefront (x block
+// of 64 columns, part r) sums rho u_x (= j_x + rho F_x / 2, Eq. 13) of the
+// pre-collision state over its part's rows in order, one column per lane
+// (the loads of a row are one 512-byte piece per direction), and writes
+// part[r][x].
+constexpr int kRowParts = 64;
+
+__global__ __launch_bounds__(64) void k3_mass_parts(Args a, double* part) {
 #pragma clang fp contract(off)
-  __shared__ double s[4];
-  const int x = blockIdx.x;
-  if (m) {
-    const size_t cs = (size_t)a.ny * (size_t)a.nz;
-    double acc = 0.0;
-    for (size_t k = threadIdx.x; k < cs; k += 256) {
-      const int y = (int)(k % (size_t)a.ny), z = (int)(k / (size_t)a.ny);
-      double f[27];
-      gather_any(a, x, y, z, f);
-      double r, jx, jy, jz;
-      rho_j(f, r, jx, jy, jz);
-      acc += jx + 0.5 * r * a.gx;
-    }
-    acc = clb::wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) m[x] = (s[0] + s[1]) + (s[2] + s[3]);
+  const int x = blockIdx.x * 64 + (int)threadIdx.x;
+  if (x >= a.nx) return;
+  const size_t cs = (size_t)a.ny * (size_t)a.nz;
+  const size_t r = blockIdx.y;
+  const size_t k0 = r * cs / kRowParts, k1 = (r + 1) * cs / kRowParts;
+  double acc = 0.0;
+  for (size_t k = k0; k < k1; ++k) {
+    const int y = (int)(k % (size_t)a.ny), z = (int)(k / (size_t)a.ny);
+    double f[27];
+    gather_any(a, x, y, z, f);
+    double rho, jx, jy, jz;
+    rho_j(f, rho, jx, jy, jz);
+    acc += jx + 0.5 * rho * a.gx;
   }
-  if (rhoc && threadIdx.x == 0) rhoc[x] = centre_density(a, x);
+  part[r * (size_t)a.nx + (size_t)x] = acc;
+}
+
+// Second pass, one thread per x: m[x] = the parts in order r = 0, 1, ...
+__global__ __launch_bounds__(256) void k3_mass_sum(Args a, const double* __restrict__ part, double* m) {
+#pragma clang fp contract(off)
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= a.nx) return;
+  double acc = 0.0;
+  for (int r = 0; r < kRowParts; ++r) acc += part[(size_t)r * (size_t)a.nx + (size_t)x];
+  m[x] = acc;
+}
+
+// rhoc[x] = rho_c(x), one thread per x (pressure-driven ducts).
+__global__ __launch_bounds__(256) void k3_centre(Args a, double* rhoc) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= a.nx) return;
+  rhoc[x] = centre_density(a, x);
 }
 
 // Pressure deviation along the centre line (Section 3.2), one thread per x:
@@ -638,7 +654,7 @@ struct clb3_ctx {
   int cur;
   double* partial;
   double* result;
-  double* cols;     // [3][nx]: s_nu(x), s_q(x) of a pressure-driven duct, then per-x scratch
+  double* cols;     // [3 + kRowParts][nx]: s_nu(x), s_q(x) of a pressure-driven duct, per-x scratch, mass-flow parts
   double* ghosts;   // [2][nz][ny][27] ghost planes (pressure-driven ducts; NULL otherwise)
   hipStream_t stream;
   int64_t steps;
@@ -735,7 +751,11 @@ size_t buffer_bytes(const clb3_params* p) {
                         << lshift_of(p));
 }
 
-size_t cols_bytes(const clb3_params* p) { return clb3::align256(3 * (size_t)p->nx * sizeof(double)); }
+// Per-column scratch: s_nu(x), s_q(x), one diagnostic column, the mass
+// flow's kRowParts partial columns.
+size_t cols_bytes(const clb3_params* p) {
+  return clb3::align256((3 + clb3::kRowParts) * (size_t)p->nx * sizeof(double));
+}
 
 size_t ghost_bytes(const clb3_params* p) {
   return p->xbc == CLB_X_PRESSURE ? clb3::align256(2 * 27 * (size_t)p->ny * (size_t)p->nz * sizeof(double)) : 0;
@@ -937,7 +957,9 @@ clb_status clb3_massflow(clb3_ctx* c, double* d_m_col, double* h_m_mean) {
   const clb3::Args a = args_of(c);
   if ((st = refresh_ghosts(c, a)) != CLB_OK) return st;
   double* m = d_m_col ? d_m_col : c->cols + 2 * (size_t)c->p.nx;
-  clb3::k3_sections<<<(unsigned)c->p.nx, 256, 0, c->stream>>>(a, m, nullptr);
+  double* part = c->cols + 3 * (size_t)c->p.nx;
+  clb3::k3_mass_parts<<<dim3((unsigned)((c->p.nx + 63) / 64), clb3::kRowParts), 64, 0, c->stream>>>(a, part);
+  clb3::k3_mass_sum<<<(unsigned)((c->p.nx + 255) / 256), 256, 0, c->stream>>>(a, part, m);
   CLB3_HIP(hipGetLastError());
   if (!h_m_mean) return CLB_OK;
   clb3::k3_sum<<<1, 256, 0, c->stream>>>(m, c->p.nx, c->result);
@@ -959,7 +981,7 @@ clb_status clb3_pressure_deviation(clb3_ctx* c, double* d_dp, double* d_rho_c) {
   const clb3::Args a = args_of(c);
   if ((st = refresh_ghosts(c, a)) != CLB_OK) return st;
   double* rc = d_rho_c ? d_rho_c : c->cols + 2 * (size_t)c->p.nx;
-  clb3::k3_sections<<<(unsigned)c->p.nx, 64, 0, c->stream>>>(a, nullptr, rc);
+  clb3::k3_centre<<<(unsigned)((c->p.nx + 255) / 256), 256, 0, c->stream>>>(a, rc);
   if (d_dp) clb3::k3_pressure_dev<<<(unsigned)((c->p.nx + 255) / 256), 256, 0, c->stream>>>(a, rc, d_dp);
   CLB3_HIP(hipGetLastError());
   return CLB_OK;

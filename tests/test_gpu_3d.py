@@ -277,3 +277,18 @@ def test_mode_specific_diagnostics_refuse_the_other_mode():
         p.flow_rate()
     f.massflow()   # the mass flow serves both kinds of duct
     p.massflow()
+
+
+@pytest.mark.parametrize("ny,nz", [(4, 4), (3, 5)])
+def test_pressure_full_length_duct(ny, nz):
+    """The benchmarked pressure-driven duct's full length (nx = 4000: four
+    row segments of 1024 columns, 62.5 workgroups of 64 columns), with the
+    cross-section cut so the reference can hold it: random state, two steps."""
+    kw = _pressure(dict(nx=4000, ny=ny, nz=nz, kn=0.1, p_ratio=2.0))
+    P0 = uniform_populations_3d(4000, ny, nz, seed=47)
+    s = _duct(**kw)
+    s.set_populations(torch.from_numpy(P0))
+    s.step(2)
+    ref = D.run(P0, _oracle_params(kw), 2)
+    assert _rel(s.populations().cpu().numpy(), ref) <= TOL
+    s.close()
