@@ -90,6 +90,31 @@ struct TileView {
   __device__ __forceinline__ int ny() const { return ny_; }
 };
 
+// The HBM rows a multi-step tile reads and writes, addressed by 32-bit byte
+// offsets from a workgroup-uniform base (row ybase, direction 0, lane 0):
+// a load's address is one 32-bit sum of its row part, column part and
+// direction slot added to a base in scalar registers, instead of a 64-bit
+// index product per load.  Valid while the rows a tile touches
+// (kTileRowsMax of them) span less than 4 GiB.
+constexpr int kTileRowsMax = 17;   // H + 2 for the largest H
+
+struct RowsView {
+  const char* base;
+  int ybase;
+  uint32_t row_bytes;   // bytes per row of the device layout
+  int lshift;
+  int nx_, ny_;
+  __device__ __forceinline__ uint32_t offset(int i, int x, int y) const {
+    const uint32_t col = ((uint32_t)((x >> lshift) * 9 + i) << lshift) + (uint32_t)(x & ((1 << lshift) - 1));
+    return (uint32_t)(y - ybase) * row_bytes + (col << 3);
+  }
+  __device__ __forceinline__ double at(int i, int x, int y) const {
+    return *reinterpret_cast<const double*>(base + offset(i, x, y));
+  }
+  __device__ __forceinline__ int nx() const { return nx_; }
+  __device__ __forceinline__ int ny() const { return ny_; }
+};
+
 template <int K>
 constexpr int tile_w() {
   return kTileX + 2 * (K - 1);
@@ -143,6 +168,10 @@ __global__ __launch_bounds__(kStepKThreads, 8) void k_stepk_periodic(StepArgs a)
   const int x0 = bx * kTileX - (K - 1), y0 = by * (H - 2 * (K - 1)) - (K - 1);   // LDS (0, 0)
   const int t = threadIdx.x;
   const Rates s{a.s3, a.snu, a.sq, a.s8};
+  // the first row any step of this tile reads or writes
+  const int ybase = y0 - 1 < 0 ? 0 : y0 - 1;
+  const uint32_t row_bytes = (uint32_t)((a.g.nseg * 9) << a.g.lshift) << 3;
+  const size_t base_off = (size_t)ybase * (size_t)((a.g.nseg * 9) << a.g.lshift);
   {
     int lx, ly;
     if (region_node<K, H>(1, t, lx, ly)) {
@@ -150,7 +179,9 @@ __global__ __launch_bounds__(kStepKThreads, 8) void k_stepk_periodic(StepArgs a)
       if (y >= 0 && y < ny) {          // rows beyond a wall are skipped
         int xw = x % nx;               // x >= -(K - 1)
         if (xw < 0) xw += nx;
-        const Gather<0, View> gat{{a.src, a.g}, a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
+        const Gather<0, RowsView> gat{{reinterpret_cast<const char*>(a.src + base_off), ybase, row_bytes, a.g.lshift,
+                                       nx, ny},
+                                      a.r, 1.0 - a.r, a.shift, 0.0, 0.0};
         double f[9];
         gat(xw, y, f);
         collide<FORCE, THIRD>(f, a.gx, a.gy, s);
@@ -188,7 +219,10 @@ __global__ __launch_bounds__(kStepKThreads, 8) void k_stepk_periodic(StepArgs a)
       double f[9];
       lds(x, y, f);
       collide<FORCE, THIRD>(f, a.gx, a.gy, s);
-      store9(a.dst, a.g, x, y, f);
+      const RowsView out{reinterpret_cast<const char*>(a.dst + base_off), ybase, row_bytes, a.g.lshift, nx, ny};
+      char* const q = reinterpret_cast<char*>(a.dst + base_off);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], reinterpret_cast<double*>(q + out.offset(i, x, y)));
     }
   }
 }
@@ -1023,8 +1057,12 @@ hipError_t launch_stepk_t(const StepArgs& a, hipStream_t st) {
 // wide: around a narrower channel (the 4-column channels of the Kn sweep)
 // the 64-column tile recomputes the few real columns many times over (a
 // loop of 64 such single-channel runs took 3.6 s instead of 2.7 s).
+// The tiles also address their rows with 32-bit offsets (RowsView): rows of
+// more than 4 GiB / kTileRowsMax (channels of more than 3.5 M columns) take
+// one step per launch.
 bool periodic_multi_step_ok(const StepArgs& a) {
-  return a.mode == 0 && a.g.nx >= kTileX;
+  const size_t row_bytes = ((size_t)a.g.nseg * 9 << a.g.lshift) * sizeof(double);
+  return a.mode == 0 && a.g.nx >= kTileX && (size_t)kTileRowsMax * row_bytes <= 0xFFFFFFFFull;
 }
 
 hipError_t stepk_setup() {
