@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--part", choices=("all", "step", "sweep", "pressure", "msweep", "adjoint", "duct", "pduct"),
                     default="all",
-                    help="run one part alone (step: the periodic step only; sweep / pressure / msweep / adjoint / "
+                    help="run one part alone (step: the periodic step only, at the chosen steps per launch alone; sweep / pressure / msweep / adjoint / "
                          "duct (force-driven 3-D duct) / pduct (pressure-driven 3-D duct): that measurement only, "
                          "printed as its own JSON line) -- for profiling runs")
     ap.add_argument("--no-loop-baseline", action="store_true",
@@ -642,21 +642,31 @@ def main():
     ok = s.check_finite()
     mlups = nodes / (ms * 1e-3) / 1e6
     k = args.steps_per_launch if s.nx >= 64 else 1   # narrower grids step one at a time
-    # the same grid at two steps per launch, for that form's HBM fraction
-    alt = None
-    if k != 2 and s.nx >= 64:
-        s.set_steps_per_launch(2)
-        s.step(4)
-        n2 = max(2, args.steps // 2 * 2)
+    def at_steps_per_launch(kk, n):
+        """The same grid at kk steps per launch: its speed and its launch's
+        HBM fraction (144 B per node per launch over the launch time)."""
+        s.set_steps_per_launch(kk)
+        s.step(2 * kk)
+        n = max(kk, n // kk * kk)
         t0.record(stream)
-        s.step(n2)
+        s.step(n)
         t1.record(stream)
         torch.cuda.synchronize()
-        ms2 = t0.elapsed_time(t1) / n2
-        alt = {"steps_per_launch": 2, "steps": n2, "ms_per_step": round(ms2, 4),
-               "mlups": round(nodes / (ms2 * 1e-3) / 1e6, 1),
-               "achieved": round(BYTES_PER_NODE * nodes / (2 * ms2 * 1e-3) / 1e9, 1),
-               "frac": round(BYTES_PER_NODE * nodes / (2 * ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        msk = t0.elapsed_time(t1) / n
+        gbs = BYTES_PER_NODE * nodes / (kk * msk * 1e-3) / 1e9
+        return {"steps_per_launch": kk, "steps": n, "ms_per_step": round(msk, 4),
+                "mlups": round(nodes / (msk * 1e-3) / 1e6, 1), "achieved": round(gbs, 1),
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    # the same grid at two steps per launch and at one (the one-step kernel),
+    # for their HBM fractions: fewer steps per launch draw more of HBM and
+    # advance the grid more slowly
+    alt = alt1 = None
+    if s.nx >= 64 and args.part != "step":   # the step part times the default form alone (profiling runs)
+        if k != 2:
+            alt = at_steps_per_launch(2, args.steps)
+        if k != 1:
+            alt1 = at_steps_per_launch(1, min(args.steps, 300))
     # average duration of one k-step launch (steps % k of the timed steps run
     # in one shorter launch at the end: one launch in 334 at 1000 steps, k = 3)
     launch_s = ms * 1e-3 * k
@@ -715,6 +725,7 @@ def main():
                      # node updates x 144 B over the time: the bandwidth a one-step kernel would need
                      "effective_gbs": round(BYTES_PER_NODE * nodes * k / launch_s / 1e9, 1),
                      "two_steps_per_launch": alt,
+                     "one_step_per_launch": alt1,
                      "bound_us": {"hbm_at_copy_rate": round(t_hbm * 1e6, 1) if t_hbm else None,
                                   "valu_issue": round(t_valu * 1e6, 1) if t_valu else None},
                      "bound_time_frac": round(max(t_hbm, t_valu) / launch_s, 4) if t_hbm and t_valu else None},
