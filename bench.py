@@ -374,6 +374,32 @@ def duct3d(steps=100, warmup=5):
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "unit_bytes": "432 B per node update"}}
 
 
+def pressure_duct_steady(chunk=5000, max_chunks=40):
+    """A shorter pressure-driven duct (400 x 8 x 8, p_in/p_out = 2,
+    Kn_out = 0.1, linear start) run until its mass flow is the same through
+    every cross-section to 1e-9: the axial pressure deviation of the steady
+    state (its peak and where it lies) and the mass flow."""
+    import numpy as np
+    from paper_1603_01955_amd import Duct
+    s = Duct(nx=400, ny=8, nz=8, xbc="pressure", kn=0.1, p_ratio=2.0, init="linear_rho")
+    t0 = time.perf_counter()
+    spread, mean, n = None, None, 0
+    for _ in range(max_chunks):
+        s.step(chunk)
+        n += chunk
+        m, mean = s.massflow()
+        m = m.cpu().numpy()
+        spread = float((m.max() - m.min()) / mean)
+        if spread < 1e-9:
+            break
+    dp = s.pressure_deviation()[0].cpu().numpy()
+    wall = time.perf_counter() - t0
+    s.close()
+    k = int(np.argmax(dp))
+    return {"steps": n, "seconds": round(wall, 3), "mass_flow": mean, "mass_flow_spread": spread,
+            "dp_max": round(float(dp[k]), 6), "x_over_L_at_dp_max": round((k + 0.5) / 400, 4)}
+
+
 def duct3d_pressure(steps=200, warmup=5):
     """The pressure-driven 3-D duct (4000 x 40 x 40, L/H = 100,
     p_in/p_out = 2, Kn_out = 0.1, linear start): time per step with HIP
@@ -412,8 +438,9 @@ def duct3d_pressure(steps=200, warmup=5):
         st["P"] = D.step(st["P"], prm)
     cpu = oracle_rate(step, w["nx"] * 16, "a 4000 x 4 x 4 pressure-driven duct (the same length, Kn_out and "
                                           "pressure ratio, the cross-section cut to 4 x 4)")
+    steady = pressure_duct_steady()
     return {"workload": "duct_pressure_4000x40x40", "steps": steps, "ms_per_step": round(ms, 4), "finite": ok,
-            "mass_flow_mean": m_mean, "cpu_oracle": cpu,
+            "mass_flow_mean": m_mean, "steady_400x8x8": steady, "cpu_oracle": cpu,
             "mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4),

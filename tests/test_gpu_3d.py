@@ -292,3 +292,31 @@ def test_pressure_full_length_duct(ny, nz):
     ref = D.run(P0, _oracle_params(kw), 2)
     assert _rel(s.populations().cpu().numpy(), ref) <= TOL
     s.close()
+
+
+def test_pressure_duct_steady_state_properties():
+    """A pressure-driven square duct (400 x 8 x 8, p_in/p_out = 2,
+    Kn_out = 0.1) run on the GPU until the mass flow no longer varies along
+    the duct: the steady state of Section 3.2 carried to 3-D -- one positive
+    mass flow through every cross-section (to 1e-9: the discrete steady
+    state conserves mass section by section; it gets there in about 65,000
+    steps), and an axial pressure lying above the linear profile
+    (compressibility: the deviation is positive inside the duct and peaks
+    past the middle, as in the 2-D channel)."""
+    kw = _pressure(dict(nx=400, ny=8, nz=8, kn=0.1, p_ratio=2.0, init="linear_rho"))
+    s = _duct(**kw)
+    spread = None
+    for _ in range(40):
+        s.step(5000)
+        m, mean = s.massflow()
+        m = m.cpu().numpy()
+        spread = (m.max() - m.min()) / mean
+        if spread < 1e-9:
+            break
+    assert s.check_finite()
+    assert mean > 0 and spread < 1e-9, spread
+    dp, _ = s.pressure_deviation()
+    dp = dp.cpu().numpy()
+    assert dp[20:-20].min() > 0
+    assert 0.45 < (np.argmax(dp) + 0.5) / 400 < 0.65
+    s.close()
