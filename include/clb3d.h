@@ -119,6 +119,15 @@ clb_status clb3_init(const clb3_params* p, void* d_workspace, size_t bytes, void
  * every cross-section from the state, three launches per step). */
 clb_status clb3_step(clb3_ctx* c, int64_t nsteps);
 
+/* Launch-overhead control for small ducts (a pressure-driven duct launches
+ * three kernels per step): with steps_per_graph in [1, 100000], clb3_step
+ * replays a hipGraph of steps_per_graph recorded steps (recorded on first
+ * use from each buffer parity, on a private stream, and replayed on the
+ * context's stream) and launches any remainder directly; 0 (default)
+ * disables it.  Results are identical either way.  Synchronises the stream
+ * when the setting changes.  CLB_EINVAL outside [0, 100000]. */
+clb_status clb3_set_graph_steps(clb3_ctx* c, int32_t steps_per_graph);
+
 /* Steps taken since clb3_init / the last clb3_set_populations. */
 clb_status clb3_steps_done(const clb3_ctx* c, int64_t* h_steps);
 

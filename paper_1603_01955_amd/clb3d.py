@@ -33,6 +33,7 @@ _SIGNATURES3 = {
     "clb3_init": (ctypes.c_int, [_P, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_void_p)]),
     "clb3_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "clb3_set_graph_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "clb3_steps_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "clb3_moments": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "clb3_massflow": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
@@ -111,6 +112,11 @@ class Duct:
 
     def step(self, n=1):
         clb.check(lib().clb3_step(self._ctx, int(n)))
+        return self
+
+    def set_graph_steps(self, steps):
+        """Replay recorded hipGraphs of `steps` steps (0: launch directly)."""
+        clb.check(lib().clb3_set_graph_steps(self._ctx, int(steps)))
         return self
 
     @property

@@ -658,6 +658,11 @@ struct clb3_ctx {
   double* ghosts;   // [2][nz][ny][27] ghost planes (pressure-driven ducts; NULL otherwise)
   hipStream_t stream;
   int64_t steps;
+  // optional hipGraph of graph_steps steps, one per starting buffer
+  int graph_steps;
+  hipStream_t capture;   // private stream used only to record the graphs
+  hipGraph_t graph[2];
+  hipGraphExec_t gexec[2];
 };
 
 namespace {
@@ -766,10 +771,11 @@ size_t total_bytes(const clb3_params* p) {
          cols_bytes(p) + ghost_bytes(p);
 }
 
-clb3::Args args_of(const clb3_ctx* c) {
+// Arguments of a step from buffer cur to the other one.
+clb3::Args args_at(const clb3_ctx* c, int cur) {
   clb3::Args a{};
-  a.src = c->buf[c->cur];
-  a.dst = c->buf[c->cur ^ 1];
+  a.src = c->buf[cur];
+  a.dst = c->buf[cur ^ 1];
   a.nx = c->p.nx;
   a.ny = c->p.ny;
   a.nz = c->p.nz;
@@ -800,12 +806,79 @@ clb3::Args args_of(const clb3_ctx* c) {
   return a;
 }
 
-// The ghost planes of the current state (pressure-driven ducts): the step,
-// and every diagnostic that gathers, reads them.
+clb3::Args args_of(const clb3_ctx* c) { return args_at(c, c->cur); }
+
+// The ghost planes of the state a.src (pressure-driven ducts) on stream st:
+// the step, and every diagnostic that gathers, reads them.
+void launch_ghosts(const clb3_ctx* c, const clb3::Args& a, hipStream_t st) {
+  clb3::k3_ghosts<<<clb3::group_blocks(2 * (size_t)c->p.ny * (size_t)c->p.nz), 256, 0, st>>>(a);
+}
+
 clb_status refresh_ghosts(clb3_ctx* c, const clb3::Args& a) {
   if (!a.pressure) return CLB_OK;
-  clb3::k3_ghosts<<<clb3::group_blocks(2 * (size_t)c->p.ny * (size_t)c->p.nz), 256, 0, c->stream>>>(a);
+  launch_ghosts(c, a, c->stream);
   CLB3_HIP(hipGetLastError());
+  return CLB_OK;
+}
+
+dim3 node_grid(const clb3_params* p);
+
+// Enqueue n steps on stream st starting from buffer parity *cur (updated
+// per step enqueued): per step of a pressure-driven duct the ghost planes,
+// the rates of every cross-section and the step; otherwise the step alone.
+// *done counts the steps enqueued (all n unless a launch fails).
+hipError_t enqueue_steps3(const clb3_ctx* c, int64_t n, hipStream_t st, int* cur, int64_t* done) {
+  *done = 0;
+  const dim3 g3 = node_grid(&c->p);
+  const dim3 grid(g3.x * g3.y * g3.z);   // k3_step orders its workgroups itself
+  const bool force = c->p.gx != 0.0 || c->p.gy != 0.0 || c->p.gz != 0.0;
+  const bool pressure = c->p.xbc == CLB_X_PRESSURE;
+  for (int64_t k = 0; k < n; ++k) {
+    const clb3::Args a = args_at(c, *cur);
+    if (pressure) {
+      launch_ghosts(c, a, st);
+      clb3::k3_rates<<<clb3::group_blocks((size_t)c->p.nx), 256, 0, st>>>(a);
+      clb3::k3_step<false, true><<<grid, clb3::kBX * clb3::kBY, 0, st>>>(a);
+    } else if (force) {
+      clb3::k3_step<true, false><<<grid, clb3::kBX * clb3::kBY, 0, st>>>(a);
+    } else {
+      clb3::k3_step<false, false><<<grid, clb3::kBX * clb3::kBY, 0, st>>>(a);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    *cur ^= 1;
+    *done += 1;
+  }
+  return hipSuccess;
+}
+
+void drop_graphs3(clb3_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+}
+
+// Record graph_steps steps starting from buffer parity c->cur on the
+// private capture stream (recording only: nothing runs there).
+clb_status record_graph3(clb3_ctx* c) {
+  const int p = c->cur;
+  if (!c->capture) CLB3_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+  CLB3_HIP(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+  int cur = p;
+  int64_t done = 0;
+  const hipError_t e = enqueue_steps3(c, c->graph_steps, c->capture, &cur, &done);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->capture, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail3(CLB_EHIP, "step launch during graph capture: %s", hipGetErrorString(e));
+  }
+  if (e2 != hipSuccess) return fail3(CLB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+  c->graph[p] = g;
+  CLB3_HIP(hipGraphInstantiate(&c->gexec[p], g, nullptr, nullptr, 0));
   return CLB_OK;
 }
 
@@ -902,25 +975,29 @@ clb_status clb3_step(clb3_ctx* c, int64_t nsteps) {
   const clb::TraceRange trace("clb3_step");
   if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
   if (nsteps < 0) return fail3(CLB_EINVAL, "nsteps: must be >= 0");
-  const dim3 g3 = node_grid(&c->p);
-  const dim3 grid(g3.x * g3.y * g3.z);   // k3_step orders its workgroups itself
-  const bool force = c->p.gx != 0.0 || c->p.gy != 0.0 || c->p.gz != 0.0;
-  const bool pressure = c->p.xbc == CLB_X_PRESSURE;
-  for (int64_t n = 0; n < nsteps; ++n) {
-    const clb3::Args a = args_of(c);
-    if (pressure) {   // ghost planes, then the rates of every cross-section, then the step
-      clb_status st = refresh_ghosts(c, a);
-      if (st != CLB_OK) return st;
-      clb3::k3_rates<<<clb3::group_blocks((size_t)c->p.nx), 256, 0, c->stream>>>(a);
-      clb3::k3_step<false, true><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
-    } else if (force) {
-      clb3::k3_step<true, false><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
-    } else {
-      clb3::k3_step<false, false><<<grid, clb3::kBX * clb3::kBY, 0, c->stream>>>(a);
-    }
-    CLB3_HIP(hipGetLastError());
-    c->cur ^= 1;
-    c->steps += 1;
+  clb_status st = CLB_OK;
+  while (c->graph_steps > 0 && nsteps >= c->graph_steps) {
+    if (!c->gexec[c->cur] && (st = record_graph3(c)) != CLB_OK) return st;
+    CLB3_HIP(hipGraphLaunch(c->gexec[c->cur], c->stream));
+    c->cur ^= c->graph_steps & 1;   // every step swaps the buffers
+    c->steps += c->graph_steps;
+    nsteps -= c->graph_steps;
+  }
+  int64_t done = 0;
+  const hipError_t e = enqueue_steps3(c, nsteps, c->stream, &c->cur, &done);
+  c->steps += done;
+  if (e != hipSuccess) return fail3(CLB_EHIP, "clb3_step: %s", hipGetErrorString(e));
+  return CLB_OK;
+}
+
+clb_status clb3_set_graph_steps(clb3_ctx* c, int32_t steps_per_graph) {
+  if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  if (steps_per_graph < 0 || steps_per_graph > 100000)
+    return fail3(CLB_EINVAL, "steps_per_graph: must lie in [0, 100000]");
+  if (steps_per_graph != c->graph_steps) {
+    CLB3_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs3(c);
+    c->graph_steps = steps_per_graph;
   }
   return CLB_OK;
 }
@@ -1043,6 +1120,9 @@ clb_status clb3_check_finite(clb3_ctx* c, int32_t* h_ok) {
 
 clb_status clb3_destroy(clb3_ctx* c) {
   if (!c) return fail3(CLB_EINVAL, "ctx: NULL");
+  if (c->gexec[0] || c->gexec[1]) (void)hipStreamSynchronize(c->stream);
+  drop_graphs3(c);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
   delete c;
   return CLB_OK;
 }

@@ -168,6 +168,7 @@ int main() {
   EXPECT(clb3_step(nullptr, 1) == CLB_EINVAL);
   EXPECT(clb3_flow_rate(nullptr, nullptr) == CLB_EINVAL);
   EXPECT(clb3_massflow(nullptr, nullptr, nullptr) == CLB_EINVAL);
+  EXPECT(clb3_set_graph_steps(nullptr, 4) == CLB_EINVAL);
   EXPECT(clb3_pressure_deviation(nullptr, nullptr, nullptr) == CLB_EINVAL);
   EXPECT(clb3_destroy(nullptr) == CLB_EINVAL);
   clb3_ctx* c3 = nullptr;
