@@ -115,6 +115,24 @@ struct RowsView {
   __device__ __forceinline__ int ny() const { return ny_; }
 };
 
+// A whole population buffer of less than 4 GiB addressed by 32-bit byte
+// offsets from its (uniform) base: the pressure kernels' HBM loads and
+// stores, one 32-bit index per access instead of 64-bit products.
+struct View32 {
+  const char* base;
+  Geo g;
+  __device__ __forceinline__ uint32_t offset(int i, int x, int y) const {
+    const uint32_t seg = (uint32_t)y * (uint32_t)g.nseg + (uint32_t)(x >> g.lshift);
+    return (((seg * 9 + (uint32_t)i) << g.lshift) + (uint32_t)(x & ((1 << g.lshift) - 1))) << 3;
+  }
+  __device__ __forceinline__ const double* ptr(int i, int x, int y) const {
+    return reinterpret_cast<const double*>(base + offset(i, x, y));
+  }
+  __device__ __forceinline__ double at(int i, int x, int y) const { return *ptr(i, x, y); }
+  __device__ __forceinline__ int nx() const { return g.nx; }
+  __device__ __forceinline__ int ny() const { return g.ny; }
+};
+
 template <int K>
 constexpr int tile_w() {
   return kTileX + 2 * (K - 1);
@@ -391,7 +409,8 @@ __device__ __forceinline__ void pressurek_step(const StepArgs& a, int blk, doubl
   if (need_in || need_out) {   // uniform across the workgroup
     const int tid = ty * W + lx, nthreads = W * ny;
     if (k == 1)
-      fill_ghosts_lean(View{a.src, a.g}, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
+      fill_ghosts_lean(View32{reinterpret_cast<const char*>(a.src), a.g}, a.rho_in, a.rho_out, need_in, need_out, gh,
+                       gh + 9 * ny, tid, nthreads);
     else
       fill_ghosts_lean(tv, a.rho_in, a.rho_out, need_in, need_out, gh, gh + 9 * ny, tid, nthreads);
     __syncthreads();
@@ -401,11 +420,11 @@ __device__ __forceinline__ void pressurek_step(const StepArgs& a, int blk, doubl
   double f[9];
   if (valid) {
     if (k == 1) {
-      const View v{a.src, a.g};
+      const View32 v{reinterpret_cast<const char*>(a.src), a.g};
       if (need_in || need_out)
-        Gather<2, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}(x, ty, f);
+        Gather<2, View32>{v, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}(x, ty, f);
       else
-        Gather<3, View>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}(x, ty, f);
+        Gather<3, View32>{v, a.r, omr, a.shift, a.rho_in, a.rho_out}(x, ty, f);
     } else {
       if (need_in || need_out)
         Gather<2, TileView>{tv, a.r, omr, a.shift, a.rho_in, a.rho_out, gh, gh + 9 * ny}(x, ty, f);
@@ -429,7 +448,10 @@ __device__ __forceinline__ void pressurek_step(const StepArgs& a, int blk, doubl
 #pragma unroll
       for (int i = 0; i < 9; ++i) s1[(i * ny + ty) * W + lx] = f[i];
     } else {
-      store9(a.dst, a.g, x, ty, f);
+      const View32 out{reinterpret_cast<const char*>(a.dst), a.g};
+      char* const q = reinterpret_cast<char*>(a.dst);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], reinterpret_cast<double*>(q + out.offset(i, x, ty)));
     }
   }
 }
@@ -906,10 +928,13 @@ hipError_t launch_step(const StepArgs& a, int block_x, hipStream_t st, size_t ld
 // 12.4 us (32-column tiles).
 constexpr int kPressureMultiStepRows = 48;
 
+// (The multi-step kernels address a buffer by 32-bit byte offsets.)
+bool buffer_below_4gib(const Geo& g) { return g.size() * sizeof(double) <= 0xFFFFFFFFull; }
+
 bool pressure_multi_step_ok(const StepArgs& a) {
   const bool rows = a.col_rates && a.ghosts &&
                     (a.pressure_path == 2 || (a.pressure_path == 0 && (size_t)a.g.nx * a.g.ny >= kPressureRowNodes));
-  return a.mode == 1 && a.g.ny <= kPressureMultiStepRows && !rows;
+  return a.mode == 1 && a.g.ny <= kPressureMultiStepRows && !rows && buffer_below_4gib(a.g);
 }
 
 // Width of K2e: the widest of 32, 16, 8 columns with (CX + 2(k - 1)) ny <=
@@ -974,7 +999,7 @@ hipError_t launch_stepk_pressure(const StepArgs& a, int k, hipStream_t st) {
 bool pbatch_multi_step_ok(const PBatchArgs& a) {
   const bool rows = a.col_rates && a.ghosts &&
                     (a.path == 2 || (a.path == 0 && (size_t)a.nch * a.g.nx * a.g.ny >= kPBatchRowNodes));
-  return a.g.ny <= kPressureMultiStepRows && !rows;
+  return a.g.ny <= kPressureMultiStepRows && !rows && buffer_below_4gib(a.g);
 }
 
 hipError_t launch_pbatch_stepk(const PBatchArgs& a, int k, hipStream_t st) {
