@@ -347,3 +347,20 @@ def test_graph_replay_equals_direct_launches(xbc):
     assert torch.equal(g.populations(), ref.populations())
     ref.close()
     g.close()
+
+
+def test_force_driven_mass_flow():
+    """clb3_massflow on a force-driven duct: sum over each cross-section of
+    rho u_x with the force's half step (Eq. 13), as the reference's."""
+    kw = dict(nx=9, ny=7, nz=6, kn=0.3, gx=2e-4, gz=1e-5)
+    P0 = uniform_populations_3d(9, 7, 6, seed=53)
+    s = _duct(**kw)
+    s.set_populations(torch.from_numpy(P0))
+    s.step(2)
+    prm = _oracle_params(kw)
+    P = D.run(P0, prm, 2)
+    m, mean = s.massflow()
+    ref = D.mass_flow(P, prm)
+    assert np.max(np.abs(m.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert abs(mean - ref.mean()) <= 1e-12 * np.max(np.abs(ref))
+    s.close()
