@@ -364,3 +364,28 @@ def test_force_driven_mass_flow():
     assert np.max(np.abs(m.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
     assert abs(mean - ref.mean()) <= 1e-12 * np.max(np.abs(ref))
     s.close()
+
+
+def test_pressure_duct_full_size_symmetries():
+    """The benchmarked pressure-driven duct itself (4000 x 40 x 40, linear
+    start), 30 steps on the GPU: properties that hold at any size -- the
+    state stays mirror-symmetric in y and in z and symmetric under the
+    exchange of y and z (a square cross-section), and it stays finite.
+    Compared on the GPU, to rounding."""
+    kw = _pressure(dict(nx=4000, ny=40, nz=40, kn=0.1, p_ratio=2.0, init="linear_rho"))
+    s = _duct(**kw)
+    s.step(30)
+    assert s.check_finite()
+    P = s.populations()                       # (27, nz, ny, nx)
+    E = [(i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1) for i in range(27)]
+    d = lambda a, b, c: (a + 1) + 3 * (b + 1) + 9 * (c + 1)
+    scale = float(P.abs().max())
+    my = P[[d(a, -b, c) for a, b, c in E]].flip(2)
+    assert float((P - my).abs().max()) <= 1e-13 * scale
+    del my
+    mz = P[[d(a, b, -c) for a, b, c in E]].flip(1)
+    assert float((P - mz).abs().max()) <= 1e-13 * scale
+    del mz
+    sw = P[[d(a, c, b) for a, b, c in E]].transpose(1, 2)
+    assert float((P - sw).abs().max()) <= 1e-13 * scale
+    s.close()
