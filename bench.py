@@ -529,7 +529,11 @@ def mass_flow_sweep(check_every=2000, tol=1e-10, max_steps=3000000, step_probe=2
     pb.close()
     out = {"workload": "mass_flow_sweep_16x2000x20", "channels": len(params), "p_ratio": w["p_ratio"],
            "sigma": w["sigma"], "kn_out": [round(k, 5) for k in kns],
-           "S": [round(float(v), 6) for v in m / m_ns], "all_converged": bool(conv.all()),
+           # Kn_ave = (Kn_in + Kn_out) / 2, Kn_in = Kn_out p_out / p_in (the abscissa of the
+           # S plot of the mass-flow study, Section 3.2); 1/S is the other plot's ordinate
+           "kn_ave": [round(k * (1.0 + 1.0 / w["p_ratio"]) / 2.0, 5) for k in kns],
+           "S": [round(float(v), 6) for v in m / m_ns],
+           "inv_S": [round(float(v), 6) for v in m_ns / m], "all_converged": bool(conv.all()),
            "steps": [int(v) for v in steps_b], "check_every": check_every, "tol": tol,
            "batched_to_steady_s": round(t_batch, 3),
            "batched_step_us": round(us_batch, 3), "batched_mlups": round(nodes / us_batch, 1),
