@@ -435,8 +435,8 @@ clb_status clb_adjoint_vjp_step(clb_adjoint* a, const double* d_P, const double*
 clb_status clb_adjoint_destroy(clb_adjoint* a);
 
 /* Measurement support (not part of the method): a plain device-to-device
- * copy of `bytes` bytes, one 16-byte load and store per thread, enqueued on
- * hip_stream.  Timed, it gives the HBM bandwidth a streaming kernel reaches
+ * copy of `bytes` bytes, one 16-byte non-temporal load and store per
+ * thread, enqueued on hip_stream.  Timed, it gives the HBM bandwidth a streaming kernel reaches
  * on the GPU at hand -- the practical ceiling beside the 8 TB/s peak against
  * which the step kernels are read -- and its FETCH_SIZE / WRITE_SIZE
  * counters calibrate the traffic counters (exactly `bytes` read and written).
