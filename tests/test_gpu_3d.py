@@ -389,3 +389,28 @@ def test_pressure_duct_full_size_symmetries():
     sw = P[[d(a, c, b) for a, b, c in E]].transpose(1, 2)
     assert float((P - sw).abs().max()) <= 1e-13 * scale
     s.close()
+
+
+def test_diagnostic_outputs_may_be_null():
+    """Each output of clb3_massflow and clb3_pressure_deviation may be NULL
+    (the others are still written, through the workspace's scratch)."""
+    import ctypes
+    from paper_1603_01955_amd import clb, clb3d
+    kw = _pressure(dict(nx=30, ny=5, nz=4, kn=0.2, init="linear_rho"))
+    s = _duct(**kw)
+    s.step(5)
+    m_full, mean_full = s.massflow()
+    dp_full, rc_full = s.pressure_deviation()
+    lib = clb3d.lib()
+    mean = ctypes.c_double()
+    assert lib.clb3_massflow(s._ctx, None, ctypes.byref(mean)) == clb.CLB_OK
+    assert mean.value == mean_full
+    assert lib.clb3_massflow(s._ctx, None, None) == clb.CLB_OK
+    dp = torch.empty(30, dtype=torch.float64, device="cuda")
+    rc = torch.empty(30, dtype=torch.float64, device="cuda")
+    assert lib.clb3_pressure_deviation(s._ctx, clb._ptr(dp), None) == clb.CLB_OK
+    assert lib.clb3_pressure_deviation(s._ctx, None, clb._ptr(rc)) == clb.CLB_OK
+    torch.cuda.synchronize()
+    assert torch.equal(dp, dp_full) and torch.equal(rc, rc_full)
+    assert lib.clb3_pressure_deviation(s._ctx, None, None) == clb.CLB_OK
+    s.close()
