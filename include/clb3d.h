@@ -100,7 +100,9 @@ typedef struct clb3_ctx clb3_ctx;
 void clb3_params_default(clb3_params* p);
 
 /* Validate *p and derive A1, r, tau_tilde, s_nu, s_q (Eqs. 18, 21 with
- * N = ny).  Host only.  CLB_EINVAL names the first invalid field. */
+ * N = ny; for a pressure-driven duct at the outlet Kn, each cross-section's
+ * own rates following from its local Kn during the step).  Host only.
+ * CLB_EINVAL names the first invalid field. */
 clb_status clb3_derive(const clb3_params* p, clb_derived* out);
 
 /* Device workspace in bytes: two population buffers (216 bytes per node,
